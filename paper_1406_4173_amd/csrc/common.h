@@ -1,0 +1,114 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/bcpp.h"
+
+namespace bcpp {
+
+constexpr uint32_t INF32 = 0xFFFFFFFFu;
+constexpr int LANES = 64;  // sources per group: one per lane of a wave64
+
+// ---------------------------------------------------------------- errors ------
+
+void set_error(const std::string& msg);
+
+struct Status {
+    int code = BC_OK;
+    bool ok() const { return code == BC_OK; }
+};
+
+#define BC_HIP(call)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            ::bcpp::set_error(std::string("HIP error in ") + #call + ": " +          \
+                              hipGetErrorString(e_));                                \
+            return e_ == hipErrorOutOfMemory ? BC_E_NOMEM : BC_E_DEVICE;             \
+        }                                                                            \
+    } while (0)
+
+#define BC_TRY(expr)                     \
+    do {                                 \
+        int rc_ = (expr);                \
+        if (rc_ != BC_OK) return rc_;    \
+    } while (0)
+
+inline int fail(int code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+// ------------------------------------------------------- device memory arena ---
+
+// A growable device buffer reused across calls on one handle. Allocation is a bump
+// pointer in 256-byte steps; reset() frees everything at once. When a request does
+// not fit, the arena is re-created larger (only between runs, when nothing in it is
+// live).
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    size_t peak = 0;
+    // capacity limit (0 = no limit) so that a budget can be enforced
+    size_t limit = 0;
+
+    int reserve(size_t bytes);  // ensure cap >= bytes (drops contents)
+    void reset() { used = 0; }
+    template <class T>
+    T* take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        if (used + bytes > cap) return nullptr;
+        T* p = reinterpret_cast<T*>(base + used);
+        used += bytes;
+        if (used > peak) peak = used;
+        return p;
+    }
+    void release();
+    ~Arena() { release(); }
+};
+
+// ------------------------------------------------------------ profiling -------
+
+struct Profiler {
+    bool on = false;
+    struct Pending {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t launches[BC_K_COUNT] = {};
+    double ms[BC_K_COUNT] = {};
+    double bytes[BC_K_COUNT] = {};
+    // device counters of algorithmic bytes, one slot per kernel kind
+    unsigned long long* d_bytes = nullptr;
+
+    hipEvent_t get_event();
+    void begin(int kind, hipStream_t s, hipEvent_t* a);
+    void end(int kind, hipStream_t s, hipEvent_t a);
+    void collect();  // resolve pending event pairs (synchronises on them)
+};
+
+Profiler& profiler();
+
+// Scoped launch timer: records events around the launches in its scope when on.
+struct KTimer {
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    KTimer(int k, hipStream_t st) : kind(k), s(st) {
+        if (profiler().on) profiler().begin(kind, s, &a);
+    }
+    ~KTimer() {
+        if (profiler().on && a) profiler().end(kind, s, a);
+    }
+};
+
+}  // namespace bcpp

@@ -1,0 +1,131 @@
+// The multi-group Brandes engine: shortest-path counting and dependency accumulation
+// for many groups of up to 64 sources at once, each group over its own node range
+// of a CSR graph.
+//
+// One group = one wave64 row per node: lane b of the row holds the state of source
+// src[b] at that node (distance, path count, dependency coefficient). The search is
+// distance-synchronous: a group's step D settles exactly the (node, source) pairs at
+// distance D, pulls their path counts from tight parents (Sec. 3, eq. parentsall, or
+// eq. multiparents with multiplicities), then relaxes their out-arcs. The backward
+// sweep replays the recorded steps in reverse and pulls dependencies from tight
+// children (eq. brandes, or eq. multibrandes). Every group advances one step per
+// engine iteration, so groups of different graphs, sizes and phases share launches.
+#pragma once
+
+#include "common.h"
+
+namespace bcpp {
+
+enum : uint32_t { NF_TARGET = 1u, NF_BLOCKED = 2u };
+
+enum : uint32_t {
+    GF_RESTRICT = 1u,  // Dijkstra_SK: blocked (frontier) parents add no paths, except the source
+    GF_BACKWARD = 2u,  // run the dependency sweep after the forward search
+    GF_CENT = 4u,      // then the interior-node Centrality pass over the tables
+    GF_UNIT = 8u,      // every arc has length 1 (plain stores replace atomics)
+};
+
+enum : int32_t { PH_DONE = 0, PH_FWD = 1, PH_BWD = 2, PH_CENT = 3 };
+
+enum : uint32_t { ERR_OVERFLOW = 1u, ERR_HIST = 2u, ERR_REC = 4u };
+
+struct EGraph {
+    const int64_t* row_ptr = nullptr;  // [nodes+1]
+    const int32_t* col = nullptr;      // [arcs]
+    const uint32_t* len = nullptr;     // [arcs] >= 1; nullptr = all 1
+    const uint64_t* mult = nullptr;    // [arcs]; nullptr = all 1
+    const uint8_t* nflag = nullptr;    // [nodes] NF_* bits; nullptr = none
+};
+
+struct GroupDesc {
+    EGraph g;
+    int32_t lo = 0, hi = 0;  // node range [lo, hi) of g this group searches
+    uint32_t flags = 0;
+    int32_t nsrc = 0;
+    uint32_t* tent = nullptr;   // [(hi-lo)*64] distance (final once <= current step)
+    uint64_t* sigma = nullptr;  // [(hi-lo)*64] path count
+    double* coef = nullptr;     // [(hi-lo)*64] (I[v in S] + delta(s|v)) / sigma(s,v)
+    uint32_t* nd = nullptr;     // [hi-lo] smallest pending distance over unsettled lanes
+    double* cacc = nullptr;     // [hi-lo] this group's share of the scores
+    int32_t* hist = nullptr;    // settled nodes in step order (backward only)
+    int64_t hist_cap = 0;
+    uint32_t* rec_d = nullptr;  // per recorded step: distance, history offset, count
+    int64_t* rec_off = nullptr;
+    int32_t* rec_cnt = nullptr;
+    int32_t rec_cap = 0;
+    // Centrality tables (GF_CENT): interior row i has entries trow[i]..trow[i+1] of
+    // (tcol = node of g in this group's range, tlen = d(f,v), tsig = sigma(f,v)).
+    const int64_t* trow = nullptr;
+    const int32_t* tcol = nullptr;
+    const uint32_t* tlen = nullptr;
+    const uint64_t* tsig = nullptr;
+    int32_t tn = 0;
+    double* cint = nullptr;  // [tn] this group's share of the interior scores
+    int32_t src[LANES];      // source node ids of g, -1 = unused lane
+};
+
+struct GroupDyn {
+    uint32_t D;
+    int32_t phase;
+    int32_t nrec;
+    int32_t rec_i;
+    int64_t hist_len;
+    int64_t rec_start;
+    uint32_t nextmin;
+    uint32_t err;
+};
+
+// Device memory needed by one group (state, history and step records).
+size_t group_bytes(int64_t range, int32_t nsrc, uint32_t flags, int64_t max_steps, int32_t tn);
+
+// Carve a group's buffers from the arena. Returns false if it does not fit.
+bool group_alloc(Arena& a, GroupDesc& G, int64_t max_steps);
+
+// An engine instance: slots for groups, the scan-chunk table and the work lists.
+struct Engine {
+    hipStream_t stream = nullptr;
+    int32_t cap = 0;           // group slots
+    GroupDesc* d_desc = nullptr;
+    GroupDyn* d_dyn = nullptr;
+    int32_t* d_chunk_g = nullptr;
+    int32_t* d_chunk_off = nullptr;
+    int64_t nchunks = 0;
+    int64_t chunk_cap = 0;
+    int2* d_wl = nullptr;      // 3 lists: forward, backward, centrality
+    int64_t wl_cap = 0;
+    uint32_t* d_ctr = nullptr; // [0..2] list counts, [3] active groups
+    uint32_t* h_ctr = nullptr; // pinned mirror
+    int blocks = 0;            // persistent grid of the work kernels
+    bool profile_bytes = false;
+
+    // Allocate the engine's own buffers in `a` for up to `slots` groups covering at
+    // most `positions` scan positions (sum over groups of max(range, tn)).
+    int setup(Arena& a, hipStream_t s, int32_t slots, int64_t positions);
+    // Install groups into slots [first, first + n) and initialise their state.
+    int install(const GroupDesc* groups, int32_t first, int32_t n);
+    // Rebuild the scan-chunk table from host descriptors of slots [0, nslots).
+    int set_chunks(const std::vector<GroupDesc>& host_desc, const std::vector<int32_t>& live);
+    // Issue `iters` engine iterations (no host synchronisation).
+    int iterate(int iters);
+    // Run until every installed group is done; then read back per-group errors.
+    int run_to_completion(int32_t nslots, std::vector<GroupDyn>* dyn_out = nullptr);
+};
+
+// Run the given groups to completion on a fresh engine (synchronous helper).
+int run_groups(Arena& a, hipStream_t s, std::vector<GroupDesc>& groups, int64_t max_steps);
+
+// Sum per-group partial scores into out[v] for v in [0, n), in group order:
+//   out[v] (+)= scale * sum_{g in [g0[v], g1[v])} part[g][idx[v]]
+// where part[g] is cacc (which[v] == 0) or cint (which[v] == 1) of group g. A null
+// g0/g1 means all groups, a null idx means idx[v] = v, idx[v] < 0 gives 0.
+int reduce_scores(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups,
+                  int32_t n, const int32_t* d_g0, const int32_t* d_g1,
+                  const int32_t* d_idx, const uint8_t* d_which, double scale,
+                  double* out_dev, bool accumulate);
+
+}  // namespace bcpp
+
+namespace bcpp {
+// Device bytes an Engine needs for `slots` groups over `positions` scan positions.
+size_t engine_bytes(int32_t slots, int64_t positions);
+}  // namespace bcpp

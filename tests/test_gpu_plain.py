@@ -1,0 +1,145 @@
+"""GPU parity of the Brandes subroutine and plain target-set Brandes against the oracle.
+
+Distances and path counts must match bit for bit; scores within a relative 1e-9
+(plus exact zeros where the oracle has zeros).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1406_4173_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-9
+
+
+def assert_scores(got, want, rel=REL):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    assert got.shape == want.shape
+    assert np.array_equal(got == 0, want == 0), "zero pattern differs"
+    err = np.abs(got - want) / np.maximum(np.abs(want), 1e-300)
+    err[want == 0] = 0
+    assert err.max(initial=0) <= rel, f"max rel err {err.max()} at {int(err.argmax())}"
+
+
+@pytest.fixture(scope="module")
+def bcpp():
+    from paper_1406_4173_amd import bcpp as b
+
+    b.lib()
+    return b
+
+
+def check_counts(b, g, src):
+    G = b.Graph(g)
+    d, sig = b.sssp_counts(G, src)
+    for i, s in enumerate(src):
+        od, osig = oracle.sssp(g, int(s))
+        assert np.array_equal(d[i], od), f"distances differ from source {s}"
+        assert np.array_equal(sig[i], osig), f"path counts differ from source {s}"
+
+
+def test_counts_small_random(bcpp):
+    for seed in range(40):
+        g = inputs.random_graph(seed, 5 + seed % 20, 0.3, wmax=[None, 4][seed % 2])
+        check_counts(bcpp, g, np.arange(g.n))
+
+
+def test_counts_grid_and_ragged_source_counts(bcpp):
+    g = inputs.grid(9, 13)
+    for ns in (1, 63, 64, 65, 117):
+        src = np.arange(ns) % g.n
+        check_counts(bcpp, g, src)
+
+
+def test_counts_planted_and_weighted(bcpp):
+    g = inputs.planted_1k()
+    check_counts(bcpp, g, inputs.random_targets(11, g.n, 130))
+    g = inputs.sbm_10k()
+    check_counts(bcpp, g, inputs.random_targets(12, g.n, 70))
+
+
+def test_counts_overflow_boundary(bcpp):
+    g = inputs.grid(34, 35)
+    check_counts(bcpp, g, [0, g.n - 1, 17])
+    g = inputs.grid(35, 35)
+    G = bcpp.Graph(g)
+    with pytest.raises(bcpp.BcError) as ei:
+        bcpp.sssp_counts(G, [0])
+    assert ei.value.code == bcpp.BC_E_OVERFLOW
+
+
+def test_plain_small_random_graphs(bcpp):
+    for seed in range(120):
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(1, 40))
+        g = inputs.random_graph(2000 + seed, n, float(rng.choice([0.05, 0.15, 0.4])),
+                                wmax=[None, 3, 9][seed % 3])
+        G = bcpp.Graph(g)
+        for ordered in (False, True):
+            assert_scores(bcpp.brandes_plain(G, g.S, ordered), oracle.bc(g, g.S, ordered))
+
+
+@pytest.mark.parametrize("n", [2, 7, 64, 65, 200])
+def test_plain_closed_forms(bcpp, n):
+    g = inputs.star(n)
+    C = bcpp.brandes_plain(bcpp.Graph(g), np.arange(n))
+    assert C[0] == (n - 1) * (n - 2) / 2 and np.all(C[1:] == 0)
+    g = inputs.path(n)
+    i = np.arange(n)
+    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), i), (i * (n - 1 - i)).astype(float))
+    if n >= 3:
+        g = inputs.cycle(n)
+        want = (n - 2) ** 2 / 8 if n % 2 == 0 else (n - 1) * (n - 3) / 8
+        assert_scores(bcpp.brandes_plain(bcpp.Graph(g), np.arange(n)), np.full(n, want))
+        g = inputs.complete(min(n, 40))
+        assert np.all(bcpp.brandes_plain(bcpp.Graph(g), np.arange(g.n)) == 0)
+
+
+def test_plain_degenerate_target_sets(bcpp):
+    g = inputs.planted_1k()
+    G = bcpp.Graph(g)
+    for S in ([], [3]):
+        assert np.all(bcpp.brandes_plain(G, np.array(S, np.int32)) == 0)
+    S = [5, 900]
+    assert_scores(bcpp.brandes_plain(G, S), oracle.bc(g, np.array(S)))
+    with pytest.raises(bcpp.BcError):
+        bcpp.brandes_plain(G, [1, 1])
+    with pytest.raises(bcpp.BcError):
+        bcpp.brandes_plain(G, [1, g.n])
+    e = inputs.empty(10)
+    assert np.all(bcpp.brandes_plain(bcpp.Graph(e), np.arange(10)) == 0)
+
+
+def test_plain_overflow(bcpp):
+    g = inputs.grid(35, 35)
+    with pytest.raises(bcpp.BcError) as ei:
+        bcpp.brandes_plain(bcpp.Graph(g), [0, g.n - 1])
+    assert ei.value.code == bcpp.BC_E_OVERFLOW
+    g = inputs.grid(34, 35)
+    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), [0, g.n - 1]),
+                  oracle.bc(g, np.array([0, g.n - 1])))
+
+
+def test_plain_planted_1k_full(bcpp):
+    g = inputs.planted_1k()
+    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), g.S), oracle.bc(g, g.S))
+
+
+def test_plain_sbm_10k_full(bcpp):
+    g = inputs.sbm_10k()
+    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), g.S), oracle.bc(g, g.S))
+
+
+def test_plain_dev_entry_point(bcpp):
+    torch = pytest.importorskip("torch")
+    g = inputs.planted_1k()
+    G = bcpp.Graph(g)
+    S = inputs.random_targets(5, g.n, 150)
+    S_dev = torch.tensor(S, dtype=torch.int32, device="cuda")
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    bcpp.brandes_plain_dev(G, S_dev, out)
+    torch.cuda.synchronize()
+    assert_scores(out.cpu().numpy(), oracle.bc(g, S))
