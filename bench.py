@@ -1,0 +1,182 @@
+"""Benchmark: exact-BC TEPS (|S| * m / s) of Brandes++ and plain Brandes on one MI355X.
+
+A step is one full Brandes++ pass over the workload: bc_partition_sk (P', frontiers,
+Dijkstra_SK, skeleton assembly) then bc_brandes_pp_dev (Brandes_SK with the fused
+Centrality pass, scores written to a device tensor). The graph is resident on the
+device before timing starts. Plain GPU Brandes on the same graph and targets is timed
+the same way and reported beside it, with the CPU oracle on a bounded sample.
+
+Prints one JSON line. Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                                             [--workload sbm_10k]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sbm_10k",
+                    choices=["planted_1k", "sbm_10k", "pareto_100k", "smallcut_100k"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain Brandes line")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="approximate CPU time budget of the oracle sample")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (a known-size "
+                         "kernel that scales profiler byte counters)")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup, sync):
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(g, budget_s):
+    """The oracle as it stands (single-threaded target-set Brandes) on the first sources
+    of S, sized to roughly `budget_s` seconds; returns TEPS over the sample."""
+    import numpy as np
+
+    import oracle
+
+    L = oracle.lib()
+    S = np.asarray(g.S, np.int32)
+    probe = S[: max(2, min(S.size, 20))]
+    t0 = time.perf_counter()
+    oracle.bc(g, probe, L=L)
+    per_src = max((time.perf_counter() - t0) / probe.size, 1e-6)
+    ns = int(max(2, min(S.size, budget_s / per_src)))
+    sample = S[:ns]
+    t0 = time.perf_counter()
+    oracle.bc(g, sample, L=L)
+    dt = time.perf_counter() - t0
+    return {
+        "value": ns * g.m / dt,
+        "unit": "TEPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {ns} of {S.size} targets of the same graph ({dt:.1f} s, single thread)",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards "
+              "by source batches across GPUs by design but only the one-GPU kernel is built",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1406_4173_amd import bcpp, inputs
+
+    g = inputs.CONFIGS[args.workload]()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    G = bcpp.Graph(g, stream=stream)
+    S_dev = torch.tensor(g.S, dtype=torch.int32, device=dev)
+    out = torch.empty(g.n, dtype=torch.float64, device=dev)
+    part = np.ascontiguousarray(g.part, np.int32)
+    S_host = np.ascontiguousarray(g.S, np.int32)
+    sync = torch.cuda.synchronize
+    state = {}
+
+    def pp_step():
+        sk = bcpp.partition_sk(G, part, g.k, S_host)
+        bcpp.brandes_pp_dev(G, sk, out)
+        state["sk"] = sk
+
+    def plain_step():
+        bcpp.brandes_plain_dev(G, S_dev, out)
+
+    if args.copy_mib:
+        a = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        sync()
+        del a, b
+
+    # timed Brandes++ steps, kernels timed with HIP events on the library's stream
+    bcpp.profile_enable(True)
+    for _ in range(args.warmup):
+        pp_step()
+    sync()
+    bcpp.profile_reset()
+    t_pp = timed(pp_step, args.steps, 0, sync)
+    prof = bcpp.profile_read()
+    bcpp.profile_enable(False)
+    sk_stats = state["sk"].stats()
+
+    units = float(len(g.S)) * g.m
+    res = {
+        "metric": "exact-BC TEPS (|S|*m/s), Brandes++ on 1 GPU",
+        "value": units / t_pp,
+        "unit": "TEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_pp * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64/f64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "n": g.n,
+            "m": g.m,
+            "targets": int(len(g.S)),
+            "parts": int(g.k),
+            "weights": "unit" if g.w is None else f"1..{int(g.w.max())}",
+            "skeleton_nodes": sk_stats["n_sk"],
+            "skeleton_arcs": sk_stats["r_arcs"] + sk_stats["clique_arcs"],
+            "table_nnz": sk_stats["table_nnz"],
+            "dijkstra_sk_sources": sk_stats["dsk_sources"],
+        },
+    }
+    # roofline of the dominant kernel (most time over the timed steps)
+    kern = max((k for k in prof if k not in ("other",)), key=lambda k: prof[k]["ms"])
+    kp = prof[kern]
+    achieved = kp["alg_bytes"] / (kp["ms"] * 1e-3) / 1e9 if kp["ms"] > 0 else 0.0
+    res["roofline"] = {
+        "kernel": kern,
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": achieved / PEAK_HBM_GBS,
+        "traffic": None,
+        "launches": kp["launches"],
+        "avg_launch_us": kp["ms"] * 1e3 / max(kp["launches"], 1),
+        "alg_bytes_per_launch": kp["alg_bytes"] / max(kp["launches"], 1),
+    }
+    res["kernels_ms_per_step"] = {k: v["ms"] / args.steps for k, v in prof.items()}
+    if not args.no_plain:
+        t_plain = timed(plain_step, args.steps, args.warmup, sync)
+        res["plain"] = {"value": units / t_plain, "unit": "TEPS", "ms_per_step": t_plain * 1e3}
+        res["pp_over_plain"] = t_plain / t_pp
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
