@@ -27,7 +27,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sbm_10k",
-                    choices=["planted_1k", "sbm_10k", "pareto_100k", "smallcut_100k"])
+                    choices=["planted_1k", "sbm_10k", "pareto_100k", "smallcut_100k", "batch_256"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain Brandes line")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -76,8 +76,51 @@ def cpu_baseline(g, budget_s):
     }
 
 
+def bench_batch(args):
+    """256 independent graphs in one device run; TEPS = sum over graphs of |S_g| m_g / s.
+    The batch entry point returns host arrays, so this rate includes the copy of all
+    scores to the host."""
+    import torch
+
+    from paper_1406_4173_amd import bcpp, inputs
+
+    gs = inputs.batch_256()
+    B = bcpp.Batch(gs)
+    sync = torch.cuda.synchronize
+    units = float(sum(len(g.S) * g.m for g in gs))
+    bcpp.profile_enable(True)
+    B.run(pp=True)
+    sync()
+    bcpp.profile_reset()
+    t_pp = timed(lambda: B.run(pp=True), args.steps, 0, sync)
+    prof = bcpp.profile_read()
+    bcpp.profile_enable(False)
+    t_plain = timed(lambda: B.run(pp=False), args.steps, args.warmup, sync)
+    kern = max((k for k in prof if k != "other"), key=lambda k: prof[k]["ms"])
+    kp = prof[kern]
+    achieved = kp["alg_bytes"] / (kp["ms"] * 1e-3) / 1e9 if kp["ms"] > 0 else 0.0
+    res = {
+        "metric": "exact-BC TEPS (|S|*m/s), Brandes++ batched, 1 GPU",
+        "value": units / t_pp, "unit": "TEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_pp * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64/f64", "data": "synthetic",
+        "config": {"workload": "batch_256", "graphs": len(gs), "n": int(sum(g.n for g in gs)),
+                   "m": int(sum(g.m for g in gs)), "targets": int(sum(len(g.S) for g in gs))},
+        "roofline": {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "launches": kp["launches"],
+                     "avg_launch_us": kp["ms"] * 1e3 / max(kp["launches"], 1)},
+        "kernels_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
+        "plain": {"value": units / t_plain, "unit": "TEPS", "ms_per_step": t_plain * 1e3},
+        "pp_over_plain": t_plain / t_pp,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "batch_256":
+        return bench_batch(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards "
               "by source batches across GPUs by design but only the one-GPU kernel is built",

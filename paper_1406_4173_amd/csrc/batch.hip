@@ -1,0 +1,272 @@
+// Batched form: many independent graphs in one device run.
+//
+// The graphs are laid side by side as one disjoint union (node ids offset per graph).
+// Plain Brandes gives each graph its own groups of 64 sources over its own node
+// range. Brandes++ builds P' per graph (targets as singleton parts inside that graph's
+// label range), so the union's skeleton is the disjoint union of the graphs'
+// skeletons and each graph's skeleton nodes and table rows are contiguous id ranges;
+// Dijkstra_SK then covers every part of every graph, and Brandes_SK + Centrality every
+// graph's groups, each in a single engine run. Scores of a disjoint union restricted
+// to one graph are that graph's own scores (no shortest path joins two graphs).
+#include <algorithm>
+#include <memory>
+
+#include "engine.h"
+#include "graph.h"
+
+struct bc_batch {
+    int32_t ng = 0;
+    std::vector<int32_t> n_off;  // [ng+1] node offset of each graph in the union
+    std::vector<int32_t> s_off;  // [ng+1] offset of each graph's targets in S_all
+    std::vector<int32_t> S_all;  // targets, union ids, graph-major
+    std::vector<int32_t> lab;    // P' labels of the union (targets singleton)
+    int32_t nlab = 0;
+    bc_graph* G = nullptr;       // the union graph
+    ~bc_batch() { delete G; }
+};
+
+namespace bcpp {
+
+static int batch_plain(bc_batch* b, double* d_out) {
+    bc_graph* G = b->G;
+    hipStream_t s = G->stream;
+    const int32_t n = G->n;
+    std::vector<GroupDesc> groups;
+    std::vector<int32_t> g0(n, 0), g1(n, 0), idx(n, -1);
+    int64_t steps = 1;
+    for (int32_t gi = 0; gi < b->ng; ++gi) {
+        const int32_t lo = b->n_off[gi], hi = b->n_off[gi + 1];
+        const int32_t ns = b->s_off[gi + 1] - b->s_off[gi];
+        const int32_t first_group = (int32_t)groups.size();
+        if (ns >= 2) {
+            steps = std::max(steps, max_steps_bound(hi - lo, LANES, (int64_t)(hi - lo) * G->maxw));
+            for (int32_t c = 0; c < ns; c += LANES) {
+                GroupDesc D;
+                D.lo = lo;
+                D.hi = hi;
+                D.flags = GF_BACKWARD | (G->unit ? GF_UNIT : 0u);
+                D.nsrc = std::min(LANES, ns - c);
+                for (int l = 0; l < LANES; ++l)
+                    D.src[l] = l < D.nsrc ? b->S_all[b->s_off[gi] + c + l] : -1;
+                groups.push_back(D);
+            }
+        }
+        for (int32_t v = lo; v < hi; ++v) {
+            g0[v] = first_group;
+            g1[v] = (int32_t)groups.size();
+            idx[v] = v - lo;
+        }
+    }
+    Arena& W = G->work;
+    size_t need = engine_bytes((int32_t)std::max<size_t>(groups.size(), 1), n) + (size_t)n * 13 +
+                  (size_t)groups.size() * 16 + (1 << 20);
+    int64_t positions = 0;
+    for (auto& D : groups) {
+        need += group_bytes(D.hi - D.lo, D.nsrc, D.flags, steps, 0);
+        positions += D.hi - D.lo;
+    }
+    need += engine_bytes((int32_t)std::max<size_t>(groups.size(), 1), positions);
+    BC_TRY(W.reserve(need));
+    uint8_t* d_flag = W.take<uint8_t>(n);
+    int32_t* d_g0 = W.take<int32_t>(n);
+    int32_t* d_g1 = W.take<int32_t>(n);
+    int32_t* d_idx = W.take<int32_t>(n);
+    if (!d_flag || !d_g0 || !d_g1 || !d_idx) return fail(BC_E_NOMEM, "batch: workspace too small");
+    std::vector<uint8_t> flag(n, 0);
+    for (int32_t v : b->S_all) flag[v] = (uint8_t)NF_TARGET;
+    BC_HIP(hipMemcpyAsync(d_flag, flag.data(), n, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(d_g0, g0.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(d_g1, g1.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(d_idx, idx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    for (auto& D : groups) {
+        D.g.row_ptr = G->d_row_ptr;
+        D.g.col = G->d_col;
+        D.g.len = G->d_len;
+        D.g.nflag = d_flag;
+    }
+    BC_TRY(run_groups(W, s, groups, steps));
+    BC_TRY(reduce_scores(s, W, groups, n, d_g0, d_g1, d_idx, nullptr, 0.5, d_out, false));
+    return BC_OK;
+}
+
+static int batch_pp(bc_batch* b, double* d_out) {
+    bc_graph* G = b->G;
+    hipStream_t s = G->stream;
+    const int32_t n = G->n;
+    bc_skeleton* skp = nullptr;
+    BC_TRY(partition_impl(G, b->lab.data(), b->nlab, b->S_all.data(), (int32_t)b->S_all.size(), &skp,
+                          true));
+    std::unique_ptr<bc_skeleton> sk(skp);
+    const auto& oi = sk->h_out_idx;
+    const auto& ow = sk->h_out_which;
+    std::vector<GroupDesc> groups;
+    std::vector<int32_t> g0(n, 0), g1(n, 0), idx(n, -1);
+    std::vector<uint8_t> which(n, 0);
+    int64_t steps = 1;
+    for (int32_t gi = 0; gi < b->ng; ++gi) {
+        const int32_t lo = b->n_off[gi], hi = b->n_off[gi + 1];
+        int32_t sk_lo = INT32_MAX, sk_hi = -1, t_lo = INT32_MAX, t_hi = -1;
+        for (int32_t v = lo; v < hi; ++v) {
+            if (oi[v] < 0) continue;
+            if (ow[v] == 0) {
+                sk_lo = std::min(sk_lo, oi[v]);
+                sk_hi = std::max(sk_hi, oi[v] + 1);
+            } else {
+                t_lo = std::min(t_lo, oi[v]);
+                t_hi = std::max(t_hi, oi[v] + 1);
+            }
+        }
+        std::vector<int32_t> src;
+        for (int32_t j = b->s_off[gi]; j < b->s_off[gi + 1]; ++j) {
+            const int32_t v = b->S_all[j];
+            if (oi[v] >= 0 && ow[v] == 0) src.push_back(oi[v]);
+        }
+        const int32_t first_group = (int32_t)groups.size();
+        if (src.size() >= 2 && sk_hi > sk_lo) {
+            const int32_t N = sk_hi - sk_lo;
+            const int32_t tn = t_hi > t_lo ? t_hi - t_lo : 0;
+            steps = std::max(steps, max_steps_bound(N, LANES, (int64_t)(hi - lo) * G->maxw));
+            for (size_t c = 0; c < src.size(); c += LANES) {
+                GroupDesc D;
+                D.g.row_ptr = sk->d_row_ptr;
+                D.g.col = sk->d_col;
+                D.g.len = sk->d_len;
+                D.g.mult = sk->d_mult;
+                D.g.nflag = sk->d_nflag;
+                D.lo = sk_lo;
+                D.hi = sk_hi;
+                D.flags = GF_BACKWARD | (tn ? GF_CENT : 0u);
+                D.trow = sk->d_trow;
+                D.tcol = sk->d_tcol;
+                D.tlen = sk->d_tlen;
+                D.tsig = sk->d_tsig;
+                D.t_lo = tn ? t_lo : 0;
+                D.tn = tn;
+                D.nsrc = (int32_t)std::min<size_t>(LANES, src.size() - c);
+                for (int l = 0; l < LANES; ++l) D.src[l] = l < D.nsrc ? src[c + l] : -1;
+                groups.push_back(D);
+            }
+        }
+        for (int32_t v = lo; v < hi; ++v) {
+            g0[v] = first_group;
+            g1[v] = (int32_t)groups.size();
+            if (oi[v] >= 0 && g1[v] > g0[v]) {
+                idx[v] = ow[v] == 0 ? oi[v] - sk_lo : oi[v] - t_lo;
+                which[v] = ow[v];
+            }
+        }
+    }
+    Arena& W = G->work;
+    size_t need = (size_t)n * 13 + (size_t)groups.size() * 16 + (1 << 20);
+    int64_t positions = 0;
+    for (auto& D : groups) {
+        need += group_bytes(D.hi - D.lo, D.nsrc, D.flags, steps, D.tn);
+        positions += std::max(D.hi - D.lo, D.tn);
+    }
+    need += engine_bytes((int32_t)std::max<size_t>(groups.size(), 1), positions);
+    BC_TRY(W.reserve(need));
+    int32_t* d_g0 = W.take<int32_t>(n);
+    int32_t* d_g1 = W.take<int32_t>(n);
+    int32_t* d_idx = W.take<int32_t>(n);
+    uint8_t* d_which = W.take<uint8_t>(n);
+    if (!d_g0 || !d_g1 || !d_idx || !d_which) return fail(BC_E_NOMEM, "batch: workspace too small");
+    BC_HIP(hipMemcpyAsync(d_g0, g0.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(d_g1, g1.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(d_idx, idx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(d_which, which.data(), n, hipMemcpyHostToDevice, s));
+    BC_TRY(run_groups(W, s, groups, steps));
+    BC_TRY(reduce_scores(s, W, groups, n, d_g0, d_g1, d_idx, d_which, 0.5, d_out, false));
+    return BC_OK;
+}
+
+}  // namespace bcpp
+
+using namespace bcpp;
+
+extern "C" {
+
+int bc_batch_create(int32_t ngraphs, const bc_csr* graphs, const int32_t* const* parts,
+                    const int32_t* ks, const int32_t* const* S, const int32_t* nS, void* hip_stream,
+                    bc_batch** out) {
+    if (!out) return fail(BC_E_INVAL, "null output handle");
+    *out = nullptr;
+    if (ngraphs < 1 || !graphs || !parts || !ks || !S || !nS) return fail(BC_E_INVAL, "bad batch arguments");
+    auto b = std::make_unique<bc_batch>();
+    b->ng = ngraphs;
+    b->n_off.assign(ngraphs + 1, 0);
+    b->s_off.assign(ngraphs + 1, 0);
+    int64_t ntot = 0, atot = 0;
+    int32_t maxw = 1;
+    bool any_w = false, all_w = true;
+    for (int32_t i = 0; i < ngraphs; ++i) {
+        int32_t mw = 1;
+        BC_TRY(validate_csr(&graphs[i], &mw));
+        maxw = std::max(maxw, mw);
+        ntot += graphs[i].n;
+        atot += graphs[i].nnz;
+        if (graphs[i].w) any_w = true; else all_w = false;
+        if (ntot >= INT32_MAX) return fail(BC_E_INVAL, "batch too large");
+        b->n_off[i + 1] = (int32_t)ntot;
+        if (ks[i] < 1 && graphs[i].n > 0) return fail(BC_E_INVAL, "k must be >= 1");
+        for (int32_t v = 0; v < graphs[i].n; ++v)
+            if (parts[i][v] < 0 || parts[i][v] >= ks[i]) return fail(BC_E_INVAL, "partition label out of range");
+        BC_TRY(validate_targets(graphs[i].n, S[i], nS[i]));
+        b->s_off[i + 1] = b->s_off[i] + nS[i];
+    }
+    (void)all_w;
+    // union CSR (weights materialised when any graph is weighted)
+    std::vector<int64_t> rp(ntot + 1, 0);
+    std::vector<int32_t> col;
+    std::vector<int32_t> w;
+    col.reserve(atot);
+    if (any_w) w.reserve(atot);
+    b->lab.assign(ntot, 0);
+    int64_t lab_off = 0;
+    for (int32_t i = 0; i < ngraphs; ++i) {
+        const bc_csr& g = graphs[i];
+        const int32_t off = b->n_off[i];
+        for (int32_t v = 0; v < g.n; ++v) {
+            for (int64_t e = g.row_ptr[v]; e < g.row_ptr[v + 1]; ++e) {
+                col.push_back(g.col[e] + off);
+                if (any_w) w.push_back(g.w ? g.w[e] : 1);
+            }
+            rp[off + v + 1] = (int64_t)col.size();
+            b->lab[off + v] = (int32_t)(lab_off + parts[i][v]);
+        }
+        for (int32_t j = 0; j < nS[i]; ++j) {
+            const int32_t v = S[i][j];
+            b->S_all.push_back(v + off);
+            b->lab[off + v] = (int32_t)(lab_off + ks[i] + j);
+        }
+        lab_off += (int64_t)ks[i] + nS[i];
+        if (lab_off >= INT32_MAX) return fail(BC_E_INVAL, "batch too large");
+    }
+    b->nlab = (int32_t)std::max<int64_t>(lab_off, 1);
+    bc_csr u{(int32_t)ntot, (int64_t)col.size(), rp.data(), col.data(), any_w ? w.data() : nullptr};
+    BC_TRY(graph_create(&u, (hipStream_t)hip_stream, &b->G));
+    *out = b.release();
+    return BC_OK;
+}
+
+int bc_batch_run(bc_batch* b, uint32_t flags, double* const* bc_out) {
+    if (!b || !bc_out) return fail(BC_E_INVAL, "null batch or outputs");
+    bc_graph* G = b->G;
+    const int32_t n = G->n;
+    if (n == 0) return BC_OK;
+    BC_TRY(G->out.reserve((size_t)n * 8 + 256));
+    double* d_out = G->out.take<double>(n);
+    BC_TRY((flags & BC_BATCH_PP) ? batch_pp(b, d_out) : batch_plain(b, d_out));
+    std::vector<double> all(n);
+    BC_HIP(hipMemcpyAsync(all.data(), d_out, (size_t)n * 8, hipMemcpyDeviceToHost, G->stream));
+    BC_HIP(hipStreamSynchronize(G->stream));
+    const double scale = (flags & BC_ORDERED) ? 2.0 : 1.0;
+    for (int32_t i = 0; i < b->ng; ++i) {
+        if (!bc_out[i]) continue;
+        for (int32_t v = b->n_off[i]; v < b->n_off[i + 1]; ++v) bc_out[i][v - b->n_off[i]] = all[v] * scale;
+    }
+    return BC_OK;
+}
+
+void bc_batch_destroy(bc_batch* b) { delete b; }
+
+}  // extern "C"

@@ -59,6 +59,7 @@ struct GroupDesc {
     const int32_t* tcol = nullptr;
     const uint32_t* tlen = nullptr;
     const uint64_t* tsig = nullptr;
+    int32_t t_lo = 0;        // first table row of this group; rows [t_lo, t_lo + tn)
     int32_t tn = 0;
     double* cint = nullptr;  // [tn] this group's share of the interior scores
     int32_t src[LANES];      // source node ids of g, -1 = unused lane

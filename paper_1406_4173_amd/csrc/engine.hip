@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(WG) k_select(const GroupDesc* __restrict__ des
         return;
     }
     if (phase == PH_CENT) {
-        emit_items(wl, wl_cap, ctr, 2, g, i < G.tn, (int32_t)i);
+        emit_items(wl, wl_cap, ctr, 2, g, i < G.tn, G.t_lo + (int32_t)i);
         return;
     }
     // PH_FWD: the nodes whose smallest pending distance is the group's step D
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(WG) k_centrality(const GroupDesc* __restrict__
         }
         if (__ballot(ovf) && lane == 0) atomicOr(&dyn[g].err, ERR_OVERFLOW);
         const double tot = wave_sum_f64(delta);
-        if (lane == 0) G.cint[i] += tot;
+        if (lane == 0) G.cint[i - G.t_lo] += tot;
         if (prof) {
             // per (source, entry): d(s,f) twice, sigma(s,f) or coef(s,f) once; per
             // entry the table row once

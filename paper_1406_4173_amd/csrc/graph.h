@@ -33,8 +33,11 @@ struct bc_skeleton {
     int64_t t_nnz = 0;       // table entries
     int64_t max_dist = 0;    // bound on skeleton distances
     bc_sk_stats stats{};
-    // skeleton targets in skeleton ids (the sources of Brandes_SK)
+    // skeleton targets in skeleton ids (the sources of Brandes_SK), in target order
     std::vector<int32_t> h_src;
+    // per original node: skeleton id (which 0), interior table row (which 1), or -1
+    std::vector<int32_t> h_out_idx;
+    std::vector<uint8_t> h_out_which;
     // device arrays (all in `store`)
     int64_t* d_row_ptr = nullptr;  // [n_sk+1]
     int32_t* d_col = nullptr;      // [m_arcs]
@@ -53,6 +56,9 @@ struct bc_skeleton {
 };
 
 namespace bcpp {
+int graph_create(const bc_csr* csr, hipStream_t stream, bc_graph** out);
+int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
+                   bc_skeleton** out, bool given_singletons);
 int validate_csr(const bc_csr* g, int32_t* maxw_out);
 int validate_targets(int32_t n, const int32_t* S, int32_t nS);
 int64_t max_steps_bound(int64_t range, int32_t lanes, int64_t max_dist);

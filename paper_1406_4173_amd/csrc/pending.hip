@@ -6,9 +6,6 @@ using namespace bcpp;
 
 extern "C" {
 static int missing(const char* what) { return fail(BC_E_INVAL, std::string(what) + ": not implemented"); }
-int bc_batch_create(int32_t, const bc_csr*, const int32_t* const*, const int32_t*, const int32_t* const*, const int32_t*, void*, bc_batch**) { return missing("bc_batch_create"); }
-int bc_batch_run(bc_batch*, uint32_t, double* const*) { return missing("bc_batch_run"); }
-void bc_batch_destroy(bc_batch*) {}
 int bc_server_create(size_t, int32_t, bc_server**) { return missing("bc_server_create"); }
 int bc_server_add_graph(bc_server*, const bc_csr*, const int32_t*, int32_t, int32_t*) { return missing("bc_server_add_graph"); }
 int bc_query_submit(bc_server*, int32_t, const int32_t*, int32_t, uint32_t, uint64_t*) { return missing("bc_query_submit"); }

@@ -122,8 +122,10 @@ __global__ void k_table(const GroupDesc* __restrict__ desc, const DskInfo* __res
 
 // ------------------------------------------------------------ partition_sk -----
 
+// given_singletons: the labels in `part` already hold every target as a singleton
+// part (the batched path builds P' per graph); otherwise target S[i] gets label k + i.
 int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
-                   bc_skeleton** out) {
+                   bc_skeleton** out, bool given_singletons) {
     const int32_t n = g->n;
     if (n > 0 && !part) return fail(BC_E_INVAL, "null partition");
     if (n > 0 && k < 1) return fail(BC_E_INVAL, "k must be >= 1");
@@ -139,12 +141,12 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     const int32_t* wt = g->h_w.empty() ? nullptr : g->h_w.data();
 
     // ---- P' (Step 1, "Target nodes in the skeleton") and frontiers (Sec. 4)
-    const int64_t nlab = (int64_t)k + nS;
+    const int64_t nlab = (int64_t)k + (given_singletons ? 0 : nS);
     std::vector<int32_t> lab(n);
     for (int32_t v = 0; v < n; ++v) lab[v] = part[v];
     std::vector<uint8_t> is_t(n, 0);
     for (int32_t i = 0; i < nS; ++i) {
-        lab[S[i]] = k + i;
+        if (!given_singletons) lab[S[i]] = k + i;
         is_t[S[i]] = 1;
     }
     std::vector<uint8_t> fr(n, 0);
@@ -404,6 +406,8 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     // Brandes_SK sources: targets that have a neighbour (isolated targets reach nobody)
     for (int32_t i = 0; i < nS; ++i)
         if (fr[S[i]]) sk->h_src.push_back(skid(S[i]));
+    sk->h_out_idx = std::move(out_idx);
+    sk->h_out_which = std::move(out_which);
     sk->n_sk = nsk;
     sk->n_int = nint;
     sk->m_arcs = M;
@@ -542,7 +546,7 @@ int bc_partition_sk(const bc_graph* g, const int32_t* part, int32_t k, const int
                     bc_skeleton** out) {
     if (!g || !out) return fail(BC_E_INVAL, "null graph or output handle");
     *out = nullptr;
-    return partition_impl(g, part, k, S, nS, out);
+    return partition_impl(g, part, k, S, nS, out, false);
 }
 
 void bc_skeleton_destroy(bc_skeleton* sk) { delete sk; }

@@ -1,0 +1,68 @@
+"""GPU parity of the batched form: many graphs in one device run.
+
+Each graph's scores must match the oracle within 1e-9, and must equal (bit for bit) the
+scores of the same graph run alone: the graph gets the same groups of sources in the
+same order either way.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1406_4173_amd import inputs
+
+from test_gpu_plain import assert_scores
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bcpp():
+    from paper_1406_4173_amd import bcpp as b
+
+    b.lib()
+    return b
+
+
+def mixed_graphs():
+    out = []
+    for seed in range(10):
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(2, 70))
+        out.append(inputs.random_graph(7000 + seed, n, float(rng.choice([0.05, 0.1, 0.2])),
+                                       wmax=[None, 4][seed % 2], k=int(rng.integers(1, 6))))
+    out.append(inputs.empty(5))
+    out[-1].part = np.zeros(5, np.int32)
+    out[-1].k = 1
+    out[-1].S = np.array([1, 3], np.int32)
+    return out
+
+
+@pytest.mark.parametrize("pp", [False, True])
+def test_batch_mixed_graphs(bcpp, pp):
+    gs = mixed_graphs()
+    B = bcpp.Batch(gs)
+    res = B.run(pp=pp)
+    for g, got in zip(gs, res):
+        assert_scores(got, oracle.bc(g, g.S))
+
+
+@pytest.mark.parametrize("pp", [False, True])
+def test_batch_item_equals_alone(bcpp, pp):
+    gs = inputs.batch_256(12)
+    res = bcpp.Batch(gs).run(pp=pp)
+    for g, got in zip(gs, res):
+        G = bcpp.Graph(g)
+        if pp:
+            alone = bcpp.brandes_pp(G, bcpp.partition_sk(G, g.part, g.k, g.S))
+        else:
+            alone = bcpp.brandes_plain(G, g.S)
+        assert np.array_equal(got, alone)
+
+
+def test_batch_256_full(bcpp):
+    gs = inputs.batch_256()
+    B = bcpp.Batch(gs)
+    for pp in (True, False):
+        res = B.run(pp=pp)
+        for g, got in zip(gs, res):
+            assert_scores(got, oracle.bc(g, g.S))
