@@ -44,6 +44,9 @@ static int batch_plain(bc_batch* b, double* d_out) {
                 GroupDesc D;
                 D.lo = lo;
                 D.hi = hi;
+                D.arc_lo = G->h_row_ptr[lo];
+                D.arcs = G->h_row_ptr[hi] - G->h_row_ptr[lo];
+                D.ring_len = G->maxw + 1;
                 D.flags = GF_BACKWARD | (G->unit ? GF_UNIT : 0u);
                 D.nsrc = std::min(LANES, ns - c);
                 for (int l = 0; l < LANES; ++l)
@@ -62,7 +65,7 @@ static int batch_plain(bc_batch* b, double* d_out) {
                   (size_t)groups.size() * 16 + (1 << 20);
     int64_t positions = 0;
     for (auto& D : groups) {
-        need += group_bytes(D.hi - D.lo, D.nsrc, D.flags, steps, 0);
+        need += group_bytes(D, steps);
         positions += D.hi - D.lo;
     }
     need += engine_bytes((int32_t)std::max<size_t>(groups.size(), 1), positions);
@@ -83,6 +86,7 @@ static int batch_plain(bc_batch* b, double* d_out) {
         D.g.col = G->d_col;
         D.g.len = G->d_len;
         D.g.nflag = d_flag;
+        D.g.twin = G->d_twin;
     }
     BC_TRY(run_groups(W, s, groups, steps));
     BC_TRY(reduce_scores(s, W, groups, n, d_g0, d_g1, d_idx, nullptr, 0.5, d_out, false));
@@ -133,8 +137,12 @@ static int batch_pp(bc_batch* b, double* d_out) {
                 D.g.len = sk->d_len;
                 D.g.mult = sk->d_mult;
                 D.g.nflag = sk->d_nflag;
+                D.g.twin = sk->d_twin;
                 D.lo = sk_lo;
                 D.hi = sk_hi;
+                D.arc_lo = sk->h_row_ptr[sk_lo];
+                D.arcs = sk->h_row_ptr[sk_hi] - sk->h_row_ptr[sk_lo];
+                D.ring_len = sk->max_len + 1;
                 D.flags = GF_BACKWARD | (tn ? GF_CENT : 0u);
                 D.trow = sk->d_trow;
                 D.tcol = sk->d_tcol;
@@ -160,7 +168,7 @@ static int batch_pp(bc_batch* b, double* d_out) {
     size_t need = (size_t)n * 13 + (size_t)groups.size() * 16 + (1 << 20);
     int64_t positions = 0;
     for (auto& D : groups) {
-        need += group_bytes(D.hi - D.lo, D.nsrc, D.flags, steps, D.tn);
+        need += group_bytes(D, steps);
         positions += std::max(D.hi - D.lo, D.tn);
     }
     need += engine_bytes((int32_t)std::max<size_t>(groups.size(), 1), positions);

@@ -194,16 +194,27 @@ int graph_create(const bc_csr* csr, hipStream_t stream, bc_graph** out) {
         delete g;
         return rc;
     };
-    size_t bytes = (size_t)(g->n + 1) * 8 + (size_t)g->nnz * 4 * (g->unit ? 1 : 2) + 4096;
+    // reverse-arc index of every arc (rows are sorted, so a binary search finds it)
+    std::vector<int64_t> twin(g->nnz);
+    for (int32_t u = 0; u < g->n; ++u)
+        for (int64_t e = csr->row_ptr[u]; e < csr->row_ptr[u + 1]; ++e) {
+            const int32_t v = csr->col[e];
+            const int32_t* b0 = csr->col + csr->row_ptr[v];
+            const int32_t* b1 = csr->col + csr->row_ptr[v + 1];
+            twin[e] = std::lower_bound(b0, b1, u) - csr->col;
+        }
+    size_t bytes = (size_t)(g->n + 1) * 8 + (size_t)g->nnz * (4 * (g->unit ? 1 : 2) + 8) + 4096;
     int rc = g->store.reserve(bytes);
     if (rc) return cleanup(rc);
     g->d_row_ptr = g->store.take<int64_t>(g->n + 1);
     g->d_col = g->store.take<int32_t>(std::max<int64_t>(g->nnz, 1));
     if (!g->unit) g->d_len = g->store.take<uint32_t>(std::max<int64_t>(g->nnz, 1));
+    g->d_twin = g->store.take<int64_t>(std::max<int64_t>(g->nnz, 1));
     if (hipMemcpyAsync(g->d_row_ptr, csr->row_ptr, (size_t)(g->n + 1) * 8, hipMemcpyHostToDevice, stream) ||
         (g->nnz && hipMemcpyAsync(g->d_col, csr->col, (size_t)g->nnz * 4, hipMemcpyHostToDevice, stream)) ||
         (!g->unit && g->nnz &&
          hipMemcpyAsync(g->d_len, csr->w, (size_t)g->nnz * 4, hipMemcpyHostToDevice, stream)) ||
+        (g->nnz && hipMemcpyAsync(g->d_twin, twin.data(), (size_t)g->nnz * 8, hipMemcpyHostToDevice, stream)) ||
         hipStreamSynchronize(stream)) {
         return cleanup(fail(BC_E_DEVICE, "graph upload failed"));
     }
@@ -229,7 +240,14 @@ int plain_run(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, u
     const int64_t max_dist = (int64_t)(n - 1) * g->maxw;
     const int64_t steps = max_steps_bound(n, LANES, max_dist);
     const int32_t ngroups = (nS + LANES - 1) / LANES;
-    const size_t per_group = group_bytes(n, LANES, GF_BACKWARD, steps, 0);
+    GroupDesc shape;
+    shape.lo = 0;
+    shape.hi = n;
+    shape.arcs = g->nnz;
+    shape.nsrc = LANES;
+    shape.flags = GF_BACKWARD;
+    shape.ring_len = g->maxw + 1;
+    const size_t per_group = group_bytes(shape, steps);
     int32_t wave_groups = (int32_t)std::max<size_t>(1, state_budget() / std::max<size_t>(per_group, 1));
     if (const char* e = getenv("BCPP_MAX_GROUPS")) wave_groups = std::max(1, atoi(e));
     wave_groups = std::min(wave_groups, ngroups);
@@ -257,8 +275,12 @@ int plain_run(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, u
             G.g.col = g->d_col;
             G.g.len = g->d_len;
             G.g.nflag = d_flag;
+            G.g.twin = g->d_twin;
             G.lo = 0;
             G.hi = n;
+            G.arc_lo = 0;
+            G.arcs = g->nnz;
+            G.ring_len = g->maxw + 1;
             G.flags = GF_BACKWARD | (g->unit ? GF_UNIT : 0u);
             const int32_t first = (g0 + j) * LANES;
             G.nsrc = std::min(LANES, nS - first);
@@ -284,10 +306,14 @@ int sssp_run(const bc_graph* gc, const int32_t* src, int32_t nsrc, int64_t* d, u
     std::vector<uint32_t> ht((size_t)n * LANES);
     std::vector<uint64_t> hs((size_t)n * LANES);
     for (int32_t g0 = 0; g0 < ngroups; ++g0) {
-        const size_t need = group_bytes(n, LANES, 0, steps, 0) + engine_bytes(1, n) + 65536;
-        BC_TRY(g->work.reserve(need));
         std::vector<GroupDesc> groups(1);
         GroupDesc& G = groups[0];
+        G.hi = n;
+        G.arcs = g->nnz;
+        G.nsrc = LANES;
+        G.ring_len = g->maxw + 1;
+        const size_t need = group_bytes(G, steps) + engine_bytes(1, n) + 65536;
+        BC_TRY(g->work.reserve(need));
         G.g.row_ptr = g->d_row_ptr;
         G.g.col = g->d_col;
         G.g.len = g->d_len;
@@ -298,7 +324,7 @@ int sssp_run(const bc_graph* gc, const int32_t* src, int32_t nsrc, int64_t* d, u
         G.nsrc = std::min(LANES, nsrc - first);
         for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? src[first + b] : -1;
         BC_TRY(run_groups(g->work, s, groups, steps));
-        BC_HIP(hipMemcpyAsync(ht.data(), G.tent, ht.size() * 4, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(ht.data(), G.dist, ht.size() * 4, hipMemcpyDeviceToHost, s));
         BC_HIP(hipMemcpyAsync(hs.data(), G.sigma, hs.size() * 8, hipMemcpyDeviceToHost, s));
         BC_HIP(hipStreamSynchronize(s));
         for (int b = 0; b < G.nsrc; ++b) {

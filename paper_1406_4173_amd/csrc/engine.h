@@ -27,7 +27,7 @@ enum : uint32_t {
 
 enum : int32_t { PH_DONE = 0, PH_FWD = 1, PH_BWD = 2, PH_CENT = 3 };
 
-enum : uint32_t { ERR_OVERFLOW = 1u, ERR_HIST = 2u, ERR_REC = 4u };
+enum : uint32_t { ERR_OVERFLOW = 1u, ERR_HIST = 2u, ERR_REC = 4u, ERR_TWIN = 8u };
 
 struct EGraph {
     const int64_t* row_ptr = nullptr;  // [nodes+1]
@@ -35,6 +35,7 @@ struct EGraph {
     const uint32_t* len = nullptr;     // [arcs] >= 1; nullptr = all 1
     const uint64_t* mult = nullptr;    // [arcs]; nullptr = all 1
     const uint8_t* nflag = nullptr;    // [nodes] NF_* bits; nullptr = none
+    const int64_t* twin = nullptr;     // [arcs] index of the reverse arc (backward groups)
 };
 
 struct GroupDesc {
@@ -42,12 +43,22 @@ struct GroupDesc {
     int32_t lo = 0, hi = 0;  // node range [lo, hi) of g this group searches
     uint32_t flags = 0;
     int32_t nsrc = 0;
-    uint32_t* tent = nullptr;   // [(hi-lo)*64] distance (final once <= current step)
+    int64_t arc_lo = 0;         // row_ptr[lo]: first arc of the range
+    int64_t arcs = 0;           // row_ptr[hi] - row_ptr[lo]
+    uint32_t* dist = nullptr;   // [(hi-lo)*64] settled distance, INF while unsettled
     uint64_t* sigma = nullptr;  // [(hi-lo)*64] path count
     double* coef = nullptr;     // [(hi-lo)*64] (I[v in S] + delta(s|v)) / sigma(s,v)
+    double* delta = nullptr;    // [(hi-lo)*64] delta(s|v)
     uint32_t* nd = nullptr;     // [hi-lo] smallest pending distance over unsettled lanes
+    uint64_t* done = nullptr;   // [hi-lo] lanes settled at the node
+    // offers: ring[node][D mod ring_len] = lanes offered distance D by a settled
+    // neighbour (ring_len = longest arc + 1, so pending offers never share a slot)
+    uint64_t* ring = nullptr;
+    int32_t ring_len = 2;
     double* cacc = nullptr;     // [hi-lo] this group's share of the scores
+    uint64_t* tmask = nullptr;  // [arcs] per arc u->x: lanes in which u is a tight parent of x
     int32_t* hist = nullptr;    // settled nodes in step order (backward only)
+    uint64_t* hmask = nullptr;  // and the lanes each settled
     int64_t hist_cap = 0;
     uint32_t* rec_d = nullptr;  // per recorded step: distance, history offset, count
     int64_t* rec_off = nullptr;
@@ -65,6 +76,14 @@ struct GroupDesc {
     int32_t src[LANES];      // source node ids of g, -1 = unused lane
 };
 
+// A unit of work in a list: a node of a group and the lanes it handles this step
+// (for centrality items, v is the table row).
+struct NodeItem {
+    int32_t g;
+    int32_t v;
+    unsigned long long mask;
+};
+
 struct GroupDyn {
     uint32_t D;
     int32_t phase;
@@ -76,8 +95,9 @@ struct GroupDyn {
     uint32_t err;
 };
 
-// Device memory needed by one group (state, history and step records).
-size_t group_bytes(int64_t range, int32_t nsrc, uint32_t flags, int64_t max_steps, int32_t tn);
+// Device memory needed by a group shaped like G (range, arcs, nsrc, flags, tn,
+// ring_len), with room for max_steps recorded steps.
+size_t group_bytes(const GroupDesc& G, int64_t max_steps);
 
 // Carve a group's buffers from the arena. Returns false if it does not fit.
 bool group_alloc(Arena& a, GroupDesc& G, int64_t max_steps);
@@ -92,7 +112,7 @@ struct Engine {
     int32_t* d_chunk_off = nullptr;
     int64_t nchunks = 0;
     int64_t chunk_cap = 0;
-    int2* d_wl = nullptr;      // 3 lists: forward, backward, centrality
+    NodeItem* d_wl = nullptr;  // 3 lists: forward, backward, centrality
     int64_t wl_cap = 0;
     uint32_t* d_ctr = nullptr; // [0..2] list counts, [3] active groups
     uint32_t* h_ctr = nullptr; // pinned mirror
@@ -108,6 +128,8 @@ struct Engine {
     int set_chunks(const std::vector<GroupDesc>& host_desc, const std::vector<int32_t>& live);
     // Issue `iters` engine iterations (no host synchronisation).
     int iterate(int iters);
+    // Sum each backward group's per-lane dependencies into its node scores.
+    int finish_scores();
     // Run until every installed group is done; then read back per-group errors.
     int run_to_completion(int32_t nslots, std::vector<GroupDyn>* dyn_out = nullptr);
 };

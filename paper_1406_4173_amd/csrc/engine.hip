@@ -1,41 +1,42 @@
 // Kernels and host driver of the multi-group Brandes engine (see engine.h).
 //
-// Layout. A group's state is row-major [node - lo][64]: the 64 lanes of a wave read
-// one node's row for all 64 sources in one coalesced access, and every CSR arc the
-// wave walks serves all 64 sources at once. Distances are uint32 (INF = all ones),
-// path counts uint64 with overflow checks, dependency coefficients double.
+// Layout. A group's per-source state is row-major [node - lo][64]: lane b of a node's
+// row belongs to source src[b]. Distances are uint32 (INF = all ones, not settled),
+// path counts uint64 with overflow checks, dependencies double.
+//
+// Distance-synchronous search. A group at step D settles exactly the (node, source)
+// pairs at distance D. Settled nodes offer D + len to their neighbours: the offered
+// lanes are or-ed into the neighbour's ring slot (D + len) mod ring_len and its pending
+// distance nd is lowered. Since every arc is at least 1 long, every lane offered D
+// and still open when step D comes has final distance D.
 //
 // One engine iteration = select -> settle -> push -> backward -> centrality -> sched:
-//   select  (grid over scan chunks) builds this iteration's work lists: forward groups
-//           take the nodes whose pending distance nd equals the group's step D,
-//           backward groups replay one recorded step, centrality groups list their
-//           table rows;
-//   settle  (persistent, wave per item) fixes sigma(s,v) of the lanes settled at D by
-//           summing sigma(s,u) * mult(u,v) over tight parents u (eq. parentsall /
-//           eq. multiparents; with GF_RESTRICT only non-frontier parents or the source
-//           count, eq. frontierparents) and recomputes nd(v);
-//   push    (persistent) relaxes the out-arcs of the settled lanes: tent(s,x) =
-//           min(tent, D + len), nd(x) likewise;
-//   backward(persistent) for the lanes at distance D:
-//           delta = sigma(s,v) * sum over tight children x of mult * coef(s,x),
-//           coef(s,v) = (I[v in S] + delta) / sigma(s,v) (eq. brandes / multibrandes),
-//           and adds the lanes' delta (sources excluded) to the group's scores;
-//   centrality (persistent) evaluates eq. localcentrality for interior nodes from the
-//           skeleton state of the group's sources;
-//   sched   (thread per group) records the step and moves the group to its next step
-//           or phase.
+//   select  (thread per node) forward groups: the nodes with nd = D take their ring
+//           slot D as the lanes to settle, record them, and move nd to the next
+//           offered distance; backward groups replay one recorded step; centrality
+//           groups list their table rows. Output: node items (group, node, lane mask).
+//   settle  (one lane per settling (node, source) pair; a wave expands up to 16 node
+//           items into 64 pairs) pulls sigma from the tight parents (eq. parentsall /
+//           eq. multiparents; restricted to non-frontier parents for Dijkstra_SK, eq.
+//           frontierparents) and marks each tight parent arc for the backward sweep.
+//   push    (wave per node item, lanes over its arcs) makes the offers.
+//   backward(one lane per pair) delta(s|v) = sigma(s,v) * sum over tight children x of
+//           mult(v,x) * coef(s,x), coef(s,v) = (I[v in S] + delta(s|v)) / sigma(s,v)
+//           (eq. brandes / eq. multibrandes).
+//   centrality (wave per interior row, lanes = sources) eq. localcentrality.
+//   sched   (thread per group) records the step and moves the group on.
+// After the last iteration the per-lane dependencies are summed per node (sources'
+// own lanes are never written, so they add nothing).
 #include "engine.h"
 
 #include <algorithm>
-#include <chrono>
-#include <thread>
 
 namespace bcpp {
 
-constexpr int WG = 256;           // threads per workgroup
+constexpr int WG = 256;  // threads per workgroup
 constexpr int WAVES_PER_WG = WG / 64;
-
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
+constexpr int ITEMS_PER_WAVE = 16;  // node items a wave expands into lanes at once
+constexpr int UNR = 4;              // arcs whose loads a lane issues together
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
 #pragma unroll
@@ -51,10 +52,7 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long t = (unsigned long long)__shfl_xor((long long)v, o, 64);
-        v += t;
-    }
+    for (int o = 32; o > 0; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o, 64);
     return v;
 }
 
@@ -62,10 +60,17 @@ __device__ __forceinline__ int popc_below(unsigned long long mask, int lane) {
     return __popcll(mask & ((1ull << lane) - 1ull));
 }
 
+// index of the k-th (0-based) set bit of m; m has more than k set bits
+__device__ __forceinline__ int nth_bit(unsigned long long m, int k) {
+    for (int t = 0; t < k; ++t) m &= m - 1ull;
+    return __ffsll((long long)m) - 1;
+}
+
 // ------------------------------------------------------------------ init -------
 
-// Fill the state of the groups listed in `slots` (chunked like select, 4 positions x
-// 64 lanes per pass of a workgroup). Sources start at distance 0 with one path.
+// Fill the state of the groups listed in the chunk table (4 positions x 64 lanes per
+// pass of a workgroup). A source node starts with its lane offered distance 0 and one
+// path, so the group's first step settles exactly the sources.
 __global__ void __launch_bounds__(WG) k_init(const GroupDesc* __restrict__ desc,
                                              const int32_t* __restrict__ chunk_g,
                                              const int32_t* __restrict__ chunk_off,
@@ -80,44 +85,53 @@ __global__ void __launch_bounds__(WG) k_init(const GroupDesc* __restrict__ desc,
     const int32_t mysrc = G.src[lane];
     const int64_t base = chunk_off[c];
     for (int p = wv; p < WG; p += WAVES_PER_WG) {
-        int64_t i = base + p;
+        const int64_t i = base + p;
         if (i < range) {
             const int32_t v = G.lo + (int32_t)i;
             const bool is_src = (mysrc == v);
-            G.tent[i * 64 + lane] = is_src ? 0u : INF32;
+            G.dist[i * 64 + lane] = is_src ? 0u : INF32;
             G.sigma[i * 64 + lane] = is_src ? 1ull : 0ull;
             if (G.coef) G.coef[i * 64 + lane] = 0.0;
-            unsigned long long any = __ballot(is_src);
+            if (G.delta) G.delta[i * 64 + lane] = 0.0;
+            const unsigned long long any = __ballot(is_src);
+            for (int r = lane; r < G.ring_len; r += 64) G.ring[i * G.ring_len + r] = r == 0 ? any : 0ull;
             if (lane == 0) {
                 G.nd[i] = any ? 0u : INF32;
+                G.done[i] = 0ull;
                 if (G.cacc) G.cacc[i] = 0.0;
             }
         }
         if ((G.flags & GF_CENT) && i < G.tn && lane == 0) G.cint[i] = 0.0;
     }
+    // tight-parent masks: the chunk's share of the group's arcs
+    if (G.tmask && base < range) {
+        const int64_t chunks = (range + WG - 1) / WG;
+        const int64_t k = base / WG;
+        const int64_t a0 = G.arcs * k / chunks, a1 = G.arcs * (k + 1) / chunks;
+        for (int64_t e = a0 + threadIdx.x; e < a1; e += WG) G.tmask[e] = 0ull;
+    }
 }
 
 // ---------------------------------------------------------------- select -------
 
-// Append (g, y) for the lanes with sel set to work list `list` (wave-level compaction).
-__device__ __forceinline__ void emit_items(int2* __restrict__ wl, int64_t wl_cap,
-                                           uint32_t* __restrict__ ctr, int list, int g, bool sel,
-                                           int32_t y) {
+// Append node items for the lanes with sel set to list `list` (wave-level compaction).
+__device__ __forceinline__ void emit_items(NodeItem* __restrict__ wl, int64_t wl_cap,
+                                           uint32_t* __restrict__ ctr, int list, bool sel,
+                                           NodeItem item) {
     const int lane = threadIdx.x & 63;
     const unsigned long long mask = __ballot(sel);
     if (mask == 0) return;
-    const int cnt = __popcll(mask);
     uint32_t wbase = 0;
-    if (lane == 0) wbase = atomicAdd(&ctr[list], (uint32_t)cnt);
+    if (lane == 0) wbase = atomicAdd(&ctr[list], (uint32_t)__popcll(mask));
     wbase = (uint32_t)__shfl((int)wbase, 0, 64);
-    if (sel) wl[(int64_t)list * wl_cap + wbase + popc_below(mask, lane)] = make_int2(g, y);
+    if (sel) wl[(int64_t)list * wl_cap + (int64_t)wbase + popc_below(mask, lane)] = item;
 }
 
 __global__ void __launch_bounds__(WG) k_select(const GroupDesc* __restrict__ desc,
                                                GroupDyn* __restrict__ dyn,
                                                const int32_t* __restrict__ chunk_g,
                                                const int32_t* __restrict__ chunk_off,
-                                               int64_t nchunks, int2* __restrict__ wl,
+                                               int64_t nchunks, NodeItem* __restrict__ wl,
                                                int64_t wl_cap, uint32_t* __restrict__ ctr) {
     const int64_t c = blockIdx.x;
     if (c >= nchunks) return;
@@ -132,23 +146,49 @@ __global__ void __launch_bounds__(WG) k_select(const GroupDesc* __restrict__ des
         const int64_t off = G.rec_off[r];
         const int32_t cnt = G.rec_cnt[r];
         const bool sel = i < cnt;
-        const int32_t y = sel ? G.hist[off + i] : 0;
-        emit_items(wl, wl_cap, ctr, 1, g, sel, y);
+        NodeItem it;
+        it.g = g;
+        it.v = sel ? G.hist[off + i] : 0;
+        it.mask = sel ? G.hmask[off + i] : 0ull;
+        emit_items(wl, wl_cap, ctr, 1, sel, it);
         return;
     }
     if (phase == PH_CENT) {
-        emit_items(wl, wl_cap, ctr, 2, g, i < G.tn, G.t_lo + (int32_t)i);
+        NodeItem it;
+        it.g = g;
+        it.v = G.t_lo + (int32_t)i;
+        it.mask = 0ull;
+        emit_items(wl, wl_cap, ctr, 2, i < G.tn, it);
         return;
     }
-    // PH_FWD: the nodes whose smallest pending distance is the group's step D
+    // PH_FWD
     const int64_t range = (int64_t)G.hi - G.lo;
     const uint32_t D = dyn[g].D;
     const uint32_t pend = (i < range) ? G.nd[i] : INF32;
     const bool sel = (pend == D);
-    const uint32_t other = wave_min_u32(sel ? INF32 : pend);
+    unsigned long long cand = 0ull;
+    uint32_t next = INF32;
+    if (sel) {
+        const int R = G.ring_len;
+        uint64_t* ring = G.ring + i * R;
+        const int slot = (int)(D % (uint32_t)R);
+        const unsigned long long done0 = G.done[i];
+        cand = ring[slot] & ~done0;
+        ring[slot] = 0ull;
+        const unsigned long long done1 = done0 | cand;
+        G.done[i] = done1;
+        for (int j = 1; j < R; ++j) {
+            if (ring[(slot + j) % R] & ~done1) {
+                next = D + (uint32_t)j;
+                break;
+            }
+        }
+        G.nd[i] = next;
+    }
+    const uint32_t other = wave_min_u32(sel ? next : pend);
     if (lane == 0 && other != INF32) atomicMin(&dyn[g].nextmin, other);
-    const int32_t y = G.lo + (int32_t)i;
-    const unsigned long long mask = __ballot(sel);
+    const bool emit = sel && cand != 0ull;
+    const unsigned long long mask = __ballot(emit);
     if (mask == 0) return;
     const int cnt = __popcll(mask);
     const int rank = popc_below(mask, lane);
@@ -161,13 +201,76 @@ __global__ void __launch_bounds__(WG) k_select(const GroupDesc* __restrict__ des
     }
     wbase = (uint32_t)__shfl((int)wbase, 0, 64);
     hbase = (unsigned long long)__shfl((long long)hbase, 0, 64);
-    if (sel) {
-        wl[wbase + rank] = make_int2(g, y);
+    if (emit) {
+        NodeItem it;
+        it.g = g;
+        it.v = G.lo + (int32_t)i;
+        it.mask = cand;
+        wl[(int64_t)wbase + rank] = it;
         if (G.flags & GF_BACKWARD) {
-            if ((int64_t)(hbase + rank) < G.hist_cap)
-                G.hist[hbase + rank] = y;
-            else
+            if ((int64_t)(hbase + rank) < G.hist_cap) {
+                G.hist[hbase + rank] = it.v;
+                G.hmask[hbase + rank] = cand;
+            } else {
                 atomicOr(&dyn[g].err, ERR_HIST);
+            }
+        }
+    }
+}
+
+// -------------------------------------------------------- pair expansion -------
+
+// A wave takes ITEMS_PER_WAVE consecutive node items and spreads their (node, lane)
+// pairs over its 64 lanes, 64 pairs per round; body(pair) runs once per lane and
+// round (pair.valid false on lanes past the last pair). All lanes stay converged.
+struct PairCursor {
+    int32_t g, v, b;
+    bool valid;
+};
+
+template <class Body>
+__device__ __forceinline__ void for_pairs(const NodeItem* __restrict__ list, uint32_t count,
+                                          Body&& body) {
+    const int lane = threadIdx.x & 63;
+    const int64_t W = (int64_t)gridDim.x * WAVES_PER_WG;
+    for (int64_t chunk = (int64_t)blockIdx.x * WAVES_PER_WG + (threadIdx.x >> 6);
+         chunk * ITEMS_PER_WAVE < (int64_t)count; chunk += W) {
+        const int64_t idx = chunk * ITEMS_PER_WAVE + lane;
+        const bool have = lane < ITEMS_PER_WAVE && idx < (int64_t)count;
+        int32_t ig = 0, iv = 0;
+        unsigned long long im = 0ull;
+        if (have) {
+            const NodeItem it = list[idx];
+            ig = it.g;
+            iv = it.v;
+            im = it.mask;
+        }
+        const int pc = __popcll(im);
+        int incl = pc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        const int total = __shfl(incl, 63, 64);
+        const int excl = incl - pc;
+        const int lo32 = (int)(uint32_t)im, hi32 = (int)(uint32_t)(im >> 32);
+        for (int r = 0; r < total; r += 64) {
+            const int p = r + lane;
+            int j = 0;
+#pragma unroll
+            for (int k = 0; k < ITEMS_PER_WAVE; ++k) j += (__shfl(incl, k, 64) <= p) ? 1 : 0;
+            const int jj = min(j, ITEMS_PER_WAVE - 1);
+            PairCursor P;
+            P.g = __shfl(ig, jj, 64);
+            P.v = __shfl(iv, jj, 64);
+            const unsigned long long m =
+                ((unsigned long long)(uint32_t)__shfl(hi32, jj, 64) << 32) |
+                (unsigned long long)(uint32_t)__shfl(lo32, jj, 64);
+            const int ex = __shfl(excl, jj, 64);
+            P.valid = p < total;
+            P.b = P.valid ? nth_bit(m, p - ex) : 0;
+            body(P);
         }
     }
 }
@@ -176,190 +279,215 @@ __global__ void __launch_bounds__(WG) k_select(const GroupDesc* __restrict__ des
 
 __global__ void __launch_bounds__(WG) k_settle(const GroupDesc* __restrict__ desc,
                                                GroupDyn* __restrict__ dyn,
-                                               const int2* __restrict__ wl,
+                                               const NodeItem* __restrict__ wl,
                                                const uint32_t* __restrict__ ctr,
                                                unsigned long long* __restrict__ prof) {
-    const int lane = threadIdx.x & 63;
-    const int64_t W = (int64_t)gridDim.x * WAVES_PER_WG;
     const uint32_t count = ctr[0];
     unsigned long long bytes = 0;
-    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_WG + (threadIdx.x >> 6); it < count;
-         it += W) {
-        const int2 item = wl[it];
-        const int g = item.x;
-        const int32_t v = item.y;
-        const GroupDesc& G = desc[g];
-        const uint32_t D = dyn[g].D;
+    for_pairs(wl, count, [&](const PairCursor& P) {
+        if (!P.valid) return;
+        const GroupDesc& G = desc[P.g];
+        const int32_t b = P.b;
+        const int32_t v = P.v;
+        if (G.src[b] == v) return;  // a source's own lane: distance 0, one path (preset)
+        const uint32_t D = dyn[P.g].D;
         const int64_t row = (int64_t)(v - G.lo);
-        const uint32_t t = G.tent[row * 64 + lane];
-        const int32_t mysrc = G.src[lane];
-        const bool act = (t == D) && (mysrc != v);
         const bool restrict_parents = (G.flags & GF_RESTRICT) != 0;
+        const int32_t mysrc = G.src[b];
         const int64_t e0 = G.g.row_ptr[v], e1 = G.g.row_ptr[v + 1];
         uint64_t sum = 0;
         bool ovf = false;
         int tight = 0;
-        if (act) {
-            for (int64_t e = e0; e < e1; ++e) {
-                const int32_t u = G.g.col[e];
-                const uint32_t L = G.g.len ? G.g.len[e] : 1u;
-                if (L > D) continue;
-                const int64_t ur = (int64_t)(u - G.lo);
-                const uint32_t tu = G.tent[ur * 64 + lane];
-                if (tu != D - L) continue;
-                if (restrict_parents && u != mysrc && G.g.nflag &&
-                    (G.g.nflag[u] & NF_BLOCKED))
-                    continue;
-                uint64_t s = G.sigma[ur * 64 + lane];
-                if (G.g.mult) {
-                    const uint64_t m = G.g.mult[e];
-                    if (__umul64hi(s, m) != 0) ovf = true;
-                    s *= m;
-                }
-                const uint64_t r = sum + s;
-                if (r < sum) ovf = true;
-                sum = r;
-                ++tight;
+        for (int64_t e = e0; e < e1; e += UNR) {
+            int32_t u[UNR];
+            uint32_t L[UNR], du[UNR];
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                const bool in = e + k < e1;
+                u[k] = in ? G.g.col[e + k] : G.lo;
+                L[k] = in ? (G.g.len ? G.g.len[e + k] : 1u) : INF32;
             }
-            G.sigma[row * 64 + lane] = sum;
+#pragma unroll
+            for (int k = 0; k < UNR; ++k)
+                du[k] = (L[k] <= D) ? G.dist[(int64_t)(u[k] - G.lo) * 64 + b] : INF32;
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                if (du[k] == INF32 || du[k] + L[k] != D) continue;
+                ++tight;
+                const bool ok = !restrict_parents || u[k] == mysrc || !G.g.nflag ||
+                                !(G.g.nflag[u[k]] & NF_BLOCKED);
+                if (ok) {
+                    uint64_t x = G.sigma[(int64_t)(u[k] - G.lo) * 64 + b];
+                    if (G.g.mult && x) {
+                        const uint64_t m = G.g.mult[e + k];
+                        if (__umul64hi(x, m) != 0) ovf = true;
+                        x *= m;
+                    }
+                    const uint64_t r = sum + x;
+                    if (r < sum) ovf = true;
+                    sum = r;
+                }
+                if (G.tmask) {
+                    const int64_t t = G.g.twin[e + k] - G.arc_lo;
+                    if (t >= 0 && t < G.arcs)
+                        atomicOr((unsigned long long*)&G.tmask[t], 1ull << b);
+                    else
+                        atomicOr(&dyn[P.g].err, ERR_TWIN);
+                }
+            }
         }
-        if (__ballot(ovf) && lane == 0) atomicOr(&dyn[g].err, ERR_OVERFLOW);
-        const uint32_t pend = wave_min_u32(t > D ? t : INF32);
-        if (lane == 0) {
-            G.nd[row] = pend;
-            if (pend != INF32) atomicMin(&dyn[g].nextmin, pend);
-        }
+        G.dist[row * 64 + b] = D;
+        G.sigma[row * 64 + b] = sum;
+        if (ovf) atomicOr(&dyn[P.g].err, ERR_OVERFLOW);
         if (prof) {
-            // algorithmic bytes: per settled lane, one distance per arc, a count per
-            // tight parent, the count written; per item the CSR row once
+            // algorithmic bytes: one distance per arc, a count per tight parent, the
+            // distance and count written
             const unsigned long long deg = (unsigned long long)(e1 - e0);
-            unsigned long long mine = act ? (4ull * deg + 8ull * (unsigned)tight + 8ull) : 0ull;
-            mine = wave_sum_u64(mine);
-            bytes += mine + 16ull + deg * (4ull + (G.g.len ? 4ull : 0ull) +
-                                           (G.g.mult ? 8ull : 0ull));
+            bytes += 4ull * deg + 8ull * (unsigned)tight + 12ull;
         }
+    });
+    if (prof) {
+        bytes = wave_sum_u64(bytes);
+        if ((threadIdx.x & 63) == 0 && bytes) atomicAdd(&prof[BC_K_SETTLE], bytes);
     }
-    if (prof && lane == 0 && bytes) atomicAdd(&prof[BC_K_SETTLE], bytes);
 }
 
 // ------------------------------------------------------------------ push -------
 
+// A node whose lanes settled at D offers D + len to each neighbour: the lanes still
+// open there are or-ed into the neighbour's ring slot for that distance and its
+// pending distance is lowered to it. A wave takes ITEMS_PER_WAVE node items and
+// spreads all their arcs over its lanes, 64 arcs per round.
 __global__ void __launch_bounds__(WG) k_push(const GroupDesc* __restrict__ desc,
                                              GroupDyn* __restrict__ dyn,
-                                             const int2* __restrict__ wl,
+                                             const NodeItem* __restrict__ wl,
                                              const uint32_t* __restrict__ ctr,
                                              unsigned long long* __restrict__ prof) {
     const int lane = threadIdx.x & 63;
     const int64_t W = (int64_t)gridDim.x * WAVES_PER_WG;
     const uint32_t count = ctr[0];
     unsigned long long bytes = 0;
-    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_WG + (threadIdx.x >> 6); it < count;
-         it += W) {
-        const int2 item = wl[it];
-        const int g = item.x;
-        const int32_t v = item.y;
-        const GroupDesc& G = desc[g];
-        const uint32_t D = dyn[g].D;
-        const int64_t row = (int64_t)(v - G.lo);
-        const bool act = G.tent[row * 64 + lane] == D;
-        const bool unit = (G.flags & GF_UNIT) != 0;
-        const int64_t e0 = G.g.row_ptr[v], e1 = G.g.row_ptr[v + 1];
-        uint32_t best = INF32;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int32_t u = G.g.col[e];
-            const uint32_t L = G.g.len ? G.g.len[e] : 1u;
-            const uint32_t nv = D + L;
-            const int64_t ur = (int64_t)(u - G.lo);
-            bool improved = false;
-            if (act) {
-                uint32_t* p = &G.tent[ur * 64 + lane];
-                const uint32_t cur = *p;
-                if (cur > nv) {
-                    if (unit) {
-                        *p = nv;  // every writer of this step stores the same D + 1
-                        improved = true;
-                    } else {
-                        improved = atomicMin(p, nv) > nv;
-                    }
-                }
-            }
-            if (__ballot(improved)) {
-                if (lane == 0) {
-                    if (unit) {
-                        if (G.nd[ur] > nv) G.nd[ur] = nv;
-                    } else {
-                        atomicMin(&G.nd[ur], nv);
-                    }
-                }
-                best = min(best, nv);
-            }
+    for (int64_t chunk = (int64_t)blockIdx.x * WAVES_PER_WG + (threadIdx.x >> 6);
+         chunk * ITEMS_PER_WAVE < (int64_t)count; chunk += W) {
+        const int64_t idx = chunk * ITEMS_PER_WAVE + lane;
+        const bool have = lane < ITEMS_PER_WAVE && idx < (int64_t)count;
+        int32_t ig = 0;
+        unsigned long long im = 0ull;
+        int64_t ie0 = 0;
+        int deg = 0;
+        if (have) {
+            const NodeItem it = wl[idx];
+            ig = it.g;
+            im = it.mask;
+            const GroupDesc& G = desc[ig];
+            ie0 = G.g.row_ptr[it.v];
+            deg = (int)(G.g.row_ptr[it.v + 1] - ie0);
         }
-        if (lane == 0 && best != INF32) atomicMin(&dyn[g].nextmin, best);
-        if (prof) {
-            const unsigned long long deg = (unsigned long long)(e1 - e0);
-            unsigned long long mine = act ? 4ull * deg : 0ull;
-            mine = wave_sum_u64(mine);
-            bytes += mine + 16ull + deg * (4ull + (G.g.len ? 4ull : 0ull));
+        int incl = deg;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        const int total = __shfl(incl, 63, 64);
+        const int excl = incl - deg;
+        const int lo32 = (int)(uint32_t)im, hi32 = (int)(uint32_t)(im >> 32);
+        const int e0lo = (int)(uint32_t)ie0, e0hi = (int)(uint32_t)((uint64_t)ie0 >> 32);
+        for (int r = 0; r < total; r += 64) {
+            const int p = r + lane;
+            int j = 0;
+#pragma unroll
+            for (int k = 0; k < ITEMS_PER_WAVE; ++k) j += (__shfl(incl, k, 64) <= p) ? 1 : 0;
+            const int jj = min(j, ITEMS_PER_WAVE - 1);
+            const int g = __shfl(ig, jj, 64);
+            const unsigned long long amask =
+                ((unsigned long long)(uint32_t)__shfl(hi32, jj, 64) << 32) |
+                (unsigned long long)(uint32_t)__shfl(lo32, jj, 64);
+            const int64_t e0 = (int64_t)(((uint64_t)(uint32_t)__shfl(e0hi, jj, 64) << 32) |
+                                         (uint64_t)(uint32_t)__shfl(e0lo, jj, 64));
+            const int ex = __shfl(excl, jj, 64);
+            if (p >= total) continue;
+            const GroupDesc& G = desc[g];
+            const uint32_t D = dyn[g].D;
+            const int64_t e = e0 + (p - ex);
+            const int64_t ur = (int64_t)(G.g.col[e] - G.lo);
+            const uint32_t nv = D + (G.g.len ? G.g.len[e] : 1u);
+            const unsigned long long open = amask & ~G.done[ur];
+            if (open) {
+                const int R = G.ring_len;
+                unsigned long long* slot = (unsigned long long*)&G.ring[ur * R + nv % (uint32_t)R];
+                if (open & ~*slot) atomicOr(slot, open);
+                if (G.nd[ur] > nv) {
+                    if (G.flags & GF_UNIT)
+                        G.nd[ur] = nv;  // every writer of this step stores D + 1
+                    else
+                        atomicMin(&G.nd[ur], nv);
+                    atomicMin(&dyn[g].nextmin, nv);
+                }
+            }
+            if (prof) bytes += 4ull + (G.g.len ? 4ull : 0ull) + 8ull + 8ull;
         }
     }
-    if (prof && lane == 0 && bytes) atomicAdd(&prof[BC_K_PUSH], bytes);
+    if (prof) {
+        bytes = wave_sum_u64(bytes);
+        if (lane == 0 && bytes) atomicAdd(&prof[BC_K_PUSH], bytes);
+    }
 }
 
 // -------------------------------------------------------------- backward -------
 
 __global__ void __launch_bounds__(WG) k_backward(const GroupDesc* __restrict__ desc,
                                                  GroupDyn* __restrict__ dyn,
-                                                 const int2* __restrict__ wl,
+                                                 const NodeItem* __restrict__ wl,
                                                  int64_t wl_cap,
                                                  const uint32_t* __restrict__ ctr,
                                                  unsigned long long* __restrict__ prof) {
-    const int lane = threadIdx.x & 63;
-    const int64_t W = (int64_t)gridDim.x * WAVES_PER_WG;
+    (void)dyn;
     const uint32_t count = ctr[1];
-    const int2* list = wl + wl_cap;
     unsigned long long bytes = 0;
-    for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_WG + (threadIdx.x >> 6); it < count;
-         it += W) {
-        const int2 item = list[it];
-        const int g = item.x;
-        const int32_t v = item.y;
-        const GroupDesc& G = desc[g];
-        const uint32_t D = dyn[g].D;
+    for_pairs(wl + wl_cap, count, [&](const PairCursor& P) {
+        if (!P.valid) return;
+        const GroupDesc& G = desc[P.g];
+        const int32_t b = P.b;
+        const int32_t v = P.v;
+        if (G.src[b] == v) return;
         const int64_t row = (int64_t)(v - G.lo);
-        const uint32_t t = G.tent[row * 64 + lane];
-        const bool act = (t == D) && (G.src[lane] != v);
         const int64_t e0 = G.g.row_ptr[v], e1 = G.g.row_ptr[v + 1];
-        double delta = 0.0;
+        double acc = 0.0;
         int kids = 0;
-        if (act) {
-            double acc = 0.0;
-            for (int64_t e = e0; e < e1; ++e) {
-                const int32_t u = G.g.col[e];
-                const uint32_t L = G.g.len ? G.g.len[e] : 1u;
-                const int64_t ur = (int64_t)(u - G.lo);
-                const uint32_t tu = G.tent[ur * 64 + lane];
-                if (tu != D + L) continue;
-                const double c = G.coef[ur * 64 + lane];
-                acc += G.g.mult ? (double)G.g.mult[e] * c : c;
+        for (int64_t e = e0; e < e1; e += UNR) {
+            bool tk[UNR];
+            int32_t u[UNR];
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                const bool in = e + k < e1;
+                tk[k] = in && ((G.tmask[e + k - G.arc_lo] >> b) & 1ull);
+                u[k] = in ? G.g.col[e + k] : G.lo;
+            }
+            double c[UNR];
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) c[k] = tk[k] ? G.coef[(int64_t)(u[k] - G.lo) * 64 + b] : 0.0;
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                if (!tk[k]) continue;
+                acc += G.g.mult ? (double)G.g.mult[e + k] * c[k] : c[k];
                 ++kids;
             }
-            const double sg = (double)G.sigma[row * 64 + lane];
-            delta = sg * acc;
-            const double ind = (G.g.nflag && (G.g.nflag[v] & NF_TARGET)) ? 1.0 : 0.0;
-            G.coef[row * 64 + lane] = (ind + delta) / sg;
         }
-        const double tot = wave_sum_f64(delta);
-        if (lane == 0 && G.cacc) G.cacc[row] += tot;
+        const double sg = (double)G.sigma[row * 64 + b];
+        const double dl = sg * acc;
+        const double ind = (G.g.nflag && (G.g.nflag[v] & NF_TARGET)) ? 1.0 : 0.0;
+        G.coef[row * 64 + b] = (ind + dl) / sg;
+        G.delta[row * 64 + b] = dl;
         if (prof) {
             const unsigned long long deg = (unsigned long long)(e1 - e0);
-            unsigned long long mine =
-                act ? (4ull * deg + 8ull * (unsigned)kids + 8ull + 8ull) : 0ull;
-            mine = wave_sum_u64(mine);
-            bytes += mine + 16ull + 8ull +
-                     deg * (4ull + (G.g.len ? 4ull : 0ull) + (G.g.mult ? 8ull : 0ull));
+            bytes += 8ull * deg + 8ull * (unsigned)kids + 8ull + 16ull;
         }
+    });
+    if (prof) {
+        bytes = wave_sum_u64(bytes);
+        if ((threadIdx.x & 63) == 0 && bytes) atomicAdd(&prof[BC_K_BACKWARD], bytes);
     }
-    if (prof && lane == 0 && bytes) atomicAdd(&prof[BC_K_BACKWARD], bytes);
 }
 
 // ------------------------------------------------------------ centrality -------
@@ -372,26 +500,26 @@ __global__ void __launch_bounds__(WG) k_backward(const GroupDesc* __restrict__ d
 //                sigma(v,f) * coef(s,f)                       (eq. localcentrality)
 __global__ void __launch_bounds__(WG) k_centrality(const GroupDesc* __restrict__ desc,
                                                    GroupDyn* __restrict__ dyn,
-                                                   const int2* __restrict__ wl,
+                                                   const NodeItem* __restrict__ wl,
                                                    int64_t wl_cap,
                                                    const uint32_t* __restrict__ ctr,
                                                    unsigned long long* __restrict__ prof) {
     const int lane = threadIdx.x & 63;
     const int64_t W = (int64_t)gridDim.x * WAVES_PER_WG;
     const uint32_t count = ctr[2];
-    const int2* list = wl + 2 * wl_cap;
+    const NodeItem* list = wl + 2 * wl_cap;
     unsigned long long bytes = 0;
     for (int64_t it = (int64_t)blockIdx.x * WAVES_PER_WG + (threadIdx.x >> 6); it < count;
          it += W) {
-        const int2 item = list[it];
-        const int g = item.x;
-        const int32_t i = item.y;
+        const NodeItem item = list[it];
+        const int g = item.g;
+        const int32_t i = item.v;
         const GroupDesc& G = desc[g];
         const int64_t e0 = G.trow[i], e1 = G.trow[i + 1];
         uint32_t dv = INF32;
         for (int64_t e = e0; e < e1; ++e) {
             const int64_t fr = (int64_t)(G.tcol[e] - G.lo);
-            const uint32_t tf = G.tent[fr * 64 + lane];
+            const uint32_t tf = G.dist[fr * 64 + lane];
             if (tf != INF32) dv = min(dv, tf + G.tlen[e]);
         }
         double delta = 0.0;
@@ -401,14 +529,14 @@ __global__ void __launch_bounds__(WG) k_centrality(const GroupDesc* __restrict__
             double acc = 0.0;
             for (int64_t e = e0; e < e1; ++e) {
                 const int64_t fr = (int64_t)(G.tcol[e] - G.lo);
-                const uint32_t tf = G.tent[fr * 64 + lane];
+                const uint32_t tf = G.dist[fr * 64 + lane];
                 if (tf == INF32) continue;
                 const uint32_t L = G.tlen[e];
                 if (tf + L == dv) {
                     const uint64_t a = G.sigma[fr * 64 + lane];
-                    const uint64_t b = G.tsig[e];
-                    if (__umul64hi(a, b) != 0) ovf = true;
-                    const uint64_t p = a * b;
+                    const uint64_t bb = G.tsig[e];
+                    if (__umul64hi(a, bb) != 0) ovf = true;
+                    const uint64_t p = a * bb;
                     const uint64_t r = sv + p;
                     if (r < sv) ovf = true;
                     sv = r;
@@ -489,6 +617,28 @@ __global__ void k_sched(const GroupDesc* __restrict__ desc, GroupDyn* __restrict
     if (phase == PH_DONE) atomicSub(&ctr[3], 1u);
 }
 
+// ------------------------------------------------------------- lane sum -------
+
+// Each node's score share of a backward group: the sum over its lanes of delta(s|v),
+// in a fixed order (a wave reduction), written once.
+__global__ void __launch_bounds__(WG) k_lane_sum(const GroupDesc* __restrict__ desc,
+                                                 const int32_t* __restrict__ chunk_g,
+                                                 const int32_t* __restrict__ chunk_off,
+                                                 int64_t nchunks) {
+    const int64_t c = blockIdx.x;
+    if (c >= nchunks) return;
+    const GroupDesc& G = desc[chunk_g[c]];
+    if (!(G.flags & GF_BACKWARD)) return;
+    const int64_t range = (int64_t)G.hi - G.lo;
+    const int lane = threadIdx.x & 63;
+    for (int p = threadIdx.x >> 6; p < WG; p += WAVES_PER_WG) {
+        const int64_t i = chunk_off[c] + p;
+        if (i >= range) break;
+        const double s = wave_sum_f64(G.delta[i * 64 + lane]);
+        if (lane == 0) G.cacc[i] = s;
+    }
+}
+
 // ---------------------------------------------------------------- reduce -------
 
 __global__ void k_reduce(const double* const* __restrict__ cacc,
@@ -513,38 +663,52 @@ __global__ void k_reduce(const double* const* __restrict__ cacc,
 
 // ==================================================================== host ======
 
-size_t group_bytes(int64_t range, int32_t nsrc, uint32_t flags, int64_t max_steps, int32_t tn) {
+size_t group_bytes(const GroupDesc& G, int64_t max_steps) {
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const int64_t range = (int64_t)G.hi - G.lo;
     size_t b = 0;
-    b += al(range * 64 * 4);  // tent
-    b += al(range * 64 * 8);  // sigma
-    b += al(range * 4);       // nd
-    if (flags & GF_BACKWARD) {
-        b += al(range * 64 * 8);  // coef
-        b += al(range * 8);       // cacc
-        b += al(range * (int64_t)std::max(nsrc, 1) * 4);  // history
+    b += al(range * 64 * 4);                   // dist
+    b += al(range * 64 * 8);                   // sigma
+    b += al(range * 4);                        // nd
+    b += al(range * 8);                        // done
+    b += al(range * (int64_t)G.ring_len * 8);  // offer ring
+    if (G.flags & GF_BACKWARD) {
+        b += al(range * 64 * 8);                     // coef
+        b += al(range * 64 * 8);                     // delta
+        b += al(range * 8);                          // cacc
+        b += al(std::max<int64_t>(G.arcs, 1) * 8);  // tight-parent masks
+        const int64_t hc = range * (int64_t)std::max(G.nsrc, 1);
+        b += al(hc * 4) + al(hc * 8);                // history: node, lanes
         b += al(max_steps * 4) + al(max_steps * 8) + al(max_steps * 4);
     }
-    if (flags & GF_CENT) b += al((size_t)tn * 8);
+    if (G.flags & GF_CENT) b += al((size_t)std::max(G.tn, 1) * 8);
     return b;
 }
 
 bool group_alloc(Arena& a, GroupDesc& G, int64_t max_steps) {
     const int64_t range = (int64_t)G.hi - G.lo;
-    G.tent = a.take<uint32_t>(range * 64);
+    if (G.ring_len < 2) return false;
+    G.dist = a.take<uint32_t>(range * 64);
     G.sigma = a.take<uint64_t>(range * 64);
     G.nd = a.take<uint32_t>(range);
-    if (!G.tent || !G.sigma || !G.nd) return false;
+    G.done = a.take<uint64_t>(range);
+    G.ring = a.take<uint64_t>(range * (int64_t)G.ring_len);
+    if (!G.dist || !G.sigma || !G.nd || !G.done || !G.ring) return false;
     if (G.flags & GF_BACKWARD) {
+        if (!G.g.twin) return false;
         G.coef = a.take<double>(range * 64);
+        G.delta = a.take<double>(range * 64);
         G.cacc = a.take<double>(range);
+        G.tmask = a.take<uint64_t>(std::max<int64_t>(G.arcs, 1));
         G.hist_cap = range * (int64_t)std::max(G.nsrc, 1);
         G.hist = a.take<int32_t>(G.hist_cap);
+        G.hmask = a.take<uint64_t>(G.hist_cap);
         G.rec_cap = (int32_t)std::min<int64_t>(max_steps, INT32_MAX);
         G.rec_d = a.take<uint32_t>(G.rec_cap);
         G.rec_off = a.take<int64_t>(G.rec_cap);
         G.rec_cnt = a.take<int32_t>(G.rec_cap);
-        if (!G.coef || !G.cacc || !G.hist || !G.rec_d || !G.rec_off || !G.rec_cnt)
+        if (!G.coef || !G.delta || !G.cacc || !G.tmask || !G.hist || !G.hmask || !G.rec_d ||
+            !G.rec_off || !G.rec_cnt)
             return false;
     }
     if (G.flags & GF_CENT) {
@@ -557,7 +721,7 @@ bool group_alloc(Arena& a, GroupDesc& G, int64_t max_steps) {
 size_t engine_bytes(int32_t slots, int64_t positions) {
     const int64_t chunks = (positions + WG - 1) / WG + slots;
     return (size_t)slots * (sizeof(GroupDesc) + sizeof(GroupDyn) + 512) + (size_t)chunks * 8 +
-           (size_t)chunks * WG * 3 * sizeof(int2) + 8192;
+           (size_t)chunks * WG * 3 * sizeof(NodeItem) + 8192;
 }
 
 int Engine::setup(Arena& a, hipStream_t s, int32_t slots, int64_t positions) {
@@ -569,7 +733,7 @@ int Engine::setup(Arena& a, hipStream_t s, int32_t slots, int64_t positions) {
     d_dyn = a.take<GroupDyn>(slots);
     d_chunk_g = a.take<int32_t>(chunk_cap);
     d_chunk_off = a.take<int32_t>(chunk_cap);
-    d_wl = a.take<int2>(3 * wl_cap);
+    d_wl = a.take<NodeItem>(3 * wl_cap);
     d_ctr = a.take<uint32_t>(8);
     if (!d_desc || !d_dyn || !d_chunk_g || !d_chunk_off || !d_wl || !d_ctr)
         return fail(BC_E_NOMEM, "engine: workspace too small");
@@ -642,18 +806,16 @@ int Engine::install(const GroupDesc* groups, int32_t first, int32_t n) {
         BC_HIP(hipGetLastError());
         BC_HIP(hipStreamSynchronize(stream));
     }
-    uint32_t add = (uint32_t)n;
     // active += n (host-side read-modify-write: the engine is idle here)
     BC_HIP(hipMemcpyAsync(h_ctr, d_ctr, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
     BC_HIP(hipStreamSynchronize(stream));
-    h_ctr[3] += add;
+    h_ctr[3] += (uint32_t)n;
     BC_HIP(hipMemcpyAsync(d_ctr + 3, h_ctr + 3, sizeof(uint32_t), hipMemcpyHostToDevice, stream));
     BC_HIP(hipStreamSynchronize(stream));
     return BC_OK;
 }
 
 int Engine::iterate(int iters) {
-    const bool dbg = getenv("BCPP_DEBUG") != nullptr;
     unsigned long long* prof = profile_bytes ? profiler().d_bytes : nullptr;
     const unsigned sel_blocks = (unsigned)std::max<int64_t>(nchunks, 1);
     for (int k = 0; k < iters; ++k) {
@@ -687,11 +849,17 @@ int Engine::iterate(int iters) {
             hipLaunchKernelGGL(k_sched, dim3((cap + 255) / 256), dim3(256), 0, stream, d_desc,
                                d_dyn, cap, d_ctr);
         }
-        if (dbg) {
-            GroupDyn d0;
-            BC_HIP(hipMemcpy(&d0, d_dyn, sizeof(d0), hipMemcpyDeviceToHost));
-            fprintf(stderr, "iter: g0 phase %d D %u nrec %d rec_i %d\n", d0.phase, d0.D, d0.nrec, d0.rec_i);
-        }
+    }
+    BC_HIP(hipGetLastError());
+    return BC_OK;
+}
+
+int Engine::finish_scores() {
+    if (!nchunks) return BC_OK;
+    {
+        KTimer kt(BC_K_OTHER, stream);
+        hipLaunchKernelGGL(k_lane_sum, dim3((unsigned)nchunks), dim3(WG), 0, stream, d_desc,
+                           d_chunk_g, d_chunk_off, nchunks);
     }
     BC_HIP(hipGetLastError());
     return BC_OK;
@@ -709,21 +877,16 @@ int Engine::run_to_completion(int32_t nslots, std::vector<GroupDyn>* dyn_out) {
         if (total > (int64_t)1 << 40) return fail(BC_E_DEVICE, "engine: no progress");
         batch = std::min(batch * 2, 32);
     }
+    BC_TRY(finish_scores());
     std::vector<GroupDyn> dy(nslots);
     BC_HIP(hipMemcpyAsync(dy.data(), d_dyn, sizeof(GroupDyn) * nslots, hipMemcpyDeviceToHost, stream));
     BC_HIP(hipStreamSynchronize(stream));
     uint32_t err = 0;
     for (auto& d : dy) err |= d.err;
-    if (getenv("BCPP_DEBUG")) {
-        fprintf(stderr, "engine: %d slots done\n", nslots);
-        for (int32_t g = 0; g < nslots && g < 8; ++g)
-            fprintf(stderr, "  group %d: phase %d D %u nrec %d rec_i %d hist %lld err %u\n", g,
-                    dy[g].phase, dy[g].D, dy[g].nrec, dy[g].rec_i, (long long)dy[g].hist_len,
-                    dy[g].err);
-    }
     if (dyn_out) *dyn_out = dy;
     if (err & ERR_OVERFLOW) return fail(BC_E_OVERFLOW, "a shortest-path count reached 2^64");
     if (err & (ERR_HIST | ERR_REC)) return fail(BC_E_DEVICE, "engine: history capacity exceeded");
+    if (err & ERR_TWIN) return fail(BC_E_DEVICE, "engine: graph arc without a reverse arc");
     return BC_OK;
 }
 
@@ -735,12 +898,12 @@ int run_groups(Arena& a, hipStream_t s, std::vector<GroupDesc>& groups, int64_t 
         positions += std::max<int64_t>((int64_t)G.hi - G.lo, (G.flags & GF_CENT) ? G.tn : 0);
     }
     Engine E;
-    BC_TRY(E.setup(a, s, (int32_t)groups.size(), positions));
-    BC_TRY(E.install(groups.data(), 0, (int32_t)groups.size()));
+    int rc = E.setup(a, s, (int32_t)groups.size(), positions);
+    if (rc == BC_OK) rc = E.install(groups.data(), 0, (int32_t)groups.size());
     std::vector<int32_t> live(groups.size());
     for (size_t i = 0; i < live.size(); ++i) live[i] = (int32_t)i;
-    BC_TRY(E.set_chunks(groups, live));
-    int rc = E.run_to_completion((int32_t)groups.size());
+    if (rc == BC_OK) rc = E.set_chunks(groups, live);
+    if (rc == BC_OK) rc = E.run_to_completion((int32_t)groups.size());
     if (E.h_ctr) (void)hipHostFree(E.h_ctr);
     return rc;
 }

@@ -19,6 +19,7 @@ struct bc_graph {
     int64_t* d_row_ptr = nullptr;
     int32_t* d_col = nullptr;
     uint32_t* d_len = nullptr;  // null for unit weights
+    int64_t* d_twin = nullptr;  // reverse arc of each arc
     bcpp::Arena store;  // graph arrays
     bcpp::Arena work;   // per-call workspace
     bcpp::Arena out;    // staging for host-pointer outputs
@@ -32,6 +33,7 @@ struct bc_skeleton {
     int64_t m_arcs = 0;      // skeleton arcs
     int64_t t_nnz = 0;       // table entries
     int64_t max_dist = 0;    // bound on skeleton distances
+    int32_t max_len = 1;     // longest skeleton arc
     bc_sk_stats stats{};
     // skeleton targets in skeleton ids (the sources of Brandes_SK), in target order
     std::vector<int32_t> h_src;
@@ -43,6 +45,8 @@ struct bc_skeleton {
     int32_t* d_col = nullptr;      // [m_arcs]
     uint32_t* d_len = nullptr;     // [m_arcs]
     uint64_t* d_mult = nullptr;    // [m_arcs]
+    int64_t* d_twin = nullptr;     // [m_arcs] reverse arc
+    std::vector<int64_t> h_row_ptr;  // host copy of d_row_ptr
     uint8_t* d_nflag = nullptr;    // [n_sk] NF_TARGET
     int64_t* d_trow = nullptr;     // [n_int+1]
     int32_t* d_tcol = nullptr;     // [t_nnz] skeleton ids

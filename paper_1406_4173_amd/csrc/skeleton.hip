@@ -47,7 +47,8 @@ __global__ void k_clique_count(const GroupDesc* __restrict__ desc, const DskInfo
 __global__ void k_clique_fill(const GroupDesc* __restrict__ desc, const DskInfo* __restrict__ info,
                               int32_t ngroups, const int64_t* __restrict__ row_ptr,
                               const int32_t* __restrict__ rdeg, int32_t* __restrict__ col,
-                              uint32_t* __restrict__ len, uint64_t* __restrict__ mult) {
+                              uint32_t* __restrict__ len, uint64_t* __restrict__ mult,
+                              uint32_t* __restrict__ maxlen) {
     const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (g >= ngroups) return;
@@ -57,14 +58,18 @@ __global__ void k_clique_fill(const GroupDesc* __restrict__ desc, const DskInfo*
     const int32_t own = I.fl0 + lane;
     const int32_t f = I.sk_base + own;
     int64_t pos = row_ptr[f] + rdeg[f];
+    uint32_t mx = 0;
     for (int32_t j = 0; j < I.nf; ++j) {
         const uint64_t s = G.sigma[(int64_t)j * 64 + lane];
         if (j == own || s == 0) continue;
+        const uint32_t d = G.dist[(int64_t)j * 64 + lane];
         col[pos] = I.sk_base + j;
-        len[pos] = G.tent[(int64_t)j * 64 + lane];
+        len[pos] = d;
         mult[pos] = s;
+        mx = max(mx, d);
         ++pos;
     }
+    if (mx) atomicMax(maxlen, mx);
 }
 
 // Cut arcs R with tuple <w(e), 1>, placed first in each skeleton row.
@@ -79,6 +84,30 @@ __global__ void k_fill_r(int32_t nsk, const int64_t* __restrict__ rptr, const in
         col[pos] = rcol[e];
         len[pos] = rw[e];
         mult[pos] = 1;
+    }
+}
+
+// Reverse arc of every skeleton arc. A row is [cut arcs][clique arcs], each segment
+// sorted by skeleton id, so the twin of f->q is found by bisection in q's segments.
+__global__ void k_sk_twin(int32_t nsk, const int64_t* __restrict__ row_ptr,
+                          const int32_t* __restrict__ rdeg, const int32_t* __restrict__ col,
+                          int64_t* __restrict__ twin) {
+    const int32_t f = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (f >= nsk) return;
+    for (int64_t e = row_ptr[f] + lane; e < row_ptr[f + 1]; e += 64) {
+        const int32_t q = col[e];
+        int64_t lo = row_ptr[q], mid_end = row_ptr[q] + rdeg[q], hi = row_ptr[q + 1];
+        int64_t found = -1;
+        for (int seg = 0; seg < 2 && found < 0; ++seg) {
+            int64_t a = seg ? mid_end : lo, b = seg ? hi : mid_end;
+            while (a < b) {
+                const int64_t m = (a + b) >> 1;
+                if (col[m] < f) a = m + 1; else b = m;
+            }
+            if (a < (seg ? hi : mid_end) && col[a] == f) found = a;
+        }
+        twin[e] = found;
     }
 }
 
@@ -105,7 +134,7 @@ __global__ void k_table(const GroupDesc* __restrict__ desc, const DskInfo* __res
         uint32_t d = 0;
         if (lane < I.nsrc) {
             s = G.sigma[local * 64 + lane];
-            d = G.tent[local * 64 + lane];
+            d = G.dist[local * 64 + lane];
         }
         const bool keep = s != 0;
         const unsigned long long m = __ballot(keep);
@@ -210,7 +239,16 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
                     rw.push_back(wt ? (uint32_t)wt[e] : 1u);
                 }
             }
-            rptr[f + 1] = (int64_t)rcol.size();
+            // rows sorted by skeleton id, so that reverse arcs can be found by bisection
+            const int64_t a0 = rptr[f], a1 = (int64_t)rcol.size();
+            std::vector<std::pair<int32_t, uint32_t>> tmp;
+            for (int64_t e = a0; e < a1; ++e) tmp.push_back({rcol[e], rw[e]});
+            std::sort(tmp.begin(), tmp.end());
+            for (int64_t e = a0; e < a1; ++e) {
+                rcol[e] = tmp[e - a0].first;
+                rw[e] = tmp[e - a0].second;
+            }
+            rptr[f + 1] = a1;
         }
     }
     // frontier ids are assigned in renumbered order, so rptr is filled in id order
@@ -233,6 +271,7 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
             G.lo = (int32_t)poff[p];
             G.hi = (int32_t)(poff[p] + psize[p]);
             G.flags = GF_RESTRICT | (wt ? 0u : GF_UNIT);
+            G.ring_len = g->maxw + 1;
             G.nsrc = (int32_t)std::min<int64_t>(LANES, pnf[p] - c);
             for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? (int32_t)(poff[p] + c + b) : -1;
             groups.push_back(G);
@@ -267,7 +306,8 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     size_t need = 0;
     for (auto& G : groups) {
         positions += (int64_t)G.hi - G.lo;
-        need += group_bytes((int64_t)G.hi - G.lo, G.nsrc, G.flags, 0, 0);
+        G.arcs = irp[G.hi] - irp[G.lo];
+        need += group_bytes(G, 0);
     }
     need += engine_bytes(std::max(ng, 1), positions);
     need += (size_t)(n + 1) * 8 + icol.size() * 4 + iw.size() * 4 + (size_t)n +
@@ -289,6 +329,7 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     int32_t* d_ig0 = W.take<int32_t>(std::max(nint, 1));
     int32_t* d_ing = W.take<int32_t>(std::max(nint, 1));
     int32_t* d_tdeg = W.take<int32_t>(std::max(nint, 1));
+    uint32_t* d_maxlen = W.take<uint32_t>(1);
     if (!d_irp || !d_icol || !d_blk || !d_rptr || !d_rcol || !d_rw || !d_rdeg || !d_cdeg || !d_info ||
         !d_il || !d_ig0 || !d_ing || !d_tdeg || (wt && !d_iw))
         return fail(BC_E_NOMEM, "partition: workspace too small");
@@ -313,6 +354,7 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     BC_TRY(h2d(d_ig0, int_g0.data(), nint * 4));
     BC_TRY(h2d(d_ing, int_ng.data(), nint * 4));
     if (nsk) BC_HIP(hipMemsetAsync(d_cdeg, 0, (size_t)nsk * 4, s));
+    BC_HIP(hipMemsetAsync(d_maxlen, 0, 4, s));
 
     for (auto& G : groups) {
         G.g.row_ptr = d_irp;
@@ -351,7 +393,7 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     const int64_t M = srow[nsk], T = trow[nint];
 
     // ---- the skeleton's own store
-    size_t sbytes = (size_t)(nsk + 1) * 8 + (size_t)M * (4 + 4 + 8) + (size_t)nsk +
+    size_t sbytes = (size_t)(nsk + 1) * 8 + (size_t)M * (4 + 4 + 8 + 8) + (size_t)nsk +
                     (size_t)(nint + 1) * 8 + (size_t)T * (4 + 4 + 8) + (size_t)nsk * 4 +
                     (size_t)nint * 4 + (size_t)n * 5 + 32 * 256;
     BC_TRY(sk->store.reserve(sbytes));
@@ -360,6 +402,7 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     sk->d_col = A.take<int32_t>(std::max<int64_t>(M, 1));
     sk->d_len = A.take<uint32_t>(std::max<int64_t>(M, 1));
     sk->d_mult = A.take<uint64_t>(std::max<int64_t>(M, 1));
+    sk->d_twin = A.take<int64_t>(std::max<int64_t>(M, 1));
     sk->d_nflag = A.take<uint8_t>(std::max(nsk, 1));
     sk->d_trow = A.take<int64_t>(nint + 1);
     sk->d_tcol = A.take<int32_t>(std::max<int64_t>(T, 1));
@@ -393,19 +436,28 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
                                d_rw, sk->d_row_ptr, sk->d_col, sk->d_len, sk->d_mult);
         if (ng) {
             hipLaunchKernelGGL(k_clique_fill, dim3((ng + 3) / 4), dim3(256), 0, s, d_desc, d_info, ng,
-                               sk->d_row_ptr, d_rdeg, sk->d_col, sk->d_len, sk->d_mult);
+                               sk->d_row_ptr, d_rdeg, sk->d_col, sk->d_len, sk->d_mult, d_maxlen);
             if (nint)
                 hipLaunchKernelGGL(k_table, dim3((nint + 3) / 4), dim3(256), 0, s, d_desc, d_info, nint,
                                    d_il, d_ig0, d_ing, nullptr, sk->d_trow, sk->d_tcol, sk->d_tlen,
                                    sk->d_tsig);
         }
+        if (nsk)
+            hipLaunchKernelGGL(k_sk_twin, dim3((nsk + 3) / 4), dim3(256), 0, s, nsk, sk->d_row_ptr,
+                               d_rdeg, sk->d_col, sk->d_twin);
     }
     BC_HIP(hipGetLastError());
+    uint32_t clique_max = 0;
+    BC_HIP(hipMemcpyAsync(&clique_max, d_maxlen, 4, hipMemcpyDeviceToHost, s));
     BC_HIP(hipStreamSynchronize(s));
+    uint32_t rmax = 1;
+    for (uint32_t x : rw) rmax = std::max(rmax, x);
+    sk->max_len = (int32_t)std::max(rmax, clique_max);
 
     // Brandes_SK sources: targets that have a neighbour (isolated targets reach nobody)
     for (int32_t i = 0; i < nS; ++i)
         if (fr[S[i]]) sk->h_src.push_back(skid(S[i]));
+    sk->h_row_ptr = srow;
     sk->h_out_idx = std::move(out_idx);
     sk->h_out_which = std::move(out_which);
     sk->n_sk = nsk;
@@ -449,7 +501,14 @@ int pp_run(const bc_graph* gc, const bc_skeleton* sk, uint32_t flags, double* ou
     const int64_t steps = max_steps_bound(N, LANES, sk->max_dist);
     const int32_t ngroups = (nsrc + LANES - 1) / LANES;
     const uint32_t gflags = GF_BACKWARD | (sk->n_int ? GF_CENT : 0u);
-    const size_t per_group = group_bytes(N, LANES, gflags, steps, sk->n_int);
+    GroupDesc shape;
+    shape.hi = N;
+    shape.arcs = sk->m_arcs;
+    shape.nsrc = LANES;
+    shape.flags = gflags;
+    shape.tn = sk->n_int;
+    shape.ring_len = sk->max_len + 1;
+    const size_t per_group = group_bytes(shape, steps);
     int32_t wave_groups = (int32_t)std::max<size_t>(1, state_budget() / std::max<size_t>(per_group, 1));
     if (const char* e = getenv("BCPP_MAX_GROUPS")) wave_groups = std::max(1, atoi(e));
     wave_groups = std::min(wave_groups, ngroups);
@@ -468,8 +527,12 @@ int pp_run(const bc_graph* gc, const bc_skeleton* sk, uint32_t flags, double* ou
             G.g.len = sk->d_len;
             G.g.mult = sk->d_mult;
             G.g.nflag = sk->d_nflag;
+            G.g.twin = sk->d_twin;
             G.lo = 0;
             G.hi = N;
+            G.arc_lo = 0;
+            G.arcs = sk->m_arcs;
+            G.ring_len = sk->max_len + 1;
             G.flags = gflags;
             G.trow = sk->d_trow;
             G.tcol = sk->d_tcol;
@@ -508,9 +571,13 @@ int sk_sssp_run(const bc_skeleton* sk, const int32_t* src, int32_t nsrc, int64_t
     std::vector<uint32_t> ht((size_t)N * LANES);
     std::vector<uint64_t> hs((size_t)N * LANES);
     for (int32_t g0 = 0; g0 * LANES < nsrc; ++g0) {
-        BC_TRY(g->work.reserve(group_bytes(N, LANES, 0, steps, 0) + engine_bytes(1, N) + 65536));
         std::vector<GroupDesc> groups(1);
         GroupDesc& G = groups[0];
+        G.hi = N;
+        G.arcs = sk->m_arcs;
+        G.nsrc = LANES;
+        G.ring_len = sk->max_len + 1;
+        BC_TRY(g->work.reserve(group_bytes(G, steps) + engine_bytes(1, N) + 65536));
         G.g.row_ptr = sk->d_row_ptr;
         G.g.col = sk->d_col;
         G.g.len = sk->d_len;
@@ -521,7 +588,7 @@ int sk_sssp_run(const bc_skeleton* sk, const int32_t* src, int32_t nsrc, int64_t
         G.nsrc = std::min(LANES, nsrc - first);
         for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? ssrc[first + b] : -1;
         BC_TRY(run_groups(g->work, s, groups, steps));
-        BC_HIP(hipMemcpyAsync(ht.data(), G.tent, ht.size() * 4, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(ht.data(), G.dist, ht.size() * 4, hipMemcpyDeviceToHost, s));
         BC_HIP(hipMemcpyAsync(hs.data(), G.sigma, hs.size() * 8, hipMemcpyDeviceToHost, s));
         BC_HIP(hipStreamSynchronize(s));
         for (int b = 0; b < G.nsrc; ++b) {
