@@ -22,6 +22,7 @@ int Arena::reserve(size_t bytes) {
         used = 0;
         return BC_OK;
     }
+    if (!owning) return fail(BC_E_NOMEM, "workspace view too small");
     release();
     hipError_t e = hipMalloc((void**)&base, bytes);
     if (e != hipSuccess) {
@@ -35,7 +36,7 @@ int Arena::reserve(size_t bytes) {
 }
 
 void Arena::release() {
-    if (base) (void)hipFree(base);
+    if (base && owning) (void)hipFree(base);
     base = nullptr;
     cap = used = 0;
 }

@@ -58,6 +58,34 @@ struct Arena {
     size_t peak = 0;
     // capacity limit (0 = no limit) so that a budget can be enforced
     size_t limit = 0;
+    bool owning = true;  // false: a view of memory owned elsewhere (never freed here)
+
+    // A non-owning arena over [base, base + cap).
+    static Arena view(void* base, size_t cap) {
+        Arena a;
+        a.base = (char*)base;
+        a.cap = cap;
+        a.owning = false;
+        return a;
+    }
+    Arena() = default;
+    Arena(const Arena&) = delete;
+    Arena& operator=(const Arena&) = delete;
+    Arena(Arena&& o) noexcept { *this = std::move(o); }
+    Arena& operator=(Arena&& o) noexcept {
+        if (this != &o) {
+            release();
+            base = o.base;
+            cap = o.cap;
+            used = o.used;
+            peak = o.peak;
+            limit = o.limit;
+            owning = o.owning;
+            o.base = nullptr;
+            o.cap = o.used = 0;
+        }
+        return *this;
+    }
 
     int reserve(size_t bytes);  // ensure cap >= bytes (drops contents)
     void reset() { used = 0; }

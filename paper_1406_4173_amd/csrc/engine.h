@@ -136,6 +136,12 @@ struct Engine {
 
 // Run the given groups to completion on a fresh engine (synchronous helper).
 int run_groups(Arena& a, hipStream_t s, std::vector<GroupDesc>& groups, int64_t max_steps);
+// Per-node sums of the lanes' dependencies for the backward groups named by the chunk
+// table (chunks of 256 positions, as built by Engine::set_chunks).
+int lane_sum(hipStream_t s, const GroupDesc* d_desc, const int32_t* d_chunk_g,
+             const int32_t* d_chunk_off, int64_t nchunks);
+// Same, for groups whose state has already been carved out (group_alloc).
+int run_groups_prealloc(Arena& a, hipStream_t s, std::vector<GroupDesc>& groups);
 
 // Sum per-group partial scores into out[v] for v in [0, n), in group order:
 //   out[v] (+)= scale * sum_{g in [g0[v], g1[v])} part[g][idx[v]]

@@ -865,6 +865,18 @@ int Engine::finish_scores() {
     return BC_OK;
 }
 
+int lane_sum(hipStream_t s, const GroupDesc* d_desc, const int32_t* d_chunk_g,
+             const int32_t* d_chunk_off, int64_t nchunks) {
+    if (!nchunks) return BC_OK;
+    {
+        KTimer kt(BC_K_OTHER, s);
+        hipLaunchKernelGGL(k_lane_sum, dim3((unsigned)nchunks), dim3(WG), 0, s, d_desc, d_chunk_g,
+                           d_chunk_off, nchunks);
+    }
+    BC_HIP(hipGetLastError());
+    return BC_OK;
+}
+
 int Engine::run_to_completion(int32_t nslots, std::vector<GroupDyn>* dyn_out) {
     // Every group finishes within 2 * (steps + 1) + 1 iterations; steps per group are
     // bounded by its record capacity, so the loop below always terminates.
@@ -892,11 +904,16 @@ int Engine::run_to_completion(int32_t nslots, std::vector<GroupDyn>* dyn_out) {
 
 int run_groups(Arena& a, hipStream_t s, std::vector<GroupDesc>& groups, int64_t max_steps) {
     if (groups.empty()) return BC_OK;
-    int64_t positions = 0;
-    for (auto& G : groups) {
+    for (auto& G : groups)
         if (!group_alloc(a, G, max_steps)) return fail(BC_E_NOMEM, "engine: group state does not fit");
+    return run_groups_prealloc(a, s, groups);
+}
+
+int run_groups_prealloc(Arena& a, hipStream_t s, std::vector<GroupDesc>& groups) {
+    if (groups.empty()) return BC_OK;
+    int64_t positions = 0;
+    for (auto& G : groups)
         positions += std::max<int64_t>((int64_t)G.hi - G.lo, (G.flags & GF_CENT) ? G.tn : 0);
-    }
     Engine E;
     int rc = E.setup(a, s, (int32_t)groups.size(), positions);
     if (rc == BC_OK) rc = E.install(groups.data(), 0, (int32_t)groups.size());

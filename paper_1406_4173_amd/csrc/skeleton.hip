@@ -13,16 +13,9 @@
 
 #include "engine.h"
 #include "graph.h"
+#include "skbuild.h"
 
 namespace bcpp {
-
-// Per Dijkstra_SK group: which slice of its part's frontier it searches from.
-struct DskInfo {
-    int32_t nf;       // |F_p|
-    int32_t fl0;      // local index of the group's lane 0 source
-    int32_t nsrc;     // sources in this group
-    int32_t sk_base;  // skeleton id of the part's first frontier node
-};
 
 // -------------------------------------------------------------- assembly -------
 
@@ -151,34 +144,31 @@ __global__ void k_table(const GroupDesc* __restrict__ desc, const DskInfo* __res
 
 // ------------------------------------------------------------ partition_sk -----
 
-// given_singletons: the labels in `part` already hold every target as a singleton
-// part (the batched path builds P' per graph); otherwise target S[i] gets label k + i.
-int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
-                   bc_skeleton** out, bool given_singletons) {
-    const int32_t n = g->n;
+int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const int32_t* Sx,
+                     int32_t nS, bool given_singletons) {
+    g = gr;
+    n = g->n;
     if (n > 0 && !part) return fail(BC_E_INVAL, "null partition");
     if (n > 0 && k < 1) return fail(BC_E_INVAL, "k must be >= 1");
     for (int32_t v = 0; v < n; ++v)
-        if (part[v] < 0 || part[v] >= k) return fail(BC_E_INVAL, "partition label out of range at node " + std::to_string(v));
-    BC_TRY(validate_targets(n, S, nS));
-    hipStream_t s = g->stream;
-    auto sk = std::make_unique<bc_skeleton>();
-    sk->graph = g;
-    sk->n = n;
+        if (part[v] < 0 || part[v] >= k)
+            return fail(BC_E_INVAL, "partition label out of range at node " + std::to_string(v));
+    BC_TRY(validate_targets(n, Sx, nS));
+    S.assign(Sx, Sx + nS);
     const int64_t* rp = g->h_row_ptr.data();
     const int32_t* cl = g->h_col.data();
     const int32_t* wt = g->h_w.empty() ? nullptr : g->h_w.data();
+    weighted = wt != nullptr;
 
     // ---- P' (Step 1, "Target nodes in the skeleton") and frontiers (Sec. 4)
-    const int64_t nlab = (int64_t)k + (given_singletons ? 0 : nS);
-    std::vector<int32_t> lab(n);
-    for (int32_t v = 0; v < n; ++v) lab[v] = part[v];
-    std::vector<uint8_t> is_t(n, 0);
+    nlab = (int64_t)k + (given_singletons ? 0 : nS);
+    lab.assign(part, part + n);
+    is_t.assign(n, 0);
     for (int32_t i = 0; i < nS; ++i) {
         if (!given_singletons) lab[S[i]] = k + i;
         is_t[S[i]] = 1;
     }
-    std::vector<uint8_t> fr(n, 0);
+    fr.assign(n, 0);
     for (int32_t v = 0; v < n; ++v)
         for (int64_t e = rp[v]; e < rp[v + 1]; ++e)
             if (lab[cl[e]] != lab[v]) {
@@ -186,12 +176,14 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
                 break;
             }
     // ---- renumbering: parts contiguous, frontier first
-    std::vector<int64_t> psize(nlab + 1, 0), pnf(nlab, 0);
+    psize.assign(nlab + 1, 0);
+    pnf.assign(nlab, 0);
     for (int32_t v = 0; v < n; ++v) {
         psize[lab[v]]++;
         pnf[lab[v]] += fr[v];
     }
-    std::vector<int64_t> poff(nlab + 1, 0), fbase(nlab + 1, 0);
+    poff.assign(nlab + 1, 0);
+    fbase.assign(nlab + 1, 0);
     for (int64_t p = 0; p < nlab; ++p) {
         poff[p + 1] = poff[p] + psize[p];
         fbase[p + 1] = fbase[p] + pnf[p];
@@ -201,25 +193,27 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
         fcur[p] = poff[p];
         icur[p] = poff[p] + pnf[p];
     }
-    std::vector<int32_t> nid(n), old(n);
+    nid.assign(n, 0);
+    old.assign(n, 0);
     for (int32_t v = 0; v < n; ++v) {
         const int32_t p = lab[v];
         const int64_t r = fr[v] ? fcur[p]++ : icur[p]++;
         nid[v] = (int32_t)r;
         old[r] = v;
     }
-    const int32_t nsk = (int32_t)fbase[nlab];
+    nsk = (int32_t)fbase[nlab];
     auto skid = [&](int32_t v) -> int32_t { return (int32_t)(fbase[lab[v]] + (nid[v] - poff[lab[v]])); };
 
     // ---- intra-part CSR (renumbered) and the cut arcs R by skeleton id
-    std::vector<int64_t> irp(n + 1, 0);
-    std::vector<int32_t> icol;
-    std::vector<uint32_t> iw;
+    irp.assign(n + 1, 0);
+    icol.clear();
+    iw.clear();
     icol.reserve(g->nnz);
-    iw.reserve(wt ? g->nnz : 0);
-    std::vector<int64_t> rptr(nsk + 1, 0);
-    std::vector<int32_t> rcol;
-    std::vector<uint32_t> rw;
+    if (wt) iw.reserve(g->nnz);
+    rptr.assign(nsk + 1, 0);
+    rcol.clear();
+    rw.clear();
+    std::vector<std::pair<int32_t, uint32_t>> tmp;
     for (int32_t r = 0; r < n; ++r) {
         const int32_t v = old[r];
         for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
@@ -232,6 +226,7 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
         irp[r + 1] = (int64_t)icol.size();
         if (fr[v]) {
             const int32_t f = skid(v);
+            const int64_t a0 = (int64_t)rcol.size();
             for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
                 const int32_t u = cl[e];
                 if (lab[u] != lab[v]) {
@@ -240,25 +235,24 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
                 }
             }
             // rows sorted by skeleton id, so that reverse arcs can be found by bisection
-            const int64_t a0 = rptr[f], a1 = (int64_t)rcol.size();
-            std::vector<std::pair<int32_t, uint32_t>> tmp;
+            const int64_t a1 = (int64_t)rcol.size();
+            tmp.clear();
             for (int64_t e = a0; e < a1; ++e) tmp.push_back({rcol[e], rw[e]});
             std::sort(tmp.begin(), tmp.end());
             for (int64_t e = a0; e < a1; ++e) {
                 rcol[e] = tmp[e - a0].first;
                 rw[e] = tmp[e - a0].second;
             }
-            rptr[f + 1] = a1;
+            rptr[f + 1] = a1;  // frontier ids come in renumbered order
         }
     }
-    // frontier ids are assigned in renumbered order, so rptr is filled in id order
-    const int64_t nR = (int64_t)rcol.size();
+    nR = (int64_t)rcol.size();
 
     // ---- Dijkstra_SK groups: every part with >= 2 nodes and a frontier
-    std::vector<GroupDesc> groups;
-    std::vector<DskInfo> info;
+    groups.clear();
+    info.clear();
     std::vector<int32_t> p_g0(nlab, 0), p_ng(nlab, 0);
-    int64_t largest = 0, kprime = 0, clique_pairs = 0, table_pairs = 0;
+    largest = kprime = clique_pairs = table_pairs = 0;
     for (int64_t p = 0; p < nlab; ++p) {
         if (psize[p] > 0) kprime++;
         largest = std::max(largest, psize[p]);
@@ -270,6 +264,7 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
             GroupDesc G;
             G.lo = (int32_t)poff[p];
             G.hi = (int32_t)(poff[p] + psize[p]);
+            G.arcs = irp[G.hi] - irp[G.lo];
             G.flags = GF_RESTRICT | (wt ? 0u : GF_UNIT);
             G.ring_len = g->maxw + 1;
             G.nsrc = (int32_t)std::min<int64_t>(LANES, pnf[p] - c);
@@ -280,9 +275,12 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
         p_ng[p] = (int32_t)groups.size() - p_g0[p];
     }
     // interior rows: non-frontier nodes of parts with groups, in renumbered order
-    std::vector<int32_t> int_local, int_g0, int_ng, int_node;
-    std::vector<int32_t> out_idx(n, -1);
-    std::vector<uint8_t> out_which(n, 0);
+    int_local.clear();
+    int_g0.clear();
+    int_ng.clear();
+    int_node.clear();
+    out_idx.assign(n, -1);
+    out_which.assign(n, 0);
     for (int64_t p = 0; p < nlab; ++p) {
         if (p_ng[p] == 0) continue;
         for (int64_t r = poff[p] + pnf[p]; r < poff[p + 1]; ++r) {
@@ -296,43 +294,54 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     }
     for (int32_t v = 0; v < n; ++v)
         if (fr[v]) out_idx[v] = skid(v);
-    const int32_t nint = (int32_t)int_local.size();
-    const int32_t ng = (int32_t)groups.size();
+    nint = (int32_t)int_local.size();
+    return BC_OK;
+}
 
-    // ---- device work: temporaries, Dijkstra_SK, assembly
-    bc_graph* gm = const_cast<bc_graph*>(g);
-    Arena& W = gm->work;
-    int64_t positions = 0;
+size_t SkBuild::temp_bytes() const {
+    const int32_t ng = (int32_t)groups.size();
     size_t need = 0;
-    for (auto& G : groups) {
-        positions += (int64_t)G.hi - G.lo;
-        G.arcs = irp[G.hi] - irp[G.lo];
-        need += group_bytes(G, 0);
-    }
-    need += engine_bytes(std::max(ng, 1), positions);
+    for (const auto& G : groups) need += group_bytes(G, 0);
     need += (size_t)(n + 1) * 8 + icol.size() * 4 + iw.size() * 4 + (size_t)n +
-            (size_t)(nsk + 1) * 8 * 2 + (size_t)nR * 8 + (size_t)nsk * 8 +
-            (size_t)ng * sizeof(DskInfo) + (size_t)ng * sizeof(GroupDesc) + (size_t)nint * 16 +
-            64 * 256;
-    BC_TRY(W.reserve(need));
-    int64_t* d_irp = W.take<int64_t>(n + 1);
-    int32_t* d_icol = W.take<int32_t>(std::max<size_t>(icol.size(), 1));
-    uint32_t* d_iw = wt ? W.take<uint32_t>(std::max<size_t>(iw.size(), 1)) : nullptr;
-    uint8_t* d_blk = W.take<uint8_t>(std::max(n, 1));
-    int64_t* d_rptr = W.take<int64_t>(nsk + 1);
-    int32_t* d_rcol = W.take<int32_t>(std::max<int64_t>(nR, 1));
-    uint32_t* d_rw = W.take<uint32_t>(std::max<int64_t>(nR, 1));
-    int32_t* d_rdeg = W.take<int32_t>(std::max(nsk, 1));
-    int32_t* d_cdeg = W.take<int32_t>(std::max(nsk, 1));
-    DskInfo* d_info = W.take<DskInfo>(std::max(ng, 1));
-    int32_t* d_il = W.take<int32_t>(std::max(nint, 1));
-    int32_t* d_ig0 = W.take<int32_t>(std::max(nint, 1));
-    int32_t* d_ing = W.take<int32_t>(std::max(nint, 1));
-    int32_t* d_tdeg = W.take<int32_t>(std::max(nint, 1));
-    uint32_t* d_maxlen = W.take<uint32_t>(1);
+            (size_t)(nsk + 1) * 8 * 2 + (size_t)nR * 8 + (size_t)nsk * 8 + (size_t)ng * sizeof(DskInfo) +
+            (size_t)ng * sizeof(GroupDesc) + (size_t)nint * 16 + 64 * 256;
+    return need;
+}
+
+size_t SkBuild::skeleton_bytes_bound() const {
+    const int64_t M = nR + clique_pairs, T = table_pairs;
+    return (size_t)(nsk + 1) * 8 + (size_t)M * (4 + 4 + 8 + 8) + (size_t)nsk + (size_t)(nint + 1) * 8 +
+           (size_t)T * (4 + 4 + 8) + (size_t)nsk * 4 + (size_t)nint * 4 + (size_t)n * 5 + 32 * 256;
+}
+
+int SkBuild::upload(Arena& W, hipStream_t s) {
+    const int32_t ng = (int32_t)groups.size();
+    d_irp = W.take<int64_t>(n + 1);
+    d_icol = W.take<int32_t>(std::max<size_t>(icol.size(), 1));
+    d_iw = weighted ? W.take<uint32_t>(std::max<size_t>(iw.size(), 1)) : nullptr;
+    d_blk = W.take<uint8_t>(std::max(n, 1));
+    d_rptr = W.take<int64_t>(nsk + 1);
+    d_rcol = W.take<int32_t>(std::max<int64_t>(nR, 1));
+    d_rw = W.take<uint32_t>(std::max<int64_t>(nR, 1));
+    d_rdeg = W.take<int32_t>(std::max(nsk, 1));
+    d_cdeg = W.take<int32_t>(std::max(nsk, 1));
+    d_info = W.take<DskInfo>(std::max(ng, 1));
+    d_il = W.take<int32_t>(std::max(nint, 1));
+    d_ig0 = W.take<int32_t>(std::max(nint, 1));
+    d_ing = W.take<int32_t>(std::max(nint, 1));
+    d_tdeg = W.take<int32_t>(std::max(nint, 1));
+    d_maxlen = W.take<uint32_t>(1);
+    d_desc = W.take<GroupDesc>(std::max(ng, 1));
     if (!d_irp || !d_icol || !d_blk || !d_rptr || !d_rcol || !d_rw || !d_rdeg || !d_cdeg || !d_info ||
-        !d_il || !d_ig0 || !d_ing || !d_tdeg || (wt && !d_iw))
+        !d_il || !d_ig0 || !d_ing || !d_tdeg || !d_maxlen || !d_desc || (weighted && !d_iw))
         return fail(BC_E_NOMEM, "partition: workspace too small");
+    for (auto& G : groups) {
+        G.g.row_ptr = d_irp;
+        G.g.col = d_icol;
+        G.g.len = d_iw;
+        G.g.nflag = d_blk;
+        if (!group_alloc(W, G, 0)) return fail(BC_E_NOMEM, "partition: group state does not fit");
+    }
     std::vector<uint8_t> blk(n);
     for (int32_t r = 0; r < n; ++r) blk[r] = fr[old[r]] ? (uint8_t)NF_BLOCKED : 0;
     std::vector<int32_t> rdeg(nsk);
@@ -341,63 +350,58 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
         if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s));
         return BC_OK;
     };
-    BC_TRY(h2d(d_irp, irp.data(), (n + 1) * 8));
+    BC_TRY(h2d(d_irp, irp.data(), (size_t)(n + 1) * 8));
     BC_TRY(h2d(d_icol, icol.data(), icol.size() * 4));
-    if (wt) BC_TRY(h2d(d_iw, iw.data(), iw.size() * 4));
+    if (weighted) BC_TRY(h2d(d_iw, iw.data(), iw.size() * 4));
     BC_TRY(h2d(d_blk, blk.data(), n));
-    BC_TRY(h2d(d_rptr, rptr.data(), (nsk + 1) * 8));
-    BC_TRY(h2d(d_rcol, rcol.data(), nR * 4));
-    BC_TRY(h2d(d_rw, rw.data(), nR * 4));
-    BC_TRY(h2d(d_rdeg, rdeg.data(), nsk * 4));
-    BC_TRY(h2d(d_info, info.data(), ng * sizeof(DskInfo)));
-    BC_TRY(h2d(d_il, int_local.data(), nint * 4));
-    BC_TRY(h2d(d_ig0, int_g0.data(), nint * 4));
-    BC_TRY(h2d(d_ing, int_ng.data(), nint * 4));
+    BC_TRY(h2d(d_rptr, rptr.data(), (size_t)(nsk + 1) * 8));
+    BC_TRY(h2d(d_rcol, rcol.data(), (size_t)nR * 4));
+    BC_TRY(h2d(d_rw, rw.data(), (size_t)nR * 4));
+    BC_TRY(h2d(d_rdeg, rdeg.data(), (size_t)nsk * 4));
+    BC_TRY(h2d(d_info, info.data(), (size_t)ng * sizeof(DskInfo)));
+    BC_TRY(h2d(d_il, int_local.data(), (size_t)nint * 4));
+    BC_TRY(h2d(d_ig0, int_g0.data(), (size_t)nint * 4));
+    BC_TRY(h2d(d_ing, int_ng.data(), (size_t)nint * 4));
+    BC_TRY(h2d(d_desc, groups.data(), (size_t)ng * sizeof(GroupDesc)));
     if (nsk) BC_HIP(hipMemsetAsync(d_cdeg, 0, (size_t)nsk * 4, s));
     BC_HIP(hipMemsetAsync(d_maxlen, 0, 4, s));
+    // the host copies above are staged by the runtime; wait so the caller may reuse them
+    BC_HIP(hipStreamSynchronize(s));
+    return BC_OK;
+}
 
-    for (auto& G : groups) {
-        G.g.row_ptr = d_irp;
-        G.g.col = d_icol;
-        G.g.len = d_iw;
-        G.g.nflag = d_blk;
-    }
-    GroupDesc* d_desc = nullptr;
+int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
+                      const std::function<int(size_t, Arena*&)>& get_store) {
+    (void)W;
+    const int32_t ng = (int32_t)groups.size();
     if (ng > 0) {
-        // Dijkstra_SK from every frontier of every part, all parts in one engine run
-        BC_TRY(run_groups(W, s, groups, 0));
-        d_desc = W.take<GroupDesc>(ng);
-        if (!d_desc) return fail(BC_E_NOMEM, "partition: workspace too small");
-        BC_TRY(h2d(d_desc, groups.data(), ng * sizeof(GroupDesc)));
-        {
-            KTimer kt(BC_K_OTHER, s);
-            hipLaunchKernelGGL(k_clique_count, dim3((ng + 3) / 4), dim3(256), 0, s, d_desc, d_info, ng,
-                               d_cdeg);
-            if (nint)
-                hipLaunchKernelGGL(k_table, dim3((nint + 3) / 4), dim3(256), 0, s, d_desc, d_info, nint,
-                                   d_il, d_ig0, d_ing, d_tdeg, nullptr, nullptr, nullptr, nullptr);
-        }
-        BC_HIP(hipGetLastError());
+        KTimer kt(BC_K_OTHER, s);
+        hipLaunchKernelGGL(k_clique_count, dim3((ng + 3) / 4), dim3(256), 0, s, d_desc, d_info, ng, d_cdeg);
+        if (nint)
+            hipLaunchKernelGGL(k_table, dim3((nint + 3) / 4), dim3(256), 0, s, d_desc, d_info, nint, d_il,
+                               d_ig0, d_ing, d_tdeg, nullptr, nullptr, nullptr, nullptr);
     }
+    BC_HIP(hipGetLastError());
     std::vector<int32_t> cdeg(nsk, 0), tdeg(nint, 0);
     if (nsk) BC_HIP(hipMemcpyAsync(cdeg.data(), d_cdeg, (size_t)nsk * 4, hipMemcpyDeviceToHost, s));
-    if (nint) BC_HIP(hipMemcpyAsync(tdeg.data(), d_tdeg, (size_t)nint * 4, hipMemcpyDeviceToHost, s));
+    if (nint && ng) BC_HIP(hipMemcpyAsync(tdeg.data(), d_tdeg, (size_t)nint * 4, hipMemcpyDeviceToHost, s));
     BC_HIP(hipStreamSynchronize(s));
     std::vector<int64_t> srow(nsk + 1, 0), trow(nint + 1, 0);
     int64_t ncl = 0;
     for (int32_t f = 0; f < nsk; ++f) {
-        srow[f + 1] = srow[f] + rdeg[f] + cdeg[f];
+        srow[f + 1] = srow[f] + (rptr[f + 1] - rptr[f]) + cdeg[f];
         ncl += cdeg[f];
     }
     for (int32_t i = 0; i < nint; ++i) trow[i + 1] = trow[i] + tdeg[i];
     const int64_t M = srow[nsk], T = trow[nint];
 
     // ---- the skeleton's own store
-    size_t sbytes = (size_t)(nsk + 1) * 8 + (size_t)M * (4 + 4 + 8 + 8) + (size_t)nsk +
-                    (size_t)(nint + 1) * 8 + (size_t)T * (4 + 4 + 8) + (size_t)nsk * 4 +
-                    (size_t)nint * 4 + (size_t)n * 5 + 32 * 256;
-    BC_TRY(sk->store.reserve(sbytes));
-    Arena& A = sk->store;
+    const size_t sbytes = (size_t)(nsk + 1) * 8 + (size_t)M * (4 + 4 + 8 + 8) + (size_t)nsk +
+                          (size_t)(nint + 1) * 8 + (size_t)T * (4 + 4 + 8) + (size_t)nsk * 4 +
+                          (size_t)nint * 4 + (size_t)n * 5 + 32 * 256;
+    Arena* Ap = nullptr;
+    BC_TRY(get_store(sbytes, Ap));
+    Arena& A = *Ap;
     sk->d_row_ptr = A.take<int64_t>(nsk + 1);
     sk->d_col = A.take<int32_t>(std::max<int64_t>(M, 1));
     sk->d_len = A.take<uint32_t>(std::max<int64_t>(M, 1));
@@ -413,6 +417,7 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     sk->d_out_idx = A.take<int32_t>(std::max(n, 1));
     sk->d_out_which = A.take<uint8_t>(std::max(n, 1));
     if (!sk->d_out_which) return fail(BC_E_NOMEM, "skeleton store too small");
+    auto skid = [&](int32_t v) -> int32_t { return (int32_t)(fbase[lab[v]] + (nid[v] - poff[lab[v]])); };
     std::vector<uint8_t> sflag(nsk, 0);
     std::vector<int32_t> nodes(nsk);
     for (int32_t r = 0; r < n; ++r) {
@@ -422,29 +427,32 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
         nodes[f] = v;
         if (is_t[v]) sflag[f] = (uint8_t)NF_TARGET;
     }
-    BC_TRY(h2d(sk->d_row_ptr, srow.data(), (nsk + 1) * 8));
-    BC_TRY(h2d(sk->d_trow, trow.data(), (nint + 1) * 8));
+    auto h2d = [&](void* d, const void* h, size_t b) -> int {
+        if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s));
+        return BC_OK;
+    };
+    BC_TRY(h2d(sk->d_row_ptr, srow.data(), (size_t)(nsk + 1) * 8));
+    BC_TRY(h2d(sk->d_trow, trow.data(), (size_t)(nint + 1) * 8));
     BC_TRY(h2d(sk->d_nflag, sflag.data(), nsk));
-    BC_TRY(h2d(sk->d_nodes, nodes.data(), nsk * 4));
-    BC_TRY(h2d(sk->d_tnode, int_node.data(), nint * 4));
-    BC_TRY(h2d(sk->d_out_idx, out_idx.data(), n * 4));
+    BC_TRY(h2d(sk->d_nodes, nodes.data(), (size_t)nsk * 4));
+    BC_TRY(h2d(sk->d_tnode, int_node.data(), (size_t)nint * 4));
+    BC_TRY(h2d(sk->d_out_idx, out_idx.data(), (size_t)n * 4));
     BC_TRY(h2d(sk->d_out_which, out_which.data(), n));
     {
         KTimer kt(BC_K_OTHER, s);
         if (nsk)
-            hipLaunchKernelGGL(k_fill_r, dim3((nsk + 255) / 256), dim3(256), 0, s, nsk, d_rptr, d_rcol,
-                               d_rw, sk->d_row_ptr, sk->d_col, sk->d_len, sk->d_mult);
+            hipLaunchKernelGGL(k_fill_r, dim3((nsk + 255) / 256), dim3(256), 0, s, nsk, d_rptr, d_rcol, d_rw,
+                               sk->d_row_ptr, sk->d_col, sk->d_len, sk->d_mult);
         if (ng) {
             hipLaunchKernelGGL(k_clique_fill, dim3((ng + 3) / 4), dim3(256), 0, s, d_desc, d_info, ng,
                                sk->d_row_ptr, d_rdeg, sk->d_col, sk->d_len, sk->d_mult, d_maxlen);
             if (nint)
-                hipLaunchKernelGGL(k_table, dim3((nint + 3) / 4), dim3(256), 0, s, d_desc, d_info, nint,
-                                   d_il, d_ig0, d_ing, nullptr, sk->d_trow, sk->d_tcol, sk->d_tlen,
-                                   sk->d_tsig);
+                hipLaunchKernelGGL(k_table, dim3((nint + 3) / 4), dim3(256), 0, s, d_desc, d_info, nint, d_il,
+                                   d_ig0, d_ing, nullptr, sk->d_trow, sk->d_tcol, sk->d_tlen, sk->d_tsig);
         }
         if (nsk)
-            hipLaunchKernelGGL(k_sk_twin, dim3((nsk + 3) / 4), dim3(256), 0, s, nsk, sk->d_row_ptr,
-                               d_rdeg, sk->d_col, sk->d_twin);
+            hipLaunchKernelGGL(k_sk_twin, dim3((nsk + 3) / 4), dim3(256), 0, s, nsk, sk->d_row_ptr, d_rdeg,
+                               sk->d_col, sk->d_twin);
     }
     BC_HIP(hipGetLastError());
     uint32_t clique_max = 0;
@@ -452,14 +460,17 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     BC_HIP(hipStreamSynchronize(s));
     uint32_t rmax = 1;
     for (uint32_t x : rw) rmax = std::max(rmax, x);
-    sk->max_len = (int32_t)std::max(rmax, clique_max);
 
+    sk->graph = g;
+    sk->n = n;
+    sk->max_len = (int32_t)std::max(rmax, clique_max);
     // Brandes_SK sources: targets that have a neighbour (isolated targets reach nobody)
-    for (int32_t i = 0; i < nS; ++i)
-        if (fr[S[i]]) sk->h_src.push_back(skid(S[i]));
+    sk->h_src.clear();
+    for (int32_t v : S)
+        if (fr[v]) sk->h_src.push_back(skid(v));
     sk->h_row_ptr = srow;
-    sk->h_out_idx = std::move(out_idx);
-    sk->h_out_which = std::move(out_which);
+    sk->h_out_idx = out_idx;
+    sk->h_out_which = out_which;
     sk->n_sk = nsk;
     sk->n_int = nint;
     sk->m_arcs = M;
@@ -478,9 +489,60 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     int64_t dsk = 0;
     for (auto& I : info) dsk += I.nsrc;
     st.dsk_sources = dsk;
-    st.device_bytes = (int64_t)A.used;
+    st.device_bytes = (int64_t)sbytes;
+    return BC_OK;
+}
+
+int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
+                   bc_skeleton** out, bool given_singletons) {
+    SkBuild b;
+    BC_TRY(b.prepare(g, part, k, S, nS, given_singletons));
+    bc_graph* gm = const_cast<bc_graph*>(g);
+    Arena& W = gm->work;
+    hipStream_t s = g->stream;
+    int64_t positions = 0;
+    for (auto& G : b.groups) positions += (int64_t)G.hi - G.lo;
+    BC_TRY(W.reserve(b.temp_bytes() + engine_bytes(std::max<int32_t>((int32_t)b.groups.size(), 1), positions)));
+    BC_TRY(b.upload(W, s));
+    if (!b.groups.empty()) BC_TRY(run_groups_prealloc(W, s, b.groups));
+    auto sk = std::make_unique<bc_skeleton>();
+    BC_TRY(b.assemble(W, s, sk.get(), [&](size_t bytes, Arena*& A) -> int {
+        BC_TRY(sk->store.reserve(bytes));
+        A = &sk->store;
+        return BC_OK;
+    }));
     *out = sk.release();
     return BC_OK;
+}
+
+std::vector<GroupDesc> bsk_groups(const bc_skeleton* sk, const int32_t* src, int32_t nsrc, int32_t lo,
+                                  int32_t hi, int32_t t_lo, int32_t tn) {
+    std::vector<GroupDesc> groups;
+    for (int32_t c = 0; c < nsrc; c += LANES) {
+        GroupDesc D;
+        D.g.row_ptr = sk->d_row_ptr;
+        D.g.col = sk->d_col;
+        D.g.len = sk->d_len;
+        D.g.mult = sk->d_mult;
+        D.g.nflag = sk->d_nflag;
+        D.g.twin = sk->d_twin;
+        D.lo = lo;
+        D.hi = hi;
+        D.arc_lo = sk->h_row_ptr[lo];
+        D.arcs = sk->h_row_ptr[hi] - sk->h_row_ptr[lo];
+        D.ring_len = sk->max_len + 1;
+        D.flags = GF_BACKWARD | (tn ? GF_CENT : 0u);
+        D.trow = sk->d_trow;
+        D.tcol = sk->d_tcol;
+        D.tlen = sk->d_tlen;
+        D.tsig = sk->d_tsig;
+        D.t_lo = tn ? t_lo : 0;
+        D.tn = tn;
+        D.nsrc = std::min(LANES, nsrc - c);
+        for (int l = 0; l < LANES; ++l) D.src[l] = l < D.nsrc ? src[c + l] : -1;
+        groups.push_back(D);
+    }
+    return groups;
 }
 
 // --------------------------------------------------------------- Brandes++ -----
