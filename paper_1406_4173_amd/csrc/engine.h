@@ -124,6 +124,12 @@ struct Engine {
     int setup(Arena& a, hipStream_t s, int32_t slots, int64_t positions);
     // Install groups into slots [first, first + n) and initialise their state.
     int install(const GroupDesc* groups, int32_t first, int32_t n);
+    // Install groups[j] into slot slots[j] (any free slots), initialise their state and
+    // make the slots in `live` the engine's working set. One synchronisation.
+    int install_at(const GroupDesc* groups, const int32_t* slots, int32_t n,
+                   const std::vector<GroupDesc>& host_desc, const std::vector<int32_t>& live);
+    GroupDesc* d_stage = nullptr;  // staging for install_at
+    int32_t* d_stage_slot = nullptr;
     // Rebuild the scan-chunk table from host descriptors of slots [0, nslots).
     int set_chunks(const std::vector<GroupDesc>& host_desc, const std::vector<int32_t>& live);
     // Issue `iters` engine iterations (no host synchronisation).

@@ -36,7 +36,7 @@ namespace bcpp {
 constexpr int WG = 256;  // threads per workgroup
 constexpr int WAVES_PER_WG = WG / 64;
 constexpr int ITEMS_PER_WAVE = 16;  // node items a wave expands into lanes at once
-constexpr int UNR = 4;              // arcs whose loads a lane issues together
+constexpr int UNR = 8;              // arcs whose loads a lane issues together
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
 #pragma unroll
@@ -112,6 +112,29 @@ __global__ void __launch_bounds__(WG) k_init(const GroupDesc* __restrict__ desc,
     }
 }
 
+// Copy staged group descriptors into their slots and reset the slots' dynamic state.
+__global__ void k_scatter_groups(const GroupDesc* __restrict__ stage, const int32_t* __restrict__ slots,
+                                 int32_t n, GroupDesc* __restrict__ desc, GroupDyn* __restrict__ dyn) {
+    const int j = blockIdx.x;
+    if (j >= n) return;
+    const int32_t s = slots[j];
+    const uint32_t* src = (const uint32_t*)(stage + j);
+    uint32_t* dst = (uint32_t*)(desc + s);
+    for (int k = threadIdx.x; k < (int)(sizeof(GroupDesc) / 4); k += blockDim.x) dst[k] = src[k];
+    if (threadIdx.x == 0) {
+        GroupDyn d;
+        d.D = 0;
+        d.phase = PH_FWD;
+        d.nrec = 0;
+        d.rec_i = 0;
+        d.hist_len = 0;
+        d.rec_start = 0;
+        d.nextmin = INF32;
+        d.err = 0;
+        dyn[s] = d;
+    }
+}
+
 // ---------------------------------------------------------------- select -------
 
 // Append node items for the lanes with sel set to list `list` (wave-level compaction).
@@ -177,11 +200,17 @@ __global__ void __launch_bounds__(WG) k_select(const GroupDesc* __restrict__ des
         ring[slot] = 0ull;
         const unsigned long long done1 = done0 | cand;
         G.done[i] = done1;
-        for (int j = 1; j < R; ++j) {
-            if (ring[(slot + j) % R] & ~done1) {
-                next = D + (uint32_t)j;
-                break;
+        // next offered distance: scan the ring in blocks of 8 slots, loads issued together
+        for (int j0 = 1; j0 < R && next == INF32; j0 += 8) {
+            unsigned long long w[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int j = j0 + k;
+                w[k] = j < R ? ring[(slot + j) % R] : 0ull;
             }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (next == INF32 && (w[k] & ~done1)) next = D + (uint32_t)(j0 + k);
         }
         G.nd[i] = next;
     }
@@ -412,12 +441,16 @@ __global__ void __launch_bounds__(WG) k_push(const GroupDesc* __restrict__ desc,
             const int64_t e = e0 + (p - ex);
             const int64_t ur = (int64_t)(G.g.col[e] - G.lo);
             const uint32_t nv = D + (G.g.len ? G.g.len[e] : 1u);
-            const unsigned long long open = amask & ~G.done[ur];
+            const int R = G.ring_len;
+            unsigned long long* slot = (unsigned long long*)&G.ring[ur * R + nv % (uint32_t)R];
+            // the three reads do not depend on each other: issue them together
+            const unsigned long long dn = G.done[ur];
+            const unsigned long long cur = *slot;
+            const uint32_t ndu = G.nd[ur];
+            const unsigned long long open = amask & ~dn;
             if (open) {
-                const int R = G.ring_len;
-                unsigned long long* slot = (unsigned long long*)&G.ring[ur * R + nv % (uint32_t)R];
-                if (open & ~*slot) atomicOr(slot, open);
-                if (G.nd[ur] > nv) {
+                if (open & ~cur) atomicOr(slot, open);
+                if (ndu > nv) {
                     if (G.flags & GF_UNIT)
                         G.nd[ur] = nv;  // every writer of this step stores D + 1
                     else
@@ -720,7 +753,7 @@ bool group_alloc(Arena& a, GroupDesc& G, int64_t max_steps) {
 
 size_t engine_bytes(int32_t slots, int64_t positions) {
     const int64_t chunks = (positions + WG - 1) / WG + slots;
-    return (size_t)slots * (sizeof(GroupDesc) + sizeof(GroupDyn) + 512) + (size_t)chunks * 8 +
+    return (size_t)slots * (2 * sizeof(GroupDesc) + sizeof(GroupDyn) + 1024) + (size_t)chunks * 8 +
            (size_t)chunks * WG * 3 * sizeof(NodeItem) + 8192;
 }
 
@@ -735,7 +768,9 @@ int Engine::setup(Arena& a, hipStream_t s, int32_t slots, int64_t positions) {
     d_chunk_off = a.take<int32_t>(chunk_cap);
     d_wl = a.take<NodeItem>(3 * wl_cap);
     d_ctr = a.take<uint32_t>(8);
-    if (!d_desc || !d_dyn || !d_chunk_g || !d_chunk_off || !d_wl || !d_ctr)
+    d_stage = a.take<GroupDesc>(slots);
+    d_stage_slot = a.take<int32_t>(slots);
+    if (!d_desc || !d_dyn || !d_chunk_g || !d_chunk_off || !d_wl || !d_ctr || !d_stage || !d_stage_slot)
         return fail(BC_E_NOMEM, "engine: workspace too small");
     if (!h_ctr) BC_HIP(hipHostMalloc((void**)&h_ctr, 8 * sizeof(uint32_t)));
     BC_HIP(hipMemsetAsync(d_ctr, 0, 8 * sizeof(uint32_t), stream));
@@ -813,6 +848,38 @@ int Engine::install(const GroupDesc* groups, int32_t first, int32_t n) {
     BC_HIP(hipMemcpyAsync(d_ctr + 3, h_ctr + 3, sizeof(uint32_t), hipMemcpyHostToDevice, stream));
     BC_HIP(hipStreamSynchronize(stream));
     return BC_OK;
+}
+
+int Engine::install_at(const GroupDesc* groups, const int32_t* slots, int32_t n,
+                       const std::vector<GroupDesc>& host_desc, const std::vector<int32_t>& live) {
+    if (n > 0) {
+        if (n > cap) return fail(BC_E_NOMEM, "engine: too many groups to install");
+        BC_HIP(hipMemcpyAsync(d_stage, groups, sizeof(GroupDesc) * n, hipMemcpyHostToDevice, stream));
+        BC_HIP(hipMemcpyAsync(d_stage_slot, slots, sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(k_scatter_groups, dim3(n), dim3(128), 0, stream, d_stage, d_stage_slot, n,
+                           d_desc, d_dyn);
+        BC_HIP(hipGetLastError());
+        std::vector<int32_t> cg, co;
+        for (int32_t j = 0; j < n; ++j) {
+            const GroupDesc& G = groups[j];
+            int64_t pos = std::max<int64_t>((int64_t)G.hi - G.lo, (G.flags & GF_CENT) ? G.tn : 0);
+            for (int64_t off = 0; off < pos; off += WG) {
+                cg.push_back(slots[j]);
+                co.push_back((int32_t)off);
+            }
+        }
+        if ((int64_t)cg.size() > chunk_cap) return fail(BC_E_NOMEM, "engine: too many init chunks");
+        if (!cg.empty()) {
+            BC_HIP(hipMemcpyAsync(d_chunk_g, cg.data(), cg.size() * 4, hipMemcpyHostToDevice, stream));
+            BC_HIP(hipMemcpyAsync(d_chunk_off, co.data(), co.size() * 4, hipMemcpyHostToDevice, stream));
+            KTimer kt(BC_K_OTHER, stream);
+            hipLaunchKernelGGL(k_init, dim3((unsigned)cg.size()), dim3(WG), 0, stream, d_desc, d_chunk_g,
+                               d_chunk_off, (int64_t)cg.size());
+        }
+        BC_HIP(hipGetLastError());
+        BC_HIP(hipStreamSynchronize(stream));  // the staged host arrays are reused after this
+    }
+    return set_chunks(host_desc, live);
 }
 
 int Engine::iterate(int iters) {

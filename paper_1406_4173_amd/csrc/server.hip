@@ -133,7 +133,11 @@ struct bc_server {
     std::vector<GroupDesc> slot_desc;
     std::vector<uint64_t> slot_owner;  // ticket, 0 = free
     GroupDyn* h_dyn = nullptr;
+    int32_t slot_hi = 0;  // slots [slot_hi, slot_cap) have never been used
     int run_error = BC_OK;
+    // host preparation of queries (P', renumbering) runs on its own thread
+    std::thread prep_th;
+    std::deque<uint64_t> prepared;
 
     ~bc_server();
 };
@@ -178,13 +182,14 @@ static int install_groups(bc_server* sv, Query* q) {
         sv->slot_desc[at] = G;
         q->slots.push_back(at);
         sv->pos_used += positions_of(G);
-        BC_TRY(sv->eng.install(&G, at, 1));
+        sv->slot_hi = std::max(sv->slot_hi, at + 1);
         ++at;
     }
     std::vector<int32_t> live;
-    for (int32_t i = 0; i < sv->slot_cap; ++i)
+    for (int32_t i = 0; i < sv->slot_hi; ++i)
         if (sv->slot_owner[i]) live.push_back(i);
-    return sv->eng.set_chunks(sv->slot_desc, live);
+    return sv->eng.install_at(q->groups.data(), q->slots.data(), (int32_t)q->groups.size(), sv->slot_desc,
+                              live);
 }
 
 static void release_slots(bc_server* sv, Query* q) {
@@ -255,12 +260,15 @@ static int start_bsk(bc_server* sv, Query* q, bool* started) {
     }
     q->groups = bsk_groups(sk, sk->h_src.data(), nsrc, 0, sk->n_sk, 0, sk->n_int);
     const int64_t steps = max_steps_bound(sk->n_sk, LANES, sk->max_dist);
-    size_t need = (size_t)n * 8 + 2 * q->groups.size() * 8 + (size_t)q->groups.size() * 8 + 4096;
+    // group states, then finish_bsk's chunk table, score vector and reduction pointers
+    size_t need = 0, chunks = 0;
     int64_t pos = 0;
     for (auto& G : q->groups) {
         need += group_bytes(G, steps) + 512;
         pos += positions_of(G);
+        chunks += ((size_t)(G.hi - G.lo) + 255) / 256;
     }
+    need += 2 * (chunks * 4 + 256) + (size_t)n * 8 + 256 + 2 * (q->groups.size() * 8 + 256) + 4096;
     if (need > sv->pool.cap || (int32_t)q->groups.size() > sv->slot_cap || pos > sv->pos_cap)
         return fail(BC_E_NOMEM, "server: query needs more than the configured budget");
     if ((int32_t)q->groups.size() > free_slots(sv) || sv->pos_used + pos > sv->pos_cap ||
@@ -313,12 +321,7 @@ static int finish_bsk(bc_server* sv, Query* q) {
 }
 
 static int admit(bc_server* sv, Query* q) {
-    if (!q->build) {
-        q->build = std::make_unique<SkBuild>();
-        const bc_graph* g = sv->graphs[q->gid].get();
-        BC_TRY(q->build->prepare(g, sv->parts[q->gid].data(), sv->ks[q->gid], q->S.data(),
-                                 (int32_t)q->S.size(), false));
-    }
+    if (!q->build) return fail(BC_E_DEVICE, "server: query was not prepared");
     SkBuild& b = *q->build;
     q->groups = b.groups;
     const size_t need = b.temp_bytes() + 4096;
@@ -338,6 +341,45 @@ static int admit(bc_server* sv, Query* q) {
     return BC_OK;
 }
 
+// Host preparation thread: P', frontiers, renumbering and the Dijkstra_SK groups of
+// each submitted query, so that the device loop never waits on it.
+static void prep_loop(bc_server* sv) {
+    for (;;) {
+        uint64_t ticket = 0;
+        Query* q = nullptr;
+        const bc_graph* g = nullptr;
+        const int32_t* part = nullptr;
+        int32_t k = 0;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv.wait(lk, [&] { return sv->stop || !sv->incoming.empty(); });
+            if (sv->stop) return;
+            ticket = sv->incoming.front();
+            sv->incoming.pop_front();
+            auto it = sv->queries.find(ticket);
+            if (it == sv->queries.end()) continue;
+            q = it->second.get();
+            // graph objects and partition buffers never move once registered
+            g = sv->graphs[q->gid].get();
+            part = sv->parts[q->gid].data();
+            k = sv->ks[q->gid];
+        }
+        auto b = std::make_unique<SkBuild>();
+        const int rc = b->prepare(g, part, k, q->S.data(), (int32_t)q->S.size(), false);
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (rc != BC_OK) {
+            q->state = Q_FAILED;
+            q->status = rc;
+            q->err = bc_last_error();
+            sv->n_failed++;
+            continue;
+        }
+        q->build = std::move(b);
+        sv->prepared.push_back(ticket);
+        sv->cv.notify_all();
+    }
+}
+
 static void server_loop(bc_server* sv) {
     (void)hipSetDevice(sv->device);
     std::vector<Query*> active;     // admitted, not finished
@@ -346,12 +388,12 @@ static void server_loop(bc_server* sv) {
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            if (active.empty() && waiting.empty() && bsk_wait.empty() && sv->incoming.empty() && !sv->stop)
+            if (active.empty() && waiting.empty() && bsk_wait.empty() && sv->prepared.empty() && !sv->stop)
                 sv->cv.wait_for(lk, std::chrono::milliseconds(20));
             if (sv->stop) break;
-            while (!sv->incoming.empty()) {
-                auto it = sv->queries.find(sv->incoming.front());
-                sv->incoming.pop_front();
+            while (!sv->prepared.empty()) {
+                auto it = sv->queries.find(sv->prepared.front());
+                sv->prepared.pop_front();
                 if (it != sv->queries.end()) waiting.push_back(it->second.get());
             }
         }
@@ -384,15 +426,15 @@ static void server_loop(bc_server* sv) {
         }
         if (active.empty()) continue;
         // one engine step for every installed group of every admitted query
-        if (sv->eng.iterate(1) != BC_OK ||
-            hipMemcpyAsync(sv->h_dyn, sv->eng.d_dyn, sizeof(GroupDyn) * sv->slot_cap, hipMemcpyDeviceToHost,
-                           sv->stream) != hipSuccess ||
+        if (sv->eng.iterate(2) != BC_OK ||
+            hipMemcpyAsync(sv->h_dyn, sv->eng.d_dyn, sizeof(GroupDyn) * std::max(sv->slot_hi, 1),
+                           hipMemcpyDeviceToHost, sv->stream) != hipSuccess ||
             hipStreamSynchronize(sv->stream) != hipSuccess) {
             for (Query* q : active) fail_query(sv, q, BC_E_DEVICE, "server: device step failed");
             active.clear();
             continue;
         }
-        sv->n_iters++;
+        sv->n_iters += 2;
         // queries that start Brandes_SK below are checked from the next step on: the
         // phase snapshot read above predates their groups
         std::vector<Query*> started_now;
@@ -452,6 +494,7 @@ bc_server::~bc_server() {
     }
     cv.notify_all();
     if (th.joinable()) th.join();
+    if (prep_th.joinable()) prep_th.join();
     if (stream) (void)hipStreamSynchronize(stream);
     engine_mem.release();
     if (d_pool) (void)hipFree(d_pool);
@@ -495,6 +538,7 @@ int bc_server_create(size_t hbm_budget_bytes, int32_t max_inflight, bc_server** 
     sv->pool.init(sv->d_pool, hbm_budget_bytes);
     bc_server* raw = sv.get();
     sv->th = std::thread([raw] { server_loop(raw); });
+    sv->prep_th = std::thread([raw] { prep_loop(raw); });
     *out = sv.release();
     return BC_OK;
 }
