@@ -54,6 +54,11 @@ typedef enum bc_status {
 
 /* flags */
 #define BC_ORDERED 0x1u    /* ordered-pair sum: 2x the default unordered score */
+/* Run every traversal on the multi-group engine (64 sources per wave, state in HBM),
+ * also where the graph (or skeleton) is small enough for the LDS-resident kernel
+ * (one source at a time per workgroup, its state in LDS), which is used otherwise.
+ * Both compute the same d and sigma; scores agree within the stated tolerance. */
+#define BC_ENGINE_ONLY 0x2u
 
 typedef struct bc_csr {
     int32_t n;              /* nodes */
@@ -205,7 +210,10 @@ void bc_server_destroy(bc_server* s);
 #define BC_K_CENTRALITY 4
 #define BC_K_SCHED 5
 #define BC_K_OTHER 6
-#define BC_K_COUNT 7
+#define BC_K_RESIDENT 7 /* the LDS-resident kernel: 32 bytes per (source, arc) and 20 per
+                         * (source, node) reached, the per-source state a traversal from
+                         * memory would move (Sec. 3 forward and backward sweeps) */
+#define BC_K_COUNT 8
 void bc_profile_enable(int on);
 /* Totals since the last reset: launches, summed milliseconds, and the algorithmic
  * bytes the kernel's work units account for (see the kernel's documentation). */

@@ -17,9 +17,10 @@ LIB_PATH = os.path.join(HERE, "libbcpp.so")
 
 BC_OK, BC_E_INVAL, BC_E_OVERFLOW, BC_E_NOMEM, BC_E_DEVICE, BC_E_AGAIN, BC_E_NOTFOUND = range(7)
 BC_ORDERED = 0x1
+BC_ENGINE_ONLY = 0x2
 BC_BATCH_PLAIN = 0x0
 BC_BATCH_PP = 0x100
-KERNELS = ["select", "settle", "push", "backward", "centrality", "sched", "other"]
+KERNELS = ["select", "settle", "push", "backward", "centrality", "sched", "other", "resident"]
 
 _P = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -167,17 +168,21 @@ def sssp_counts(G: Graph, src):
     return d, sig
 
 
-def brandes_plain(G: Graph, S, ordered: bool = False):
+def _flags(ordered: bool, engine_only: bool) -> int:
+    return (BC_ORDERED if ordered else 0) | (BC_ENGINE_ONLY if engine_only else 0)
+
+
+def brandes_plain(G: Graph, S, ordered: bool = False, engine_only: bool = False):
     S = _i32a(S)
     out = np.empty(G.n, np.float64)
-    _check(lib().bc_brandes_plain(G.h, _p(S), S.size, BC_ORDERED if ordered else 0, _p(out)))
+    _check(lib().bc_brandes_plain(G.h, _p(S), S.size, _flags(ordered, engine_only), _p(out)))
     return out
 
 
-def brandes_plain_dev(G: Graph, S_dev, out_dev, ordered: bool = False):
+def brandes_plain_dev(G: Graph, S_dev, out_dev, ordered: bool = False, engine_only: bool = False):
     """S_dev: int32 device tensor; out_dev: float64 device tensor of G.n entries."""
     _check(lib().bc_brandes_plain_dev(G.h, ctypes.c_void_p(S_dev.data_ptr()), S_dev.numel(),
-                                      BC_ORDERED if ordered else 0,
+                                      _flags(ordered, engine_only),
                                       ctypes.c_void_p(out_dev.data_ptr())))
     return out_dev
 
@@ -246,14 +251,15 @@ def partition_sk(G: Graph, part, k: int, S) -> Skeleton:
     return Skeleton(G, part, k, S)
 
 
-def brandes_pp(G: Graph, sk: Skeleton, ordered: bool = False):
+def brandes_pp(G: Graph, sk: Skeleton, ordered: bool = False, engine_only: bool = False):
     out = np.empty(G.n, np.float64)
-    _check(lib().bc_brandes_pp(G.h, sk.h, BC_ORDERED if ordered else 0, _p(out)))
+    _check(lib().bc_brandes_pp(G.h, sk.h, _flags(ordered, engine_only), _p(out)))
     return out
 
 
-def brandes_pp_dev(G: Graph, sk: Skeleton, out_dev, ordered: bool = False):
-    _check(lib().bc_brandes_pp_dev(G.h, sk.h, BC_ORDERED if ordered else 0,
+def brandes_pp_dev(G: Graph, sk: Skeleton, out_dev, ordered: bool = False,
+                   engine_only: bool = False):
+    _check(lib().bc_brandes_pp_dev(G.h, sk.h, _flags(ordered, engine_only),
                                    ctypes.c_void_p(out_dev.data_ptr())))
     return out_dev
 
@@ -281,11 +287,11 @@ class Batch:
                                      ctypes.byref(h)))
         self.h = h
 
-    def run(self, pp: bool = True):
+    def run(self, pp: bool = True, engine_only: bool = False):
         outs = [np.empty(n, np.float64) for n in self.ns]
         ptrs = (ctypes.c_void_p * len(outs))(*[o.ctypes.data for o in outs])
-        _check(lib().bc_batch_run(self.h, BC_BATCH_PP if pp else BC_BATCH_PLAIN,
-                                  ctypes.cast(ptrs, _P)))
+        fl = (BC_BATCH_PP if pp else BC_BATCH_PLAIN) | (BC_ENGINE_ONLY if engine_only else 0)
+        _check(lib().bc_batch_run(self.h, fl, ctypes.cast(ptrs, _P)))
         return outs
 
     def close(self):

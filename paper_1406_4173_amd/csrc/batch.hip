@@ -27,20 +27,61 @@ struct bc_batch {
 
 namespace bcpp {
 
-static int batch_plain(bc_batch* b, double* d_out) {
+// Run a list of groups of which some (resident[i]) go to the LDS-resident kernel and
+// the rest to the engine; the score pointers end up in groups[i] either way, so the
+// list keeps its order (each graph's groups contiguous) for the reduction.
+static int run_mixed(Arena& W, hipStream_t s, std::vector<GroupDesc>& groups,
+                     const std::vector<uint8_t>& resident, int64_t steps) {
+    std::vector<GroupDesc> E, R;
+    for (size_t i = 0; i < groups.size(); ++i) (resident[i] ? R : E).push_back(groups[i]);
+    for (GroupDesc& D : R)
+        if (!resident_alloc(W, D)) return fail(BC_E_NOMEM, "batch: workspace too small");
+    if (!R.empty()) BC_TRY(run_resident(s, W, R));
+    if (!E.empty()) BC_TRY(run_groups(W, s, E, steps));
+    size_t e = 0, r = 0;
+    for (size_t i = 0; i < groups.size(); ++i) groups[i] = resident[i] ? R[r++] : E[e++];
+    return BC_OK;
+}
+
+// Workspace of the groups of run_mixed.
+static size_t mixed_bytes(const std::vector<GroupDesc>& groups, const std::vector<uint8_t>& resident,
+                          int64_t steps) {
+    size_t need = 0, nres = 0, neng = 0;
+    int64_t positions = 0;
+    for (size_t i = 0; i < groups.size(); ++i) {
+        const GroupDesc& D = groups[i];
+        if (resident[i]) {
+            need += resident_group_bytes(D);
+            ++nres;
+        } else {
+            need += group_bytes(D, steps);
+            positions += std::max<int64_t>((int64_t)D.hi - D.lo, (D.flags & GF_CENT) ? D.tn : 0);
+            ++neng;
+        }
+    }
+    if (nres) need += resident_launch_bytes(nres);
+    if (neng) need += engine_bytes((int32_t)neng, positions);
+    return need;
+}
+
+static int batch_plain(bc_batch* b, uint32_t flags, double* d_out) {
     bc_graph* G = b->G;
     hipStream_t s = G->stream;
     const int32_t n = G->n;
     std::vector<GroupDesc> groups;
+    std::vector<uint8_t> resident;
     std::vector<int32_t> g0(n, 0), g1(n, 0), idx(n, -1);
     int64_t steps = 1;
+    const int64_t rmax = (flags & BC_ENGINE_ONLY) ? 0 : resident_max_range();
     for (int32_t gi = 0; gi < b->ng; ++gi) {
         const int32_t lo = b->n_off[gi], hi = b->n_off[gi + 1];
         const int32_t ns = b->s_off[gi + 1] - b->s_off[gi];
         const int32_t first_group = (int32_t)groups.size();
         if (ns >= 2) {
-            steps = std::max(steps, max_steps_bound(hi - lo, LANES, (int64_t)(hi - lo) * G->maxw));
-            for (int32_t c = 0; c < ns; c += LANES) {
+            const bool res = hi - lo <= rmax;
+            const int32_t per = res ? resident_sources_per_group(ns) : LANES;
+            if (!res) steps = std::max(steps, max_steps_bound(hi - lo, LANES, (int64_t)(hi - lo) * G->maxw));
+            for (int32_t c = 0; c < ns; c += per) {
                 GroupDesc D;
                 D.lo = lo;
                 D.hi = hi;
@@ -48,10 +89,11 @@ static int batch_plain(bc_batch* b, double* d_out) {
                 D.arcs = G->h_row_ptr[hi] - G->h_row_ptr[lo];
                 D.ring_len = G->maxw + 1;
                 D.flags = GF_BACKWARD | (G->unit ? GF_UNIT : 0u);
-                D.nsrc = std::min(LANES, ns - c);
+                D.nsrc = std::min(per, ns - c);
                 for (int l = 0; l < LANES; ++l)
                     D.src[l] = l < D.nsrc ? b->S_all[b->s_off[gi] + c + l] : -1;
                 groups.push_back(D);
+                resident.push_back(res ? 1 : 0);
             }
         }
         for (int32_t v = lo; v < hi; ++v) {
@@ -61,14 +103,8 @@ static int batch_plain(bc_batch* b, double* d_out) {
         }
     }
     Arena& W = G->work;
-    size_t need = engine_bytes((int32_t)std::max<size_t>(groups.size(), 1), n) + (size_t)n * 13 +
-                  (size_t)groups.size() * 16 + (1 << 20);
-    int64_t positions = 0;
-    for (auto& D : groups) {
-        need += group_bytes(D, steps);
-        positions += D.hi - D.lo;
-    }
-    need += engine_bytes((int32_t)std::max<size_t>(groups.size(), 1), positions);
+    const size_t need = mixed_bytes(groups, resident, steps) + (size_t)n * 13 +
+                        (size_t)groups.size() * 16 + (1 << 20);
     BC_TRY(W.reserve(need));
     uint8_t* d_flag = W.take<uint8_t>(n);
     int32_t* d_g0 = W.take<int32_t>(n);
@@ -88,12 +124,12 @@ static int batch_plain(bc_batch* b, double* d_out) {
         D.g.nflag = d_flag;
         D.g.twin = G->d_twin;
     }
-    BC_TRY(run_groups(W, s, groups, steps));
+    BC_TRY(run_mixed(W, s, groups, resident, steps));
     BC_TRY(reduce_scores(s, W, groups, n, d_g0, d_g1, d_idx, nullptr, 0.5, d_out, false));
     return BC_OK;
 }
 
-static int batch_pp(bc_batch* b, double* d_out) {
+static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
     bc_graph* G = b->G;
     hipStream_t s = G->stream;
     const int32_t n = G->n;
@@ -104,9 +140,11 @@ static int batch_pp(bc_batch* b, double* d_out) {
     const auto& oi = sk->h_out_idx;
     const auto& ow = sk->h_out_which;
     std::vector<GroupDesc> groups;
+    std::vector<uint8_t> resident;
     std::vector<int32_t> g0(n, 0), g1(n, 0), idx(n, -1);
     std::vector<uint8_t> which(n, 0);
     int64_t steps = 1;
+    const int64_t rmax = (flags & BC_ENGINE_ONLY) ? 0 : resident_max_range();
     for (int32_t gi = 0; gi < b->ng; ++gi) {
         const int32_t lo = b->n_off[gi], hi = b->n_off[gi + 1];
         int32_t sk_lo = INT32_MAX, sk_hi = -1, t_lo = INT32_MAX, t_hi = -1;
@@ -129,8 +167,10 @@ static int batch_pp(bc_batch* b, double* d_out) {
         if (src.size() >= 2 && sk_hi > sk_lo) {
             const int32_t N = sk_hi - sk_lo;
             const int32_t tn = t_hi > t_lo ? t_hi - t_lo : 0;
-            steps = std::max(steps, max_steps_bound(N, LANES, (int64_t)(hi - lo) * G->maxw));
-            for (size_t c = 0; c < src.size(); c += LANES) {
+            const bool res = N <= rmax;
+            const size_t per = res ? (size_t)resident_sources_per_group((int64_t)src.size()) : LANES;
+            if (!res) steps = std::max(steps, max_steps_bound(N, LANES, (int64_t)(hi - lo) * G->maxw));
+            for (size_t c = 0; c < src.size(); c += per) {
                 GroupDesc D;
                 D.g.row_ptr = sk->d_row_ptr;
                 D.g.col = sk->d_col;
@@ -150,9 +190,10 @@ static int batch_pp(bc_batch* b, double* d_out) {
                 D.tsig = sk->d_tsig;
                 D.t_lo = tn ? t_lo : 0;
                 D.tn = tn;
-                D.nsrc = (int32_t)std::min<size_t>(LANES, src.size() - c);
+                D.nsrc = (int32_t)std::min<size_t>(per, src.size() - c);
                 for (int l = 0; l < LANES; ++l) D.src[l] = l < D.nsrc ? src[c + l] : -1;
                 groups.push_back(D);
+                resident.push_back(res ? 1 : 0);
             }
         }
         for (int32_t v = lo; v < hi; ++v) {
@@ -165,13 +206,8 @@ static int batch_pp(bc_batch* b, double* d_out) {
         }
     }
     Arena& W = G->work;
-    size_t need = (size_t)n * 13 + (size_t)groups.size() * 16 + (1 << 20);
-    int64_t positions = 0;
-    for (auto& D : groups) {
-        need += group_bytes(D, steps);
-        positions += std::max(D.hi - D.lo, D.tn);
-    }
-    need += engine_bytes((int32_t)std::max<size_t>(groups.size(), 1), positions);
+    const size_t need = mixed_bytes(groups, resident, steps) + (size_t)n * 13 +
+                        (size_t)groups.size() * 16 + (1 << 20);
     BC_TRY(W.reserve(need));
     int32_t* d_g0 = W.take<int32_t>(n);
     int32_t* d_g1 = W.take<int32_t>(n);
@@ -182,7 +218,7 @@ static int batch_pp(bc_batch* b, double* d_out) {
     BC_HIP(hipMemcpyAsync(d_g1, g1.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
     BC_HIP(hipMemcpyAsync(d_idx, idx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
     BC_HIP(hipMemcpyAsync(d_which, which.data(), n, hipMemcpyHostToDevice, s));
-    BC_TRY(run_groups(W, s, groups, steps));
+    BC_TRY(run_mixed(W, s, groups, resident, steps));
     BC_TRY(reduce_scores(s, W, groups, n, d_g0, d_g1, d_idx, d_which, 0.5, d_out, false));
     return BC_OK;
 }
@@ -263,7 +299,7 @@ int bc_batch_run(bc_batch* b, uint32_t flags, double* const* bc_out) {
     if (n == 0) return BC_OK;
     BC_TRY(G->out.reserve((size_t)n * 8 + 256));
     double* d_out = G->out.take<double>(n);
-    BC_TRY((flags & BC_BATCH_PP) ? batch_pp(b, d_out) : batch_plain(b, d_out));
+    BC_TRY((flags & BC_BATCH_PP) ? batch_pp(b, flags, d_out) : batch_plain(b, flags, d_out));
     std::vector<double> all(n);
     BC_HIP(hipMemcpyAsync(all.data(), d_out, (size_t)n * 8, hipMemcpyDeviceToHost, G->stream));
     BC_HIP(hipStreamSynchronize(G->stream));

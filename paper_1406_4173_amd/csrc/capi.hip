@@ -227,6 +227,50 @@ int graph_create(const bc_csr* csr, hipStream_t stream, bc_graph** out) {
 
 // Plain target-set Brandes over g for the host-validated targets S (host copy);
 // S_dev (device copy or null) is used to mark targets. Scores go to out_dev.
+// Plain Brandes with the LDS-resident kernel: groups of resident_sources_per_group(nS)
+// targets over the whole graph.
+int plain_resident(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, double scale,
+                   double* out_dev) {
+    hipStream_t s = g->stream;
+    const int32_t n = g->n;
+    const int32_t spg = resident_sources_per_group(nS);
+    const int32_t ngroups = (nS + spg - 1) / spg;
+    std::vector<GroupDesc> groups(ngroups);
+    size_t need = resident_launch_bytes(ngroups) + (size_t)n + (size_t)nS * 4 + 2 * ((size_t)ngroups * 8 + 256) +
+                  65536;
+    for (int32_t j = 0; j < ngroups; ++j) {
+        GroupDesc& G = groups[j];
+        G.lo = 0;
+        G.hi = n;
+        G.flags = GF_BACKWARD;
+        const int32_t first = j * spg;
+        G.nsrc = std::min(spg, nS - first);
+        for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? S[first + b] : -1;
+        need += resident_group_bytes(G);
+    }
+    BC_TRY(g->work.reserve(need));
+    uint8_t* d_flag = g->work.take<uint8_t>(n);
+    const int32_t* d_S = S_dev;
+    if (!d_S) {
+        int32_t* t = g->work.take<int32_t>(nS);
+        BC_HIP(hipMemcpyAsync(t, S, (size_t)nS * 4, hipMemcpyHostToDevice, s));
+        d_S = t;
+    }
+    BC_HIP(hipMemsetAsync(d_flag, 0, n, s));
+    hipLaunchKernelGGL(k_mark_targets, dim3((nS + 255) / 256), dim3(256), 0, s, d_S, nS, d_flag);
+    BC_HIP(hipGetLastError());
+    for (GroupDesc& G : groups) {
+        G.g.row_ptr = g->d_row_ptr;
+        G.g.col = g->d_col;
+        G.g.len = g->d_len;
+        G.g.nflag = d_flag;
+        if (!resident_alloc(g->work, G)) return fail(BC_E_NOMEM, "plain: workspace too small");
+    }
+    BC_TRY(run_resident(s, g->work, groups));
+    return reduce_scores(s, g->work, groups, n, nullptr, nullptr, nullptr, nullptr, scale, out_dev,
+                         false);
+}
+
 int plain_run(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, uint32_t flags,
               double* out_dev) {
     hipStream_t s = g->stream;
@@ -238,6 +282,8 @@ int plain_run(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, u
         BC_HIP(hipStreamSynchronize(s));
         return BC_OK;
     }
+    if (!(flags & BC_ENGINE_ONLY) && n <= resident_max_range())
+        return plain_resident(g, S, nS, S_dev, scale, out_dev);
     const int64_t max_dist = (int64_t)(n - 1) * g->maxw;
     const int64_t steps = max_steps_bound(n, LANES, max_dist);
     const int32_t ngroups = (nS + LANES - 1) / LANES;

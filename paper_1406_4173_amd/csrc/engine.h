@@ -163,4 +163,22 @@ int reduce_scores(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups,
 namespace bcpp {
 // Device bytes an Engine needs for `slots` groups over `positions` scan positions.
 size_t engine_bytes(int32_t slots, int64_t positions);
+
+// ---- LDS-resident kernel (resident.hip) ----
+// One workgroup per group runs the group's sources one after another with the state
+// of one source (distance and path count of every node of the range) in LDS. Used
+// for groups whose node range fits; fills cacc (and cint for GF_CENT groups). For
+// resident groups, dist and sigma point at [tn] interior scratch instead of per-lane
+// state, and no other engine buffer is used.
+// Largest node range that fits in LDS (0: kernel unavailable or switched off).
+int64_t resident_max_range();
+// Sources per resident group for a source set of nsrc (a function of nsrc only, so a
+// graph is split the same way alone and inside a batch).
+int32_t resident_sources_per_group(int64_t nsrc);
+size_t resident_group_bytes(const GroupDesc& G);
+bool resident_alloc(Arena& a, GroupDesc& G);
+// Workspace run_resident takes from the arena for `ngroups` groups.
+size_t resident_launch_bytes(size_t ngroups);
+// Run the groups to completion (synchronises); BC_E_OVERFLOW if a count reached 2^64.
+int run_resident(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups);
 }  // namespace bcpp

@@ -1,0 +1,463 @@
+// LDS-resident Brandes: one workgroup per group of sources, the group's sources one
+// after another, with the distance and path count of every node of the group's range
+// held in LDS (12 bytes per node: up to about 13,000 nodes in gfx950's 160 KB).
+//
+// For one source s the workgroup runs (Sec. 3 and Sec. 5, Step 2):
+//   forward   distance-synchronous steps D = 0, then the next pending distance: every
+//             node with tentative distance D is settled, pulls sigma(s,v) from its
+//             tight parents (eq. parentsall, or eq. multiparents with multiplicities)
+//             and lowers its neighbours' tentative distances with LDS atomics. Arc
+//             lengths are at least 1, so a node whose tentative distance equals the
+//             current step's D is final, and its parents were settled (and their counts
+//             written) in earlier steps, behind a barrier.
+//   interior  (skeleton groups with tables, Sec. 5, Step 3) d(s,v) and sigma(s,v) of
+//             every interior row from the frontier state.
+//   backward  the same steps in decreasing distance: delta(s|v) = sigma(s,v) * sum over
+//             tight children x of m(v,x) * coef(s,x), coef(s,v) = (I[v in S] + delta(s|v))
+//             / sigma(s,v) (eq. brandes / eq. multibrandes). coef replaces sigma in LDS.
+//   interior  delta(s|v) of the interior rows (eq. localcentrality).
+// A group's node scores (cacc) and interior scores (cint) are owned by its workgroup
+// and accumulated in source order, so results do not depend on what else runs.
+//
+// The graph's CSR is read from global memory; it is small enough to stay in L2 for the
+// graphs this kernel takes, so the only HBM traffic is the first touch of the CSR and
+// the per-group score rows.
+#include <algorithm>
+
+#include "engine.h"
+
+namespace bcpp {
+
+namespace {
+
+constexpr int RUNR = 8;  // arcs whose loads a thread issues together
+
+__device__ __forceinline__ uint32_t wmin_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wmax_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o, 64);
+    return v;
+}
+
+// index of the k-th (0-based) set bit of m; m has more than k set bits
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int k) {
+    int pos = 0;
+    int c = __popc((uint32_t)m);
+    if (k >= c) {
+        k -= c;
+        m >>= 32;
+        pos = 32;
+    }
+    uint32_t w = (uint32_t)m;
+    c = __popc(w & 0xFFFFu);
+    if (k >= c) {
+        k -= c;
+        w >>= 16;
+        pos += 16;
+    }
+    c = __popc(w & 0xFFu);
+    if (k >= c) {
+        k -= c;
+        w >>= 8;
+        pos += 8;
+    }
+    c = __popc(w & 0xFu);
+    if (k >= c) {
+        k -= c;
+        w >>= 4;
+        pos += 4;
+    }
+    c = __popc(w & 0x3u);
+    if (k >= c) {
+        k -= c;
+        w >>= 2;
+        pos += 2;
+    }
+    if (k >= (int)(w & 1u)) pos += 1;
+    return pos;
+}
+
+// Visit the nodes v of [0, n) for which sel(v) holds. Each wave scans 64 consecutive
+// nodes per pass (its share: passes T apart), queues the selected ones in registers
+// (one per lane) and hands every full queue of 64, and the last partial one, to
+// body(v, valid) with all lanes converged. A step that settles few nodes thus costs
+// one round of neighbour loads per wave instead of one per scan pass.
+template <int T, class Sel, class Body>
+__device__ __forceinline__ void for_selected(int32_t n, Sel&& sel, Body&& body) {
+    const int lane = threadIdx.x & 63;
+    int cnt = 0;
+    int32_t q = 0;
+    for (int32_t base = (int32_t)(threadIdx.x & ~63u); base < n; base += T) {
+        const int32_t v = base + lane;
+        const bool hit = v < n && sel(v);
+        const unsigned long long m = __ballot(hit);
+        int avail = __popcll(m), used = 0;
+        while (avail > 0) {
+            const int take = min(64 - cnt, avail);
+            if (lane >= cnt && lane < cnt + take) q = base + nth_set_bit(m, used + lane - cnt);
+            cnt += take;
+            used += take;
+            avail -= take;
+            if (cnt == 64) {
+                body(q, true);
+                cnt = 0;
+            }
+        }
+    }
+    if (cnt > 0) body(q, lane < cnt);
+}
+
+template <int T>
+__global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ desc,
+                                                uint32_t* __restrict__ err,
+                                                unsigned long long* __restrict__ prof) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ uint32_t fwd_next[3];  // rotating: step k writes [k%3], clears [(k+1)%3]
+    __shared__ uint32_t bwd_prev[3];
+    __shared__ uint32_t ovf_flag;
+
+    const GroupDesc& G = desc[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int32_t lo = G.lo;
+    const int32_t n = G.hi - G.lo;
+    uint32_t* __restrict__ dist = reinterpret_cast<uint32_t*>(lds);
+    uint64_t* __restrict__ sig = reinterpret_cast<uint64_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15));
+    const int64_t* __restrict__ rp = G.g.row_ptr;
+    const int32_t* __restrict__ col = G.g.col;
+    const uint32_t* __restrict__ len = G.g.len;
+    const uint64_t* __restrict__ mult = G.g.mult;
+    const uint8_t* __restrict__ nflag = G.g.nflag;
+    const bool cent = (G.flags & GF_CENT) != 0 && G.tn > 0;
+    double* __restrict__ cacc = G.cacc;
+    // interior scratch of the current source: d(s,v) and sigma(s,v) per table row
+    uint32_t* __restrict__ idist = G.dist;
+    uint64_t* __restrict__ isig = G.sigma;
+
+    for (int32_t v = tid; v < n; v += T) cacc[v] = 0.0;
+    if (cent)
+        for (int32_t i = tid; i < G.tn; i += T) G.cint[i] = 0.0;
+    unsigned long long bytes = 0;
+    if (tid == 0) ovf_flag = 0u;  // ordered before any use by the barrier below
+
+    for (int b = 0; b < G.nsrc; ++b) {
+        const int32_t s = G.src[b] - lo;
+        for (int32_t v = tid; v < n; v += T) {
+            dist[v] = (v == s) ? 0u : INF32;
+            sig[v] = (v == s) ? 1ull : 0ull;
+        }
+        if (tid == 0) {
+            fwd_next[0] = fwd_next[1] = fwd_next[2] = INF32;
+            bwd_prev[0] = bwd_prev[1] = bwd_prev[2] = 0u;
+        }
+        __syncthreads();
+
+        // ------------------------------------------------------------ forward ----
+        uint32_t D = 0;
+        bool ovf = false;
+        for (int k = 0;; ++k) {
+            uint32_t mn = INF32;
+            for_selected<T>(
+                n,
+                [&](int32_t v) {
+                    const uint32_t dv = dist[v];
+                    if (dv == D) return true;
+                    if (dv > D && dv != INF32) mn = min(mn, dv);
+                    return false;
+                },
+                [&](int32_t v, bool valid) {
+                    if (!valid) return;
+                    const int64_t e0 = rp[lo + v], e1 = rp[lo + v + 1];
+                    if (prof) bytes += 32ull * (unsigned long long)(e1 - e0) + 20ull;
+                    const bool pull = v != s;
+                    uint64_t sum = 0;
+                    for (int64_t e = e0; e < e1; e += RUNR) {
+                        int32_t u[RUNR];
+                        uint32_t L[RUNR];
+#pragma unroll
+                        for (int j = 0; j < RUNR; ++j) {
+                            const bool in = e + j < e1;
+                            u[j] = in ? col[e + j] - lo : -1;
+                            L[j] = in ? (len ? len[e + j] : 1u) : INF32;
+                        }
+                        // parents: settled at D - L in an earlier step (eq. parentsall /
+                        // eq. multiparents); offers made below are all above D
+                        if (pull) {
+#pragma unroll
+                            for (int j = 0; j < RUNR; ++j) {
+                                if (L[j] > D) continue;
+                                const uint32_t du = dist[u[j]];
+                                if (du == INF32 || du + L[j] != D) continue;
+                                uint64_t x = sig[u[j]];
+                                if (mult) {
+                                    const uint64_t m = mult[e + j];
+                                    if (__umul64hi(x, m) != 0) ovf = true;
+                                    x *= m;
+                                }
+                                const uint64_t r = sum + x;
+                                if (r < sum) ovf = true;
+                                sum = r;
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < RUNR; ++j) {
+                            if (u[j] < 0) continue;
+                            const uint32_t nv = D + L[j];
+                            if (nv < dist[u[j]]) {
+                                const uint32_t old = atomicMin(&dist[u[j]], nv);
+                                if (nv < old) mn = min(mn, nv);
+                            }
+                        }
+                    }
+                    if (pull) sig[v] = sum;
+                });
+            mn = wmin_u32(mn);
+            if (lane == 0 && mn != INF32) atomicMin(&fwd_next[k % 3], mn);
+            if (tid == 0) fwd_next[(k + 1) % 3] = INF32;
+            __syncthreads();
+            const uint32_t nx = fwd_next[k % 3];
+            if (nx == INF32) break;
+            D = nx;
+        }
+        if (ovf) ovf_flag = 1u;
+
+        // ------------------------------------------- interior rows: d and sigma ----
+        if (cent) {
+            for (int32_t i = tid; i < G.tn; i += T) {
+                const int64_t e0 = G.trow[G.t_lo + i], e1 = G.trow[G.t_lo + i + 1];
+                uint32_t dv = INF32;
+                for (int64_t e = e0; e < e1; ++e) {
+                    const uint32_t tf = dist[G.tcol[e] - lo];
+                    if (tf != INF32) dv = min(dv, tf + G.tlen[e]);
+                }
+                uint64_t sv = 0;
+                bool o2 = false;
+                if (dv != INF32) {
+                    for (int64_t e = e0; e < e1; ++e) {
+                        const int32_t f = G.tcol[e] - lo;
+                        const uint32_t tf = dist[f];
+                        if (tf == INF32 || tf + G.tlen[e] != dv) continue;
+                        const uint64_t a = sig[f], m = G.tsig[e];
+                        if (__umul64hi(a, m) != 0) o2 = true;
+                        const uint64_t r = sv + a * m;
+                        if (r < sv) o2 = true;
+                        sv = r;
+                    }
+                }
+                idist[i] = dv;
+                isig[i] = sv;
+                if (o2) ovf_flag = 1u;
+                if (prof) bytes += 32ull * (unsigned long long)(e1 - e0);
+            }
+        }
+        __syncthreads();
+
+        // ----------------------------------------------------------- backward ----
+        for (int k = 0; D > 0; ++k) {
+            uint32_t mx = 0;
+            for_selected<T>(
+                n,
+                [&](int32_t v) {
+                    const uint32_t dv = dist[v];
+                    if (dv == D) return true;
+                    if (dv < D) mx = max(mx, dv);
+                    return false;
+                },
+                [&](int32_t v, bool valid) {
+                    if (!valid) return;
+                    const int64_t e0 = rp[lo + v], e1 = rp[lo + v + 1];
+                    double acc = 0.0;
+                    for (int64_t e = e0; e < e1; e += RUNR) {
+                        int32_t x[RUNR];
+                        uint32_t L[RUNR];
+#pragma unroll
+                        for (int j = 0; j < RUNR; ++j) {
+                            const bool in = e + j < e1;
+                            x[j] = in ? col[e + j] - lo : 0;
+                            L[j] = in ? (len ? len[e + j] : 1u) : 0u;
+                        }
+#pragma unroll
+                        for (int j = 0; j < RUNR; ++j) {
+                            if (L[j] == 0u) continue;
+                            const uint32_t dx = dist[x[j]];
+                            if (dx == INF32 || dx != D + L[j]) continue;
+                            const double c = __longlong_as_double((long long)sig[x[j]]);
+                            acc += mult ? (double)mult[e + j] * c : c;
+                        }
+                    }
+                    const double sv = (double)sig[v];
+                    const double dl = sv * acc;
+                    cacc[v] += dl;
+                    const double ind = (nflag && (nflag[lo + v] & NF_TARGET)) ? 1.0 : 0.0;
+                    sig[v] = (uint64_t)__double_as_longlong((ind + dl) / sv);
+                });
+            mx = wmax_u32(mx);
+            if (lane == 0 && mx != 0u) atomicMax(&bwd_prev[k % 3], mx);
+            if (tid == 0) bwd_prev[(k + 1) % 3] = 0u;
+            __syncthreads();
+            D = bwd_prev[k % 3];
+        }
+
+        // --------------------------------------------- interior rows: delta ----
+        if (cent) {
+            for (int32_t i = tid; i < G.tn; i += T) {
+                const uint32_t dv = idist[i];
+                if (dv == INF32) continue;
+                const int64_t e0 = G.trow[G.t_lo + i], e1 = G.trow[G.t_lo + i + 1];
+                double acc = 0.0;
+                for (int64_t e = e0; e < e1; ++e) {
+                    const int32_t f = G.tcol[e] - lo;
+                    const uint32_t tf = dist[f];
+                    if (tf == INF32 || tf != dv + G.tlen[e]) continue;
+                    acc += (double)G.tsig[e] * __longlong_as_double((long long)sig[f]);
+                }
+                G.cint[i] += (double)isig[i] * acc;
+            }
+        }
+        __syncthreads();
+    }
+    if (ovf_flag && tid == 0) atomicOr(err, ERR_OVERFLOW);
+    if (prof) {
+        bytes = wsum_u64(bytes);
+        if (lane == 0 && bytes) atomicAdd(&prof[BC_K_RESIDENT], bytes);
+    }
+}
+
+size_t lds_bytes(int64_t range) { return (((size_t)range * 4 + 15) & ~(size_t)15) + (size_t)range * 8; }
+
+struct ResidentLimits {
+    bool init = false;
+    size_t lds = 0;  // usable dynamic LDS per workgroup
+};
+
+ResidentLimits& limits() {
+    static ResidentLimits L;
+    return L;
+}
+
+int query_limits() {
+    ResidentLimits& L = limits();
+    if (L.init) return BC_OK;
+    int dev = 0, v = 0;
+    BC_HIP(hipGetDevice(&dev));
+    BC_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    // keep room for the kernel's own static LDS
+    size_t usable = v > 1024 ? (size_t)v - 1024 : 0;
+    if (usable > 65536) {
+        if (hipFuncSetAttribute((const void*)k_resident<1024>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_resident<256>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess) {
+            (void)hipGetLastError();
+            usable = 65536 - 1024;
+        }
+    }
+    L.lds = usable;
+    L.init = true;
+    return BC_OK;
+}
+
+// ranges up to this many nodes run with 256 threads per workgroup
+constexpr int64_t SMALL_RANGE = 2048;
+
+}  // namespace
+
+int64_t resident_max_range() {
+    if (const char* e = getenv("BCPP_RESIDENT")) {
+        if (atoi(e) == 0) return 0;
+    }
+    if (query_limits() != BC_OK) return 0;
+    const size_t cap = limits().lds;
+    int64_t n = (int64_t)(cap / 12);
+    while (n > 0 && lds_bytes(n) > cap) --n;
+    return n;
+}
+
+int32_t resident_sources_per_group(int64_t nsrc) {
+    return (int32_t)std::min<int64_t>(LANES, std::max<int64_t>(1, (nsrc + 1023) / 1024));
+}
+
+size_t resident_group_bytes(const GroupDesc& G) {
+    const int64_t range = (int64_t)G.hi - G.lo;
+    size_t b = ((size_t)range * 8 + 255) & ~(size_t)255;
+    if ((G.flags & GF_CENT) && G.tn > 0)
+        b += (((size_t)G.tn * 8 + 255) & ~(size_t)255) * 2 + (((size_t)G.tn * 4 + 255) & ~(size_t)255);
+    return b + 256;
+}
+
+bool resident_alloc(Arena& a, GroupDesc& G) {
+    const int64_t range = (int64_t)G.hi - G.lo;
+    G.cacc = a.take<double>((size_t)std::max<int64_t>(range, 1));
+    if (!G.cacc) return false;
+    if ((G.flags & GF_CENT) && G.tn > 0) {
+        G.cint = a.take<double>((size_t)G.tn);
+        G.dist = a.take<uint32_t>((size_t)G.tn);
+        G.sigma = a.take<uint64_t>((size_t)G.tn);
+        if (!G.cint || !G.dist || !G.sigma) return false;
+    }
+    return true;
+}
+
+size_t resident_launch_bytes(size_t ngroups) {
+    return ((ngroups * sizeof(GroupDesc) + 255) & ~(size_t)255) * 2 + 512;
+}
+
+int run_resident(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups) {
+    if (groups.empty()) return BC_OK;
+    BC_TRY(query_limits());
+    // two launches: small ranges with 256 threads per workgroup, the rest with 1024
+    std::vector<GroupDesc> small, large;
+    size_t lds_small = 0, lds_large = 0;
+    for (const GroupDesc& G : groups) {
+        const int64_t range = (int64_t)G.hi - G.lo;
+        const size_t need = lds_bytes(range);
+        if (need > limits().lds) return fail(BC_E_INVAL, "resident: node range does not fit in LDS");
+        if (range <= SMALL_RANGE) {
+            small.push_back(G);
+            lds_small = std::max(lds_small, need);
+        } else {
+            large.push_back(G);
+            lds_large = std::max(lds_large, need);
+        }
+    }
+    uint32_t* d_err = a.take<uint32_t>(1);
+    GroupDesc* d_small = small.empty() ? nullptr : a.take<GroupDesc>(small.size());
+    GroupDesc* d_large = large.empty() ? nullptr : a.take<GroupDesc>(large.size());
+    if (!d_err || (!small.empty() && !d_small) || (!large.empty() && !d_large))
+        return fail(BC_E_NOMEM, "resident: workspace too small");
+    BC_HIP(hipMemsetAsync(d_err, 0, sizeof(uint32_t), s));
+    unsigned long long* prof = profiler().on ? profiler().d_bytes : nullptr;
+    if (!large.empty()) {
+        BC_HIP(hipMemcpyAsync(d_large, large.data(), large.size() * sizeof(GroupDesc),
+                              hipMemcpyHostToDevice, s));
+        KTimer kt(BC_K_RESIDENT, s);
+        hipLaunchKernelGGL(k_resident<1024>, dim3((unsigned)large.size()), dim3(1024), lds_large, s,
+                           d_large, d_err, prof);
+    }
+    if (!small.empty()) {
+        BC_HIP(hipMemcpyAsync(d_small, small.data(), small.size() * sizeof(GroupDesc),
+                              hipMemcpyHostToDevice, s));
+        KTimer kt(BC_K_RESIDENT, s);
+        hipLaunchKernelGGL(k_resident<256>, dim3((unsigned)small.size()), dim3(256), lds_small, s,
+                           d_small, d_err, prof);
+    }
+    BC_HIP(hipGetLastError());
+    uint32_t herr = 0;
+    BC_HIP(hipMemcpyAsync(&herr, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    BC_HIP(hipStreamSynchronize(s));
+    if (herr & ERR_OVERFLOW) return fail(BC_E_OVERFLOW, "a shortest-path count reached 2^64");
+    return BC_OK;
+}
+
+}  // namespace bcpp

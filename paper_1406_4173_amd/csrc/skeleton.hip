@@ -547,6 +547,44 @@ std::vector<GroupDesc> bsk_groups(const bc_skeleton* sk, const int32_t* src, int
 
 // --------------------------------------------------------------- Brandes++ -----
 
+// Brandes_SK and Centrality with the LDS-resident kernel: the skeleton fits in LDS.
+static int pp_resident(bc_graph* g, const bc_skeleton* sk, double scale, double* out_dev) {
+    hipStream_t s = g->stream;
+    const int32_t nsrc = (int32_t)sk->h_src.size();
+    const int32_t spg = resident_sources_per_group(nsrc);
+    const int32_t ngroups = (nsrc + spg - 1) / spg;
+    std::vector<GroupDesc> groups(ngroups);
+    size_t need = resident_launch_bytes(ngroups) + 2 * ((size_t)ngroups * 8 + 256) + 65536;
+    for (int32_t j = 0; j < ngroups; ++j) {
+        GroupDesc& G = groups[j];
+        G.g.row_ptr = sk->d_row_ptr;
+        G.g.col = sk->d_col;
+        G.g.len = sk->d_len;
+        G.g.mult = sk->d_mult;
+        G.g.nflag = sk->d_nflag;
+        G.lo = 0;
+        G.hi = sk->n_sk;
+        G.flags = GF_BACKWARD | (sk->n_int ? GF_CENT : 0u);
+        G.trow = sk->d_trow;
+        G.tcol = sk->d_tcol;
+        G.tlen = sk->d_tlen;
+        G.tsig = sk->d_tsig;
+        G.t_lo = 0;
+        G.tn = sk->n_int;
+        const int32_t first = j * spg;
+        G.nsrc = std::min(spg, nsrc - first);
+        for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? sk->h_src[first + b] : -1;
+        need += resident_group_bytes(G);
+    }
+    BC_TRY(g->work.reserve(need));
+    g->work.used = 0;
+    for (GroupDesc& G : groups)
+        if (!resident_alloc(g->work, G)) return fail(BC_E_NOMEM, "Brandes++: workspace too small");
+    BC_TRY(run_resident(s, g->work, groups));
+    return reduce_scores(s, g->work, groups, g->n, nullptr, nullptr, sk->d_out_idx, sk->d_out_which,
+                         scale, out_dev, false);
+}
+
 int pp_run(const bc_graph* gc, const bc_skeleton* sk, uint32_t flags, double* out_dev) {
     bc_graph* g = const_cast<bc_graph*>(gc);
     hipStream_t s = g->stream;
@@ -560,6 +598,7 @@ int pp_run(const bc_graph* gc, const bc_skeleton* sk, uint32_t flags, double* ou
         return BC_OK;
     }
     const int32_t N = sk->n_sk;
+    if (!(flags & BC_ENGINE_ONLY) && N <= resident_max_range()) return pp_resident(g, sk, scale, out_dev);
     const int64_t steps = max_steps_bound(N, LANES, sk->max_dist);
     const int32_t ngroups = (nsrc + LANES - 1) / LANES;
     const uint32_t gflags = GF_BACKWARD | (sk->n_int ? GF_CENT : 0u);

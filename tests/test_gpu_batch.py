@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_1406_4173_amd import inputs
 
-from test_gpu_plain import assert_scores
+from test_gpu_plain import PATHS, assert_scores
 
 pytestmark = pytest.mark.gpu
 
@@ -37,26 +37,41 @@ def mixed_graphs():
     return out
 
 
+@PATHS
 @pytest.mark.parametrize("pp", [False, True])
-def test_batch_mixed_graphs(bcpp, pp):
+def test_batch_mixed_graphs(bcpp, pp, engine_only):
     gs = mixed_graphs()
     B = bcpp.Batch(gs)
-    res = B.run(pp=pp)
+    res = B.run(pp=pp, engine_only=engine_only)
     for g, got in zip(gs, res):
         assert_scores(got, oracle.bc(g, g.S))
 
 
+@PATHS
 @pytest.mark.parametrize("pp", [False, True])
-def test_batch_item_equals_alone(bcpp, pp):
+def test_batch_item_equals_alone(bcpp, pp, engine_only):
     gs = inputs.batch_256(12)
-    res = bcpp.Batch(gs).run(pp=pp)
+    res = bcpp.Batch(gs).run(pp=pp, engine_only=engine_only)
     for g, got in zip(gs, res):
         G = bcpp.Graph(g)
         if pp:
-            alone = bcpp.brandes_pp(G, bcpp.partition_sk(G, g.part, g.k, g.S))
+            alone = bcpp.brandes_pp(G, bcpp.partition_sk(G, g.part, g.k, g.S), engine_only=engine_only)
         else:
-            alone = bcpp.brandes_plain(G, g.S)
+            alone = bcpp.brandes_plain(G, g.S, engine_only=engine_only)
         assert np.array_equal(got, alone)
+
+
+@pytest.mark.parametrize("pp", [False, True])
+def test_batch_resident_and_engine_graphs_together(bcpp, pp):
+    # a graph too large for LDS (engine) between graphs that fit (resident kernel)
+    # (20,000 nodes with 15,000 cut edges: its skeleton too has more nodes than LDS holds)
+    big = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 96, 0), inputs.equal_sizes(20000, 40),
+                     4.0 / 499, 15000, 3, "big20k")
+    big.S = inputs.random_targets(33, big.n, 25)
+    gs = mixed_graphs()[:4] + [big] + mixed_graphs()[4:]
+    res = bcpp.Batch(gs).run(pp=pp)
+    for g, got in zip(gs, res):
+        assert_scores(got, oracle.bc(g, g.S))
 
 
 def test_batch_256_full(bcpp):

@@ -12,6 +12,8 @@ from paper_1406_4173_amd import inputs
 pytestmark = pytest.mark.gpu
 
 REL = 1e-9
+# the two traversal paths: LDS-resident kernel where the graph fits, and the engine
+PATHS = pytest.mark.parametrize("engine_only", [False, True], ids=["resident", "engine"])
 
 
 def assert_scores(got, want, rel=REL):
@@ -71,7 +73,8 @@ def test_counts_overflow_boundary(bcpp):
     assert ei.value.code == bcpp.BC_E_OVERFLOW
 
 
-def test_plain_small_random_graphs(bcpp):
+@PATHS
+def test_plain_small_random_graphs(bcpp, engine_only):
     for seed in range(120):
         rng = np.random.default_rng(seed)
         n = int(rng.integers(1, 40))
@@ -79,58 +82,82 @@ def test_plain_small_random_graphs(bcpp):
                                 wmax=[None, 3, 9][seed % 3])
         G = bcpp.Graph(g)
         for ordered in (False, True):
-            assert_scores(bcpp.brandes_plain(G, g.S, ordered), oracle.bc(g, g.S, ordered))
+            assert_scores(bcpp.brandes_plain(G, g.S, ordered, engine_only=engine_only),
+                          oracle.bc(g, g.S, ordered))
 
 
-@pytest.mark.parametrize("n", [2, 7, 64, 65, 200])
-def test_plain_closed_forms(bcpp, n):
+@PATHS
+@pytest.mark.parametrize("n", [2, 7, 64, 65, 200, 3000])
+def test_plain_closed_forms(bcpp, n, engine_only):
+    def run(g, S):
+        return bcpp.brandes_plain(bcpp.Graph(g), S, engine_only=engine_only)
+
     g = inputs.star(n)
-    C = bcpp.brandes_plain(bcpp.Graph(g), np.arange(n))
+    C = run(g, np.arange(n))
     assert C[0] == (n - 1) * (n - 2) / 2 and np.all(C[1:] == 0)
     g = inputs.path(n)
     i = np.arange(n)
-    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), i), (i * (n - 1 - i)).astype(float))
+    assert_scores(run(g, i), (i * (n - 1 - i)).astype(float))
     if n >= 3:
         g = inputs.cycle(n)
         want = (n - 2) ** 2 / 8 if n % 2 == 0 else (n - 1) * (n - 3) / 8
-        assert_scores(bcpp.brandes_plain(bcpp.Graph(g), np.arange(n)), np.full(n, want))
+        assert_scores(run(g, np.arange(n)), np.full(n, want))
         g = inputs.complete(min(n, 40))
-        assert np.all(bcpp.brandes_plain(bcpp.Graph(g), np.arange(g.n)) == 0)
+        assert np.all(run(g, np.arange(g.n)) == 0)
 
 
-def test_plain_degenerate_target_sets(bcpp):
+@PATHS
+def test_plain_degenerate_target_sets(bcpp, engine_only):
     g = inputs.planted_1k()
     G = bcpp.Graph(g)
     for S in ([], [3]):
-        assert np.all(bcpp.brandes_plain(G, np.array(S, np.int32)) == 0)
+        assert np.all(bcpp.brandes_plain(G, np.array(S, np.int32), engine_only=engine_only) == 0)
     S = [5, 900]
-    assert_scores(bcpp.brandes_plain(G, S), oracle.bc(g, np.array(S)))
+    assert_scores(bcpp.brandes_plain(G, S, engine_only=engine_only), oracle.bc(g, np.array(S)))
     with pytest.raises(bcpp.BcError):
         bcpp.brandes_plain(G, [1, 1])
     with pytest.raises(bcpp.BcError):
         bcpp.brandes_plain(G, [1, g.n])
     e = inputs.empty(10)
-    assert np.all(bcpp.brandes_plain(bcpp.Graph(e), np.arange(10)) == 0)
+    assert np.all(bcpp.brandes_plain(bcpp.Graph(e), np.arange(10), engine_only=engine_only) == 0)
 
 
-def test_plain_overflow(bcpp):
+@PATHS
+def test_plain_overflow(bcpp, engine_only):
     g = inputs.grid(35, 35)
     with pytest.raises(bcpp.BcError) as ei:
-        bcpp.brandes_plain(bcpp.Graph(g), [0, g.n - 1])
+        bcpp.brandes_plain(bcpp.Graph(g), [0, g.n - 1], engine_only=engine_only)
     assert ei.value.code == bcpp.BC_E_OVERFLOW
     g = inputs.grid(34, 35)
-    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), [0, g.n - 1]),
+    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), [0, g.n - 1], engine_only=engine_only),
                   oracle.bc(g, np.array([0, g.n - 1])))
 
 
-def test_plain_planted_1k_full(bcpp):
+@PATHS
+def test_plain_planted_1k_full(bcpp, engine_only):
     g = inputs.planted_1k()
-    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), g.S), oracle.bc(g, g.S))
+    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), g.S, engine_only=engine_only), oracle.bc(g, g.S))
 
 
-def test_plain_sbm_10k_full(bcpp):
+@PATHS
+def test_plain_sbm_10k_full(bcpp, engine_only):
     g = inputs.sbm_10k()
-    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), g.S), oracle.bc(g, g.S))
+    assert_scores(bcpp.brandes_plain(bcpp.Graph(g), g.S, engine_only=engine_only), oracle.bc(g, g.S))
+
+
+def test_plain_resident_overflow_in_a_later_source(bcpp):
+    # the overflowing source is not the first of its group: the flag must survive the
+    # sources after it
+    # (more than 1024 targets: two per group; corner 0 is the second source of the
+    # first group, and the opposite corner is the second of the last full group)
+    g = inputs.grid(35, 35)
+    S = np.arange(g.n, dtype=np.int32)
+    S[0], S[1] = 1, 0
+    S[-1], S[-2] = S[-2], S[-1]
+    for engine_only in (False, True):
+        with pytest.raises(bcpp.BcError) as ei:
+            bcpp.brandes_plain(bcpp.Graph(g), S, engine_only=engine_only)
+        assert ei.value.code == bcpp.BC_E_OVERFLOW
 
 
 def test_plain_dev_entry_point(bcpp):

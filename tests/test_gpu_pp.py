@@ -13,7 +13,7 @@ import pytest
 import oracle
 from paper_1406_4173_amd import inputs
 
-from test_gpu_plain import assert_scores
+from test_gpu_plain import PATHS, assert_scores
 
 pytestmark = pytest.mark.gpu
 
@@ -89,7 +89,8 @@ def test_skeleton_preserves_distances_and_counts(bcpp):
             assert np.array_equal(sig[i], osig[nodes]), f"sigma_SK != sigma_G from {s}"
 
 
-def test_pp_small_random_graphs(bcpp):
+@PATHS
+def test_pp_small_random_graphs(bcpp, engine_only):
     for seed in range(150):
         rng = np.random.default_rng(seed)
         n = int(rng.integers(1, 50))
@@ -98,11 +99,12 @@ def test_pp_small_random_graphs(bcpp):
         G = bcpp.Graph(g)
         sk = bcpp.partition_sk(G, g.part, g.k, g.S)
         want = oracle.bc(g, g.S)
-        assert_scores(bcpp.brandes_pp(G, sk), want)
-        assert_scores(bcpp.brandes_pp(G, sk, ordered=True), 2 * want)
+        assert_scores(bcpp.brandes_pp(G, sk, engine_only=engine_only), want)
+        assert_scores(bcpp.brandes_pp(G, sk, ordered=True, engine_only=engine_only), 2 * want)
 
 
-def test_pp_partition_invariance(bcpp):
+@PATHS
+def test_pp_partition_invariance(bcpp, engine_only):
     g = inputs.planted_1k()
     S = inputs.random_targets(31, g.n, 90)
     want = oracle.bc(g, S)
@@ -115,10 +117,11 @@ def test_pp_partition_invariance(bcpp):
     }
     for name, (part, k) in parts.items():
         sk = bcpp.partition_sk(G, part, k, S)
-        assert_scores(bcpp.brandes_pp(G, sk), want)
+        assert_scores(bcpp.brandes_pp(G, sk, engine_only=engine_only), want)
 
 
-def test_pp_edge_cases(bcpp):
+@PATHS
+def test_pp_edge_cases(bcpp, engine_only):
     # isolated targets, a part with no frontier, a part made only of targets
     g = inputs.graph_from_edges(12, [0, 1, 2, 3, 5, 6, 8], [1, 2, 3, 4, 6, 7, 9])
     g.part = np.array([0, 0, 0, 1, 1, 2, 2, 2, 3, 3, 4, 5], np.int32)
@@ -127,43 +130,47 @@ def test_pp_edge_cases(bcpp):
     for S in ([0, 4, 10, 11], [0, 4], [3, 4, 0], [10, 11], [], [2]):
         S = np.array(S, np.int32)
         sk = bcpp.partition_sk(G, g.part, g.k, S)
-        assert_scores(bcpp.brandes_pp(G, sk), oracle.bc(g, S))
+        assert_scores(bcpp.brandes_pp(G, sk, engine_only=engine_only), oracle.bc(g, S))
     with pytest.raises(bcpp.BcError):
         bcpp.partition_sk(G, g.part, 3, [0, 4])
     with pytest.raises(bcpp.BcError):
         bcpp.partition_sk(G, g.part, g.k, [0, 0])
 
 
-def test_pp_overflow(bcpp):
+@PATHS
+def test_pp_overflow(bcpp, engine_only):
     g = inputs.grid(35, 35)
     G = bcpp.Graph(g)
     part = (np.arange(g.n) // 35 // 5).astype(np.int32)
     sk = bcpp.partition_sk(G, part, 7, [0, g.n - 1])
     with pytest.raises(bcpp.BcError) as ei:
-        bcpp.brandes_pp(G, sk)
+        bcpp.brandes_pp(G, sk, engine_only=engine_only)
     assert ei.value.code == bcpp.BC_E_OVERFLOW
 
 
-def test_pp_planted_1k_full(bcpp):
+@PATHS
+def test_pp_planted_1k_full(bcpp, engine_only):
     g = inputs.planted_1k()
     G = bcpp.Graph(g)
     sk = bcpp.partition_sk(G, g.part, g.k, g.S)
-    assert_scores(bcpp.brandes_pp(G, sk), oracle.bc(g, g.S))
+    assert_scores(bcpp.brandes_pp(G, sk, engine_only=engine_only), oracle.bc(g, g.S))
 
 
-def test_pp_sbm_10k_full(bcpp):
+@PATHS
+def test_pp_sbm_10k_full(bcpp, engine_only):
     g = inputs.sbm_10k()
     G = bcpp.Graph(g)
     sk = bcpp.partition_sk(G, g.part, g.k, g.S)
-    assert_scores(bcpp.brandes_pp(G, sk), oracle.bc(g, g.S))
+    assert_scores(bcpp.brandes_pp(G, sk, engine_only=engine_only), oracle.bc(g, g.S))
 
 
-def test_pp_smallcut_100k(bcpp):
+@PATHS
+def test_pp_smallcut_100k(bcpp, engine_only):
     g = inputs.smallcut_100k()
     G = bcpp.Graph(g)
     sk = bcpp.partition_sk(G, g.part, g.k, g.S)
     want = oracle.bc(g, g.S)
-    assert_scores(bcpp.brandes_pp(G, sk), want)
+    assert_scores(bcpp.brandes_pp(G, sk, engine_only=engine_only), want)
     assert_scores(bcpp.brandes_plain(G, g.S), want)
 
 
