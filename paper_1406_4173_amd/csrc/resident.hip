@@ -30,8 +30,6 @@ namespace bcpp {
 
 namespace {
 
-constexpr int RUNR = 8;  // arcs whose loads a thread issues together
-
 __device__ __forceinline__ uint32_t wmin_u32(uint32_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
@@ -92,30 +90,79 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long m, int k) {
 // nodes per pass (its share: passes T apart), queues the selected ones in registers
 // (one per lane) and hands every full queue of 64, and the last partial one, to
 // body(v, valid) with all lanes converged. A step that settles few nodes thus costs
-// one round of neighbour loads per wave instead of one per scan pass.
+// one round of neighbour loads per wave instead of one per scan pass. sel is
+// evaluated for SCAN passes before their nodes are handed on, so it must not depend
+// on what body does to other nodes in the same step.
+constexpr int SCAN = 4;
 template <int T, class Sel, class Body>
 __device__ __forceinline__ void for_selected(int32_t n, Sel&& sel, Body&& body) {
     const int lane = threadIdx.x & 63;
     int cnt = 0;
     int32_t q = 0;
-    for (int32_t base = (int32_t)(threadIdx.x & ~63u); base < n; base += T) {
-        const int32_t v = base + lane;
-        const bool hit = v < n && sel(v);
-        const unsigned long long m = __ballot(hit);
-        int avail = __popcll(m), used = 0;
-        while (avail > 0) {
-            const int take = min(64 - cnt, avail);
-            if (lane >= cnt && lane < cnt + take) q = base + nth_set_bit(m, used + lane - cnt);
-            cnt += take;
-            used += take;
-            avail -= take;
-            if (cnt == 64) {
-                body(q, true);
-                cnt = 0;
+    for (int32_t base0 = (int32_t)(threadIdx.x & ~63u); base0 < n; base0 += SCAN * T) {
+        unsigned long long ms[SCAN];
+#pragma unroll
+        for (int p = 0; p < SCAN; ++p) {
+            const int32_t v = base0 + p * T + lane;
+            ms[p] = __ballot(v < n && sel(v));
+        }
+#pragma unroll
+        for (int p = 0; p < SCAN; ++p) {
+            const unsigned long long m = ms[p];
+            const int32_t base = base0 + p * T;
+            int avail = __popcll(m), used = 0;
+            while (avail > 0) {
+                const int take = min(64 - cnt, avail);
+                if (lane >= cnt && lane < cnt + take) q = base + nth_set_bit(m, used + lane - cnt);
+                cnt += take;
+                used += take;
+                avail -= take;
+                if (cnt == 64) {
+                    body(q, true);
+                    cnt = 0;
+                }
             }
         }
     }
     if (cnt > 0) body(q, lane < cnt);
+}
+
+// Arc expansion of a queue: lane i holds queued node q (valid) whose arcs are
+// [rp[lo+q], rp[lo+q+1]). Round r hands the queue's arcs r .. r+63, in node order, one
+// per lane, to f(owner, e, ok, incl, excl, r): owner = queue slot of the arc's node,
+// e = the arc, ok = false past the last arc; incl/excl are the calling lane's own
+// inclusive/exclusive arc offsets (its slot's range [excl, incl)). All lanes stay
+// converged, so f may use cross-lane operations before it branches on ok.
+template <class F>
+__device__ __forceinline__ void for_queue_arcs(const int64_t* __restrict__ rp, int32_t lo, int32_t q,
+                                               bool valid, F&& f) {
+    const int lane = threadIdx.x & 63;
+    int64_t e0 = 0;
+    int deg = 0;
+    if (valid) {
+        e0 = rp[lo + q];
+        deg = (int)(rp[lo + q + 1] - e0);
+    }
+    int incl = deg;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    const int total = __shfl(incl, 63, 64);
+    const int excl = incl - deg;
+    const int e0lo = (int)(uint32_t)(uint64_t)e0, e0hi = (int)(uint32_t)((uint64_t)e0 >> 32);
+    for (int r = 0; r < total; r += 64) {
+        const int p = r + lane;
+        // owner = number of slots whose arcs end at or before p (at most 63)
+        int i = 0;
+#pragma unroll
+        for (int st = 32; st > 0; st >>= 1)
+            if (__shfl(incl, i + st - 1, 64) <= p) i += st;
+        const int ex = __shfl(excl, i, 64);
+        const uint64_t base = ((uint64_t)(uint32_t)__shfl(e0hi, i, 64) << 32) | (uint32_t)__shfl(e0lo, i, 64);
+        f(i, (int64_t)base + (p - ex), p < total, incl, excl, r);
+    }
 }
 
 template <int T>
@@ -176,51 +223,39 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
                     if (dv > D && dv != INF32) mn = min(mn, dv);
                     return false;
                 },
-                [&](int32_t v, bool valid) {
-                    if (!valid) return;
-                    const int64_t e0 = rp[lo + v], e1 = rp[lo + v + 1];
-                    if (prof) bytes += 32ull * (unsigned long long)(e1 - e0) + 20ull;
-                    const bool pull = v != s;
-                    uint64_t sum = 0;
-                    for (int64_t e = e0; e < e1; e += RUNR) {
-                        int32_t u[RUNR];
-                        uint32_t L[RUNR];
-#pragma unroll
-                        for (int j = 0; j < RUNR; ++j) {
-                            const bool in = e + j < e1;
-                            u[j] = in ? col[e + j] - lo : -1;
-                            L[j] = in ? (len ? len[e + j] : 1u) : INF32;
-                        }
-                        // parents: settled at D - L in an earlier step (eq. parentsall /
-                        // eq. multiparents); offers made below are all above D
-                        if (pull) {
-#pragma unroll
-                            for (int j = 0; j < RUNR; ++j) {
-                                if (L[j] > D) continue;
-                                const uint32_t du = dist[u[j]];
-                                if (du == INF32 || du + L[j] != D) continue;
-                                uint64_t x = sig[u[j]];
+                [&](int32_t q, bool valid) {
+                    if (prof && valid) bytes += 20ull;
+                    for_queue_arcs(rp, lo, q, valid, [&](int owner, int64_t e, bool ok, int, int, int) {
+                        const int32_t v = __shfl(q, owner, 64);
+                        if (!ok) return;
+                        if (prof) bytes += 32ull;
+                        const int32_t u = col[e] - lo;
+                        const uint32_t L = len ? len[e] : 1u;
+                        // u is a parent of v if it settled at D - L in an earlier step (eq.
+                        // parentsall / eq. multiparents); the count adds in with an atomic,
+                        // exact for integers, and a wrap of any addition is an overflow
+                        if (v != s && L <= D) {
+                            const uint32_t du = dist[u];
+                            if (du != INF32 && du + L == D) {
+                                uint64_t x = sig[u];
                                 if (mult) {
-                                    const uint64_t m = mult[e + j];
+                                    const uint64_t m = mult[e];
                                     if (__umul64hi(x, m) != 0) ovf = true;
                                     x *= m;
                                 }
-                                const uint64_t r = sum + x;
-                                if (r < sum) ovf = true;
-                                sum = r;
+                                if (x) {
+                                    const uint64_t old = atomicAdd((unsigned long long*)&sig[v], (unsigned long long)x);
+                                    if (old + x < old) ovf = true;
+                                }
                             }
                         }
-#pragma unroll
-                        for (int j = 0; j < RUNR; ++j) {
-                            if (u[j] < 0) continue;
-                            const uint32_t nv = D + L[j];
-                            if (nv < dist[u[j]]) {
-                                const uint32_t old = atomicMin(&dist[u[j]], nv);
-                                if (nv < old) mn = min(mn, nv);
-                            }
+                        // offers: all above D, so they never meet the parent test above
+                        const uint32_t nv = D + L;
+                        if (nv < dist[u]) {
+                            const uint32_t old = atomicMin(&dist[u], nv);
+                            if (nv < old) mn = min(mn, nv);
                         }
-                    }
-                    if (pull) sig[v] = sum;
+                    });
                 });
             mn = wmin_u32(mn);
             if (lane == 0 && mn != INF32) atomicMin(&fwd_next[k % 3], mn);
@@ -274,33 +309,43 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
                     if (dv < D) mx = max(mx, dv);
                     return false;
                 },
-                [&](int32_t v, bool valid) {
-                    if (!valid) return;
-                    const int64_t e0 = rp[lo + v], e1 = rp[lo + v + 1];
-                    double acc = 0.0;
-                    for (int64_t e = e0; e < e1; e += RUNR) {
-                        int32_t x[RUNR];
-                        uint32_t L[RUNR];
-#pragma unroll
-                        for (int j = 0; j < RUNR; ++j) {
-                            const bool in = e + j < e1;
-                            x[j] = in ? col[e + j] - lo : 0;
-                            L[j] = in ? (len ? len[e + j] : 1u) : 0u;
-                        }
-#pragma unroll
-                        for (int j = 0; j < RUNR; ++j) {
-                            if (L[j] == 0u) continue;
-                            const uint32_t dx = dist[x[j]];
-                            if (dx == INF32 || dx != D + L[j]) continue;
-                            const double c = __longlong_as_double((long long)sig[x[j]]);
-                            acc += mult ? (double)mult[e + j] * c : c;
-                        }
+                [&](int32_t q, bool valid) {
+                    double prev = 0.0, ind = 0.0, acc = 0.0;
+                    if (valid) {
+                        prev = cacc[q];
+                        ind = (nflag && (nflag[lo + q] & NF_TARGET)) ? 1.0 : 0.0;
                     }
-                    const double sv = (double)sig[v];
-                    const double dl = sv * acc;
-                    cacc[v] += dl;
-                    const double ind = (nflag && (nflag[lo + v] & NF_TARGET)) ? 1.0 : 0.0;
-                    sig[v] = (uint64_t)__double_as_longlong((ind + dl) / sv);
+                    for_queue_arcs(rp, lo, q, valid, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
+                        // segment of this lane's arc: lanes from its node's first arc in
+                        // this round
+                        const int seg = max(__shfl(excl, owner, 64) - r, 0);
+                        double c = 0.0;
+                        if (ok) {
+                            const int32_t x = col[e] - lo;
+                            const uint32_t L = len ? len[e] : 1u;
+                            const uint32_t dx = dist[x];
+                            if (dx != INF32 && dx == D + L) {
+                                c = __longlong_as_double((long long)sig[x]);
+                                if (mult) c *= (double)mult[e];
+                            }
+                        }
+                        // per-node sums of the round: segmented inclusive scan
+#pragma unroll
+                        for (int o = 1; o < 64; o <<= 1) {
+                            const double t = __shfl_up(c, o, 64);
+                            if (lane - o >= seg) c += t;
+                        }
+                        // each slot takes the sum at the last lane of its arcs in the round
+                        const int a = max(excl - r, 0), b = min(incl - r, 64);
+                        const double part = __shfl(c, max(b - 1, 0), 64);
+                        if (b > a) acc += part;
+                    });
+                    if (valid) {
+                        const double sv = (double)sig[q];
+                        const double dl = sv * acc;
+                        cacc[q] = prev + dl;
+                        sig[q] = (uint64_t)__double_as_longlong((ind + dl) / sv);
+                    }
                 });
             mx = wmax_u32(mx);
             if (lane == 0 && mx != 0u) atomicMax(&bwd_prev[k % 3], mx);
@@ -357,6 +402,8 @@ int query_limits() {
     if (usable > 65536) {
         if (hipFuncSetAttribute((const void*)k_resident<1024>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_resident<512>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
             hipFuncSetAttribute((const void*)k_resident<256>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess) {
             (void)hipGetLastError();
@@ -368,8 +415,10 @@ int query_limits() {
     return BC_OK;
 }
 
-// ranges up to this many nodes run with 256 threads per workgroup
+// ranges up to SMALL_RANGE nodes run with 256 threads per workgroup, up to MID_RANGE
+// with 512 (several workgroups per CU), larger ones with 1024
 constexpr int64_t SMALL_RANGE = 2048;
+constexpr int64_t MID_RANGE = 6000;
 
 }  // namespace
 
@@ -410,47 +459,45 @@ bool resident_alloc(Arena& a, GroupDesc& G) {
 }
 
 size_t resident_launch_bytes(size_t ngroups) {
-    return ((ngroups * sizeof(GroupDesc) + 255) & ~(size_t)255) * 2 + 512;
+    // descriptors of up to three launches and the error word, each rounded to 256 B
+    return ngroups * sizeof(GroupDesc) + 4 * 256 + 512;
 }
 
 int run_resident(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups) {
     if (groups.empty()) return BC_OK;
     BC_TRY(query_limits());
-    // two launches: small ranges with 256 threads per workgroup, the rest with 1024
-    std::vector<GroupDesc> small, large;
-    size_t lds_small = 0, lds_large = 0;
+    // one launch per size class
+    std::vector<GroupDesc> cls[3];
+    size_t lds[3] = {0, 0, 0};
     for (const GroupDesc& G : groups) {
         const int64_t range = (int64_t)G.hi - G.lo;
         const size_t need = lds_bytes(range);
         if (need > limits().lds) return fail(BC_E_INVAL, "resident: node range does not fit in LDS");
-        if (range <= SMALL_RANGE) {
-            small.push_back(G);
-            lds_small = std::max(lds_small, need);
-        } else {
-            large.push_back(G);
-            lds_large = std::max(lds_large, need);
-        }
+        const int c = range <= SMALL_RANGE ? 0 : range <= MID_RANGE ? 1 : 2;
+        cls[c].push_back(G);
+        lds[c] = std::max(lds[c], need);
     }
     uint32_t* d_err = a.take<uint32_t>(1);
-    GroupDesc* d_small = small.empty() ? nullptr : a.take<GroupDesc>(small.size());
-    GroupDesc* d_large = large.empty() ? nullptr : a.take<GroupDesc>(large.size());
-    if (!d_err || (!small.empty() && !d_small) || (!large.empty() && !d_large))
-        return fail(BC_E_NOMEM, "resident: workspace too small");
+    GroupDesc* d_desc[3];
+    for (int c = 0; c < 3; ++c) {
+        d_desc[c] = cls[c].empty() ? nullptr : a.take<GroupDesc>(cls[c].size());
+        if (!cls[c].empty() && !d_desc[c]) return fail(BC_E_NOMEM, "resident: workspace too small");
+    }
+    if (!d_err) return fail(BC_E_NOMEM, "resident: workspace too small");
     BC_HIP(hipMemsetAsync(d_err, 0, sizeof(uint32_t), s));
     unsigned long long* prof = profiler().on ? profiler().d_bytes : nullptr;
-    if (!large.empty()) {
-        BC_HIP(hipMemcpyAsync(d_large, large.data(), large.size() * sizeof(GroupDesc),
+    for (int c = 2; c >= 0; --c) {
+        if (cls[c].empty()) continue;
+        BC_HIP(hipMemcpyAsync(d_desc[c], cls[c].data(), cls[c].size() * sizeof(GroupDesc),
                               hipMemcpyHostToDevice, s));
         KTimer kt(BC_K_RESIDENT, s);
-        hipLaunchKernelGGL(k_resident<1024>, dim3((unsigned)large.size()), dim3(1024), lds_large, s,
-                           d_large, d_err, prof);
-    }
-    if (!small.empty()) {
-        BC_HIP(hipMemcpyAsync(d_small, small.data(), small.size() * sizeof(GroupDesc),
-                              hipMemcpyHostToDevice, s));
-        KTimer kt(BC_K_RESIDENT, s);
-        hipLaunchKernelGGL(k_resident<256>, dim3((unsigned)small.size()), dim3(256), lds_small, s,
-                           d_small, d_err, prof);
+        const dim3 grid((unsigned)cls[c].size());
+        if (c == 2)
+            hipLaunchKernelGGL(k_resident<1024>, grid, dim3(1024), lds[c], s, d_desc[c], d_err, prof);
+        else if (c == 1)
+            hipLaunchKernelGGL(k_resident<512>, grid, dim3(512), lds[c], s, d_desc[c], d_err, prof);
+        else
+            hipLaunchKernelGGL(k_resident<256>, grid, dim3(256), lds[c], s, d_desc[c], d_err, prof);
     }
     BC_HIP(hipGetLastError());
     uint32_t herr = 0;
