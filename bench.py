@@ -20,6 +20,41 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
+# source file of each kernel kind: measured HBM traffic is reported only while the
+# kernel's source is the one the counters were taken on
+KERNEL_SOURCES = {
+    "resident": "paper_1406_4173_amd/csrc/resident.hip",
+    "select": "paper_1406_4173_amd/csrc/engine.hip",
+    "settle": "paper_1406_4173_amd/csrc/engine.hip",
+    "push": "paper_1406_4173_amd/csrc/engine.hip",
+    "backward": "paper_1406_4173_amd/csrc/engine.hip",
+    "centrality": "paper_1406_4173_amd/csrc/engine.hip",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs summarised in profiles/hbm_traffic.json (each counter scaled by its
+    reading for a plain device copy of known size), or None when there is no entry or
+    the kernel's source has changed since the counters were taken."""
+    import hashlib
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = table.get(workload, {}).get(kernel)
+    src = KERNEL_SOURCES.get(kernel)
+    if not ent or not src:
+        return None
+    with open(os.path.join(ROOT, src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != ent.get("source_sha256"):
+        return None
+    return float(ent["fetch_bytes_per_launch"]) + float(ent["write_bytes_per_launch"])
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -111,7 +146,9 @@ def bench_batch(args):
         "config": {"workload": "batch_256", "graphs": len(gs), "n": int(sum(g.n for g in gs)),
                    "m": int(sum(g.m for g in gs)), "targets": int(sum(len(g.S) for g in gs))},
         "roofline": {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": measured_traffic("batch_256", kern),
+                     "alg_bytes_per_launch": kp["alg_bytes"] / max(kp["launches"], 1),
                      "launches": kp["launches"],
                      "avg_launch_us": kp["ms"] * 1e3 / max(kp["launches"], 1)},
         "kernels_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
@@ -283,7 +320,7 @@ def main():
         "peak": PEAK_HBM_GBS,
         "unit": "GB/s",
         "frac": achieved / PEAK_HBM_GBS,
-        "traffic": None,
+        "traffic": measured_traffic(args.workload, kern),
         "launches": kp["launches"],
         "avg_launch_us": kp["ms"] * 1e3 / max(kp["launches"], 1),
         "alg_bytes_per_launch": kp["alg_bytes"] / max(kp["launches"], 1),

@@ -48,83 +48,47 @@ __device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
     return v;
 }
 
-// index of the k-th (0-based) set bit of m; m has more than k set bits
-__device__ __forceinline__ int nth_set_bit(unsigned long long m, int k) {
-    int pos = 0;
-    int c = __popc((uint32_t)m);
-    if (k >= c) {
-        k -= c;
-        m >>= 32;
-        pos = 32;
-    }
-    uint32_t w = (uint32_t)m;
-    c = __popc(w & 0xFFFFu);
-    if (k >= c) {
-        k -= c;
-        w >>= 16;
-        pos += 16;
-    }
-    c = __popc(w & 0xFFu);
-    if (k >= c) {
-        k -= c;
-        w >>= 8;
-        pos += 8;
-    }
-    c = __popc(w & 0xFu);
-    if (k >= c) {
-        k -= c;
-        w >>= 4;
-        pos += 4;
-    }
-    c = __popc(w & 0x3u);
-    if (k >= c) {
-        k -= c;
-        w >>= 2;
-        pos += 2;
-    }
-    if (k >= (int)(w & 1u)) pos += 1;
-    return pos;
-}
-
 // Visit the nodes v of [0, n) for which sel(v) holds. Each wave scans 64 consecutive
-// nodes per pass (its share: passes T apart), queues the selected ones in registers
-// (one per lane) and hands every full queue of 64, and the last partial one, to
-// body(v, valid) with all lanes converged. A step that settles few nodes thus costs
+// nodes per pass (its share: passes T apart), appends the selected ones to its own LDS
+// queue wq (128 entries) and hands every full queue of 64, and the last partial one,
+// to body(v, valid) with all lanes converged. A step that settles few nodes thus costs
 // one round of neighbour loads per wave instead of one per scan pass. sel is
 // evaluated for SCAN passes before their nodes are handed on, so it must not depend
-// on what body does to other nodes in the same step.
+// on what body does to other nodes in the same step. The queue is private to the
+// wave, whose LDS accesses complete in order.
 constexpr int SCAN = 4;
+constexpr int WQ = 128;
 template <int T, class Sel, class Body>
-__device__ __forceinline__ void for_selected(int32_t n, Sel&& sel, Body&& body) {
+__device__ __forceinline__ void for_selected(int32_t n, int32_t* __restrict__ wq, Sel&& sel, Body&& body) {
     const int lane = threadIdx.x & 63;
     int cnt = 0;
-    int32_t q = 0;
     for (int32_t base0 = (int32_t)(threadIdx.x & ~63u); base0 < n; base0 += SCAN * T) {
         unsigned long long ms[SCAN];
+        bool hit[SCAN];
 #pragma unroll
         for (int p = 0; p < SCAN; ++p) {
             const int32_t v = base0 + p * T + lane;
-            ms[p] = __ballot(v < n && sel(v));
+            hit[p] = v < n && sel(v);
+            ms[p] = __ballot(hit[p]);
         }
 #pragma unroll
         for (int p = 0; p < SCAN; ++p) {
             const unsigned long long m = ms[p];
-            const int32_t base = base0 + p * T;
-            int avail = __popcll(m), used = 0;
-            while (avail > 0) {
-                const int take = min(64 - cnt, avail);
-                if (lane >= cnt && lane < cnt + take) q = base + nth_set_bit(m, used + lane - cnt);
-                cnt += take;
-                used += take;
-                avail -= take;
-                if (cnt == 64) {
-                    body(q, true);
-                    cnt = 0;
-                }
+            if (m == 0ull) continue;
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (hit[p]) wq[cnt + rank] = base0 + p * T + lane;
+            cnt += __popcll(m);
+            if (cnt >= 64) {
+                body(wq[lane], true);
+                const int rest = cnt - 64;
+                const int32_t t = lane < rest ? wq[64 + lane] : 0;
+                if (lane < rest) wq[lane] = t;
+                cnt = rest;
             }
         }
     }
-    if (cnt > 0) body(q, lane < cnt);
+    if (cnt > 0) body(lane < cnt ? wq[lane] : 0, lane < cnt);
 }
 
 // Arc expansion of a queue: lane i holds queued node q (valid) whose arcs are
@@ -173,10 +137,12 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
     __shared__ uint32_t fwd_next[3];  // rotating: step k writes [k%3], clears [(k+1)%3]
     __shared__ uint32_t bwd_prev[3];
     __shared__ uint32_t ovf_flag;
+    __shared__ int32_t wqueue[T / 64][WQ];
 
     const GroupDesc& G = desc[blockIdx.x];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    int32_t* __restrict__ wq = wqueue[tid >> 6];
     const int32_t lo = G.lo;
     const int32_t n = G.hi - G.lo;
     uint32_t* __restrict__ dist = reinterpret_cast<uint32_t*>(lds);
@@ -216,7 +182,7 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
         for (int k = 0;; ++k) {
             uint32_t mn = INF32;
             for_selected<T>(
-                n,
+                n, wq,
                 [&](int32_t v) {
                     const uint32_t dv = dist[v];
                     if (dv == D) return true;
@@ -302,7 +268,7 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
         for (int k = 0; D > 0; ++k) {
             uint32_t mx = 0;
             for_selected<T>(
-                n,
+                n, wq,
                 [&](int32_t v) {
                     const uint32_t dv = dist[v];
                     if (dv == D) return true;
@@ -397,8 +363,9 @@ int query_limits() {
     int dev = 0, v = 0;
     BC_HIP(hipGetDevice(&dev));
     BC_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    // keep room for the kernel's own static LDS
-    size_t usable = v > 1024 ? (size_t)v - 1024 : 0;
+    // keep room for the kernel's own static LDS (wave queues and step variables)
+    const size_t stat = 16 * WQ * 4 + 1024;
+    size_t usable = (size_t)v > stat ? (size_t)v - stat : 0;
     if (usable > 65536) {
         if (hipFuncSetAttribute((const void*)k_resident<1024>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
@@ -407,7 +374,7 @@ int query_limits() {
             hipFuncSetAttribute((const void*)k_resident<256>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess) {
             (void)hipGetLastError();
-            usable = 65536 - 1024;
+            usable = 65536 - stat;
         }
     }
     L.lds = usable;

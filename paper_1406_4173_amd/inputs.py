@@ -258,10 +258,11 @@ def pareto_100k() -> Graph:
 
 
 def smallcut_100k() -> Graph:
-    """Paper regime (small cuts): 100,000 nodes in 5,000 communities of 20, mean degree
-    8 with 99.5% of edges inside a community, weights uniform in {1..4}, |S| = 200."""
+    """Paper regime (small cuts between parts): 100,000 nodes in 2,000 communities of 50,
+    mean degree 8 with 99% of edges inside a community (98% of the nodes in one
+    connected component), weights uniform in {1..4}, |S| = 200."""
     rng = rng_for(SEED_BASE + 5)
-    g = _community_graph(rng, 100000, 5000, 8.0, 0.995, 4, "smallcut_100k")
+    g = _community_graph(rng, 100000, 2000, 8.0, 0.99, 4, "smallcut_100k")
     g.S = np.sort(rng.choice(g.n, 200, replace=False)).astype(np.int32)
     return g
 
