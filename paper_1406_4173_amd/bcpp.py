@@ -324,11 +324,11 @@ class Server:
         self.ns[gid.value] = int(g.n)
         return gid.value
 
-    def submit(self, gid: int, S, ordered: bool = False):
+    def submit(self, gid: int, S, ordered: bool = False, engine_only: bool = False):
         """Returns a ticket, or None when the queue is full (BC_E_AGAIN)."""
         S = _i32a(S)
         t = _u64(0)
-        rc = lib().bc_query_submit(self.h, int(gid), _p(S), S.size, BC_ORDERED if ordered else 0,
+        rc = lib().bc_query_submit(self.h, int(gid), _p(S), S.size, _flags(ordered, engine_only),
                                    ctypes.byref(t))
         if rc == BC_E_AGAIN:
             return None

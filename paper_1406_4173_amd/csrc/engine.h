@@ -157,6 +157,17 @@ int reduce_scores(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups,
                   int32_t n, const int32_t* d_g0, const int32_t* d_g1,
                   const int32_t* d_idx, const uint8_t* d_which, double scale,
                   double* out_dev, bool accumulate);
+// The same in two parts (no synchronisation): reduce_upload copies the groups' score
+// pointers to the device (on s), reduce_launch only enqueues the reduction.
+struct ReducePtrs {
+    const double** pc = nullptr;
+    const double** pi = nullptr;
+    int32_t ngroups = 0;
+};
+int reduce_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, ReducePtrs* R);
+int reduce_launch(hipStream_t s, const ReducePtrs& R, int32_t n, const int32_t* d_g0, const int32_t* d_g1,
+                  const int32_t* d_idx, const uint8_t* d_which, double scale, double* out_dev,
+                  bool accumulate);
 
 }  // namespace bcpp
 
@@ -181,4 +192,16 @@ bool resident_alloc(Arena& a, GroupDesc& G);
 size_t resident_launch_bytes(size_t ngroups);
 // Run the groups to completion (synchronises); BC_E_OVERFLOW if a count reached 2^64.
 int run_resident(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups);
+// The same in two parts for callers that must not block: resident_upload copies the
+// descriptors (host to device, on s) and clears the error word; resident_launch only
+// enqueues kernels, so it can go on a stream with work still pending. After the
+// launch completes, *d_err has ERR_OVERFLOW set if a count reached 2^64.
+struct ResidentLaunch {
+    GroupDesc* d_desc[3] = {nullptr, nullptr, nullptr};
+    int32_t count[3] = {0, 0, 0};
+    size_t lds[3] = {0, 0, 0};
+    uint32_t* d_err = nullptr;
+};
+int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, ResidentLaunch* L);
+int resident_launch(hipStream_t s, const ResidentLaunch& L);
 }  // namespace bcpp

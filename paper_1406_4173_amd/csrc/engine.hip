@@ -992,28 +992,42 @@ int run_groups_prealloc(Arena& a, hipStream_t s, std::vector<GroupDesc>& groups)
     return rc;
 }
 
-int reduce_scores(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, int32_t n,
-                  const int32_t* d_g0, const int32_t* d_g1, const int32_t* d_idx,
-                  const uint8_t* d_which, double scale, double* out_dev, bool accumulate) {
-    if (n <= 0) return BC_OK;
+int reduce_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, ReducePtrs* R) {
     const size_t ng = std::max<size_t>(groups.size(), 1);
     std::vector<const double*> pc(ng, nullptr), pi(ng, nullptr);
     for (size_t g = 0; g < groups.size(); ++g) {
         pc[g] = groups[g].cacc;
         pi[g] = groups[g].cint;
     }
-    const double** d_pc = a.take<const double*>(ng);
-    const double** d_pi = a.take<const double*>(ng);
-    if (!d_pc || !d_pi) return fail(BC_E_NOMEM, "reduce: workspace too small");
-    BC_HIP(hipMemcpyAsync(d_pc, pc.data(), ng * sizeof(void*), hipMemcpyHostToDevice, s));
-    BC_HIP(hipMemcpyAsync(d_pi, pi.data(), ng * sizeof(void*), hipMemcpyHostToDevice, s));
+    R->pc = a.take<const double*>(ng);
+    R->pi = a.take<const double*>(ng);
+    R->ngroups = (int32_t)groups.size();
+    if (!R->pc || !R->pi) return fail(BC_E_NOMEM, "reduce: workspace too small");
+    BC_HIP(hipMemcpyAsync(R->pc, pc.data(), ng * sizeof(void*), hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(R->pi, pi.data(), ng * sizeof(void*), hipMemcpyHostToDevice, s));
+    return BC_OK;
+}
+
+int reduce_launch(hipStream_t s, const ReducePtrs& R, int32_t n, const int32_t* d_g0, const int32_t* d_g1,
+                  const int32_t* d_idx, const uint8_t* d_which, double scale, double* out_dev,
+                  bool accumulate) {
+    if (n <= 0) return BC_OK;
     {
         KTimer kt(BC_K_OTHER, s);
-        hipLaunchKernelGGL(k_reduce, dim3((n + 255) / 256), dim3(256), 0, s, d_pc, d_pi, n, d_g0,
-                           d_g1, d_idx, d_which, 0, (int32_t)groups.size(), scale,
-                           accumulate ? 1 : 0, out_dev);
+        hipLaunchKernelGGL(k_reduce, dim3((n + 255) / 256), dim3(256), 0, s, R.pc, R.pi, n, d_g0, d_g1,
+                           d_idx, d_which, 0, R.ngroups, scale, accumulate ? 1 : 0, out_dev);
     }
     BC_HIP(hipGetLastError());
+    return BC_OK;
+}
+
+int reduce_scores(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, int32_t n,
+                  const int32_t* d_g0, const int32_t* d_g1, const int32_t* d_idx,
+                  const uint8_t* d_which, double scale, double* out_dev, bool accumulate) {
+    if (n <= 0) return BC_OK;
+    ReducePtrs R;
+    BC_TRY(reduce_upload(s, a, groups, &R));
+    BC_TRY(reduce_launch(s, R, n, d_g0, d_g1, d_idx, d_which, scale, out_dev, accumulate));
     BC_HIP(hipStreamSynchronize(s));
     return BC_OK;
 }

@@ -430,45 +430,57 @@ size_t resident_launch_bytes(size_t ngroups) {
     return ngroups * sizeof(GroupDesc) + 4 * 256 + 512;
 }
 
-int run_resident(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups) {
-    if (groups.empty()) return BC_OK;
+int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, ResidentLaunch* L) {
+    *L = ResidentLaunch();
     BC_TRY(query_limits());
     // one launch per size class
     std::vector<GroupDesc> cls[3];
-    size_t lds[3] = {0, 0, 0};
     for (const GroupDesc& G : groups) {
         const int64_t range = (int64_t)G.hi - G.lo;
         const size_t need = lds_bytes(range);
         if (need > limits().lds) return fail(BC_E_INVAL, "resident: node range does not fit in LDS");
         const int c = range <= SMALL_RANGE ? 0 : range <= MID_RANGE ? 1 : 2;
         cls[c].push_back(G);
-        lds[c] = std::max(lds[c], need);
+        L->lds[c] = std::max(L->lds[c], need);
     }
-    uint32_t* d_err = a.take<uint32_t>(1);
-    GroupDesc* d_desc[3];
+    L->d_err = a.take<uint32_t>(1);
+    if (!L->d_err) return fail(BC_E_NOMEM, "resident: workspace too small");
+    BC_HIP(hipMemsetAsync(L->d_err, 0, sizeof(uint32_t), s));
     for (int c = 0; c < 3; ++c) {
-        d_desc[c] = cls[c].empty() ? nullptr : a.take<GroupDesc>(cls[c].size());
-        if (!cls[c].empty() && !d_desc[c]) return fail(BC_E_NOMEM, "resident: workspace too small");
+        L->count[c] = (int32_t)cls[c].size();
+        if (cls[c].empty()) continue;
+        L->d_desc[c] = a.take<GroupDesc>(cls[c].size());
+        if (!L->d_desc[c]) return fail(BC_E_NOMEM, "resident: workspace too small");
+        BC_HIP(hipMemcpyAsync(L->d_desc[c], cls[c].data(), cls[c].size() * sizeof(GroupDesc),
+                              hipMemcpyHostToDevice, s));
     }
-    if (!d_err) return fail(BC_E_NOMEM, "resident: workspace too small");
-    BC_HIP(hipMemsetAsync(d_err, 0, sizeof(uint32_t), s));
+    return BC_OK;
+}
+
+int resident_launch(hipStream_t s, const ResidentLaunch& L) {
     unsigned long long* prof = profiler().on ? profiler().d_bytes : nullptr;
     for (int c = 2; c >= 0; --c) {
-        if (cls[c].empty()) continue;
-        BC_HIP(hipMemcpyAsync(d_desc[c], cls[c].data(), cls[c].size() * sizeof(GroupDesc),
-                              hipMemcpyHostToDevice, s));
+        if (!L.count[c]) continue;
         KTimer kt(BC_K_RESIDENT, s);
-        const dim3 grid((unsigned)cls[c].size());
+        const dim3 grid((unsigned)L.count[c]);
         if (c == 2)
-            hipLaunchKernelGGL(k_resident<1024>, grid, dim3(1024), lds[c], s, d_desc[c], d_err, prof);
+            hipLaunchKernelGGL(k_resident<1024>, grid, dim3(1024), L.lds[c], s, L.d_desc[c], L.d_err, prof);
         else if (c == 1)
-            hipLaunchKernelGGL(k_resident<512>, grid, dim3(512), lds[c], s, d_desc[c], d_err, prof);
+            hipLaunchKernelGGL(k_resident<512>, grid, dim3(512), L.lds[c], s, L.d_desc[c], L.d_err, prof);
         else
-            hipLaunchKernelGGL(k_resident<256>, grid, dim3(256), lds[c], s, d_desc[c], d_err, prof);
+            hipLaunchKernelGGL(k_resident<256>, grid, dim3(256), L.lds[c], s, L.d_desc[c], L.d_err, prof);
     }
     BC_HIP(hipGetLastError());
+    return BC_OK;
+}
+
+int run_resident(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups) {
+    if (groups.empty()) return BC_OK;
+    ResidentLaunch L;
+    BC_TRY(resident_upload(s, a, groups, &L));
+    BC_TRY(resident_launch(s, L));
     uint32_t herr = 0;
-    BC_HIP(hipMemcpyAsync(&herr, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    BC_HIP(hipMemcpyAsync(&herr, L.d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     BC_HIP(hipStreamSynchronize(s));
     if (herr & ERR_OVERFLOW) return fail(BC_E_OVERFLOW, "a shortest-path count reached 2^64");
     return BC_OK;

@@ -80,7 +80,8 @@ struct Block {
     bool live = false;
 };
 
-enum { Q_QUEUED = 0, Q_DSK = 1, Q_BSK = 2, Q_DONE = 3, Q_FAILED = 4 };
+// Q_RES: Brandes_SK + Centrality running as one LDS-resident launch on a side stream
+enum { Q_QUEUED = 0, Q_DSK = 1, Q_BSK = 2, Q_DONE = 3, Q_FAILED = 4, Q_RES = 5 };
 
 struct Query {
     uint64_t ticket = 0;
@@ -97,6 +98,10 @@ struct Query {
     std::vector<GroupDesc> groups;
     Block tmp, store, bsk;
     Arena a_tmp, a_store, a_bsk;
+    // Q_RES: completion event, error word and scores on the device
+    hipEvent_t ev = nullptr;
+    uint32_t* d_err = nullptr;
+    double* d_out = nullptr;
     std::chrono::steady_clock::time_point t_submit, t_done;
 };
 
@@ -135,6 +140,13 @@ struct bc_server {
     GroupDyn* h_dyn = nullptr;
     int32_t slot_hi = 0;  // slots [slot_hi, slot_cap) have never been used
     int run_error = BC_OK;
+    // side streams of the resident launches (round robin), a stream for their result
+    // copies, and the event that orders a launch after its skeleton's assembly
+    static constexpr int NRS = 4;
+    hipStream_t rs[NRS] = {};
+    unsigned rnext = 0;
+    hipStream_t cs = nullptr;
+    hipEvent_t asm_ev = nullptr;
     // host preparation of queries (P', renumbering) runs on its own thread
     std::thread prep_th;
     std::deque<uint64_t> prepared;
@@ -200,7 +212,13 @@ static void release_slots(bc_server* sv, Query* q) {
     q->slots.clear();
 }
 
+static void drop_event(Query* q) {
+    if (q->ev) (void)hipEventDestroy(q->ev);
+    q->ev = nullptr;
+}
+
 static void fail_query(bc_server* sv, Query* q, int code, const std::string& msg) {
+    drop_event(q);
     release_slots(sv, q);
     free_block(sv, q->tmp, q->a_tmp);
     free_block(sv, q->bsk, q->a_bsk);
@@ -215,6 +233,7 @@ static void fail_query(bc_server* sv, Query* q, int code, const std::string& msg
 }
 
 static void finish_query(bc_server* sv, Query* q, std::vector<double>&& res) {
+    drop_event(q);
     release_slots(sv, q);
     free_block(sv, q->tmp, q->a_tmp);
     free_block(sv, q->bsk, q->a_bsk);
@@ -256,6 +275,39 @@ static int start_bsk(bc_server* sv, Query* q, bool* started) {
                 (unsigned long long)q->ticket, sk->n_sk, sk->n_int, (long long)sk->m_arcs, nsrc);
     if (nsrc < 2 || sk->n_sk == 0) {
         finish_query(sv, q, std::vector<double>(n, 0.0));
+        return BC_OK;
+    }
+    if (!(q->flags & BC_ENGINE_ONLY) && sk->n_sk <= resident_max_range()) {
+        // one LDS-resident launch on a side stream; the loop polls its event. Every
+        // host-to-device copy goes on the loop's own stream (idle here), so nothing
+        // below waits for a kernel.
+        std::vector<GroupDesc> groups = resident_bsk_groups(sk);
+        size_t need = resident_launch_bytes(groups.size()) + 2 * (groups.size() * 8 + 256) +
+                      (size_t)n * 8 + 256 + 4096;
+        for (const GroupDesc& G : groups) need += resident_group_bytes(G);
+        if (need > sv->pool.cap) return fail(BC_E_NOMEM, "server: query needs more than the configured budget");
+        if (!alloc_block(sv, need, q->bsk, q->a_bsk)) return BC_E_AGAIN;
+        for (GroupDesc& G : groups)
+            if (!resident_alloc(q->a_bsk, G)) return fail(BC_E_NOMEM, "server: block too small");
+        q->groups = std::move(groups);
+        ResidentLaunch L;
+        ReducePtrs R;
+        BC_TRY(resident_upload(s, q->a_bsk, q->groups, &L));
+        BC_TRY(reduce_upload(s, q->a_bsk, q->groups, &R));
+        q->d_err = L.d_err;
+        q->d_out = q->a_bsk.take<double>(std::max(n, 1));
+        if (!q->d_out) return fail(BC_E_NOMEM, "server: block too small");
+        hipStream_t r = sv->rs[sv->rnext++ % bc_server::NRS];
+        BC_HIP(hipEventRecord(sv->asm_ev, s));
+        BC_HIP(hipStreamWaitEvent(r, sv->asm_ev, 0));
+        BC_TRY(resident_launch(r, L));
+        const double scale = (q->flags & BC_ORDERED) ? 1.0 : 0.5;
+        BC_TRY(reduce_launch(r, R, n, nullptr, nullptr, sk->d_out_idx, sk->d_out_which, scale, q->d_out,
+                             false));
+        BC_HIP(hipEventCreateWithFlags(&q->ev, hipEventDisableTiming));
+        BC_HIP(hipEventRecord(q->ev, r));
+        q->state = Q_RES;
+        *started = true;
         return BC_OK;
     }
     q->groups = bsk_groups(sk, sk->h_src.data(), nsrc, 0, sk->n_sk, 0, sk->n_int);
@@ -316,6 +368,19 @@ static int finish_bsk(bc_server* sv, Query* q) {
         fprintf(stderr, "server: query %llu done, %zu groups, sum %g, nrec0 %d\n",
                 (unsigned long long)q->ticket, q->groups.size(), tot, dy.empty() ? -1 : dy[0].nrec);
     }
+    finish_query(sv, q, std::move(res));
+    return BC_OK;
+}
+
+// A resident launch completed: read its error word and scores.
+static int finish_res(bc_server* sv, Query* q) {
+    const int32_t n = q->sk->n;
+    uint32_t err = 0;
+    std::vector<double> res(n);
+    BC_HIP(hipMemcpyAsync(&err, q->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, sv->cs));
+    BC_HIP(hipMemcpyAsync(res.data(), q->d_out, (size_t)n * 8, hipMemcpyDeviceToHost, sv->cs));
+    BC_HIP(hipStreamSynchronize(sv->cs));
+    if (err & ERR_OVERFLOW) return fail(BC_E_OVERFLOW, "a shortest-path count reached 2^64");
     finish_query(sv, q, std::move(res));
     return BC_OK;
 }
@@ -385,17 +450,31 @@ static void server_loop(bc_server* sv) {
     std::vector<Query*> active;     // admitted, not finished
     std::deque<Query*> waiting;     // not yet admitted
     std::vector<Query*> bsk_wait;   // Dijkstra_SK done, Brandes_SK memory not free yet
+    std::vector<Query*> res_run;    // resident launches in flight
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             if (active.empty() && waiting.empty() && bsk_wait.empty() && sv->prepared.empty() && !sv->stop)
-                sv->cv.wait_for(lk, std::chrono::milliseconds(20));
+                sv->cv.wait_for(lk, res_run.empty() ? std::chrono::microseconds(20000)
+                                                    : std::chrono::microseconds(200));
             if (sv->stop) break;
             while (!sv->prepared.empty()) {
                 auto it = sv->queries.find(sv->prepared.front());
                 sv->prepared.pop_front();
                 if (it != sv->queries.end()) waiting.push_back(it->second.get());
             }
+        }
+        // finished resident launches
+        for (size_t i = 0; i < res_run.size();) {
+            Query* q = res_run[i];
+            const hipError_t e = hipEventQuery(q->ev);
+            if (e == hipErrorNotReady) {
+                ++i;
+                continue;
+            }
+            res_run.erase(res_run.begin() + i);
+            const int rc = e == hipSuccess ? finish_res(sv, q) : fail(BC_E_DEVICE, "server: resident launch failed");
+            if (rc != BC_OK) fail_query(sv, q, rc, bc_last_error());
         }
         // Brandes_SK starts for queries whose skeleton is ready (they go first)
         for (size_t i = 0; i < bsk_wait.size();) {
@@ -410,10 +489,11 @@ static void server_loop(bc_server* sv) {
             if (rc != BC_OK)
                 fail_query(sv, q, rc, bc_last_error());
             else if (started)
-                active.push_back(q);
+                (q->state == Q_RES ? res_run : active).push_back(q);
         }
         // admission of new queries, in arrival order, while memory and slots allow
-        while (bsk_wait.empty() && !waiting.empty() && (int32_t)active.size() < sv->max_inflight) {
+        while (bsk_wait.empty() && !waiting.empty() &&
+               (int32_t)(active.size() + res_run.size()) < sv->max_inflight) {
             Query* q = waiting.front();
             int rc = admit(sv, q);
             if (rc == BC_E_AGAIN) break;
@@ -465,7 +545,7 @@ static void server_loop(bc_server* sv) {
                     bsk_wait.push_back(q);
                     continue;
                 }
-                if (rc == BC_OK && started) started_now.push_back(q);
+                if (rc == BC_OK && started) (q->state == Q_RES ? res_run : started_now).push_back(q);
             } else {
                 rc = finish_bsk(sv, q);
             }
@@ -473,13 +553,17 @@ static void server_loop(bc_server* sv) {
         }
         active.insert(active.end(), started_now.begin(), started_now.end());
         // nothing can make progress: the oldest waiting skeleton cannot get memory
-        if (active.empty() && !bsk_wait.empty()) {
+        if (active.empty() && res_run.empty() && !bsk_wait.empty()) {
             Query* q = bsk_wait.front();
             bsk_wait.erase(bsk_wait.begin());
             fail_query(sv, q, BC_E_NOMEM, "server: Brandes_SK state does not fit the budget");
         }
     }
-    // shut down: fail whatever is left
+    // shut down: let launches in flight end before their memory is released, then fail
+    // whatever is left
+    for (hipStream_t r : sv->rs)
+        if (r) (void)hipStreamSynchronize(r);
+    for (Query* q : res_run) fail_query(sv, q, BC_E_DEVICE, "server stopped");
     for (Query* q : active) fail_query(sv, q, BC_E_DEVICE, "server stopped");
     for (Query* q : bsk_wait) fail_query(sv, q, BC_E_DEVICE, "server stopped");
     for (Query* q : waiting) fail_query(sv, q, BC_E_DEVICE, "server stopped");
@@ -496,11 +580,17 @@ bc_server::~bc_server() {
     if (th.joinable()) th.join();
     if (prep_th.joinable()) prep_th.join();
     if (stream) (void)hipStreamSynchronize(stream);
+    for (hipStream_t r : rs)
+        if (r) (void)hipStreamSynchronize(r);
     engine_mem.release();
     if (d_pool) (void)hipFree(d_pool);
     if (h_dyn) (void)hipHostFree(h_dyn);
     if (eng.h_ctr) (void)hipHostFree(eng.h_ctr);
     graphs.clear();
+    for (hipStream_t r : rs)
+        if (r) (void)hipStreamDestroy(r);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (asm_ev) (void)hipEventDestroy(asm_ev);
     if (stream) (void)hipStreamDestroy(stream);
 }
 
@@ -516,6 +606,9 @@ int bc_server_create(size_t hbm_budget_bytes, int32_t max_inflight, bc_server** 
     sv->max_inflight = max_inflight;
     BC_HIP(hipGetDevice(&sv->device));
     BC_HIP(hipStreamCreate(&sv->stream));
+    for (hipStream_t& r : sv->rs) BC_HIP(hipStreamCreate(&r));
+    BC_HIP(hipStreamCreate(&sv->cs));
+    BC_HIP(hipEventCreateWithFlags(&sv->asm_ev, hipEventDisableTiming));
     // engine: group slots and scan positions sized from the budget
     sv->slot_cap = 4096;
     sv->pos_cap = (int64_t)std::max<size_t>(hbm_budget_bytes / 512, (size_t)1 << 20);
@@ -614,7 +707,8 @@ int bc_server_stats_get(bc_server* s, bc_server_stats* out) {
     out->failed = s->n_failed;
     out->queued = (int64_t)s->incoming.size();
     int64_t inflight = 0;
-    for (auto& kv : s->queries) inflight += (kv.second->state == Q_DSK || kv.second->state == Q_BSK);
+    for (auto& kv : s->queries)
+        inflight += (kv.second->state == Q_DSK || kv.second->state == Q_BSK || kv.second->state == Q_RES);
     out->inflight = inflight;
     out->iterations = s->n_iters;
     std::vector<double> l = s->lat_ms;

@@ -79,5 +79,8 @@ struct SkBuild {
 // [t_lo, t_lo + tn).
 std::vector<GroupDesc> bsk_groups(const bc_skeleton* sk, const int32_t* src, int32_t nsrc,
                                   int32_t lo, int32_t hi, int32_t t_lo, int32_t tn);
+// Brandes_SK + Centrality groups of the whole skeleton for the LDS-resident kernel
+// (resident_sources_per_group sources each, in target order); buffers not yet carved.
+std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk);
 
 }  // namespace bcpp

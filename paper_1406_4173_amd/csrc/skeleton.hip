@@ -547,14 +547,11 @@ std::vector<GroupDesc> bsk_groups(const bc_skeleton* sk, const int32_t* src, int
 
 // --------------------------------------------------------------- Brandes++ -----
 
-// Brandes_SK and Centrality with the LDS-resident kernel: the skeleton fits in LDS.
-static int pp_resident(bc_graph* g, const bc_skeleton* sk, double scale, double* out_dev) {
-    hipStream_t s = g->stream;
+std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk) {
     const int32_t nsrc = (int32_t)sk->h_src.size();
     const int32_t spg = resident_sources_per_group(nsrc);
     const int32_t ngroups = (nsrc + spg - 1) / spg;
     std::vector<GroupDesc> groups(ngroups);
-    size_t need = resident_launch_bytes(ngroups) + 2 * ((size_t)ngroups * 8 + 256) + 65536;
     for (int32_t j = 0; j < ngroups; ++j) {
         GroupDesc& G = groups[j];
         G.g.row_ptr = sk->d_row_ptr;
@@ -574,8 +571,16 @@ static int pp_resident(bc_graph* g, const bc_skeleton* sk, double scale, double*
         const int32_t first = j * spg;
         G.nsrc = std::min(spg, nsrc - first);
         for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? sk->h_src[first + b] : -1;
-        need += resident_group_bytes(G);
     }
+    return groups;
+}
+
+// Brandes_SK and Centrality with the LDS-resident kernel: the skeleton fits in LDS.
+static int pp_resident(bc_graph* g, const bc_skeleton* sk, double scale, double* out_dev) {
+    hipStream_t s = g->stream;
+    std::vector<GroupDesc> groups = resident_bsk_groups(sk);
+    size_t need = resident_launch_bytes(groups.size()) + 2 * (groups.size() * 8 + 256) + 65536;
+    for (const GroupDesc& G : groups) need += resident_group_bytes(G);
     BC_TRY(g->work.reserve(need));
     g->work.used = 0;
     for (GroupDesc& G : groups)

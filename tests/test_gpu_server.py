@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_1406_4173_amd import inputs
 
-from test_gpu_plain import assert_scores
+from test_gpu_plain import PATHS, assert_scores
 
 pytestmark = pytest.mark.gpu
 
@@ -48,12 +48,18 @@ def pool():
     gs = [inputs.random_graph(8100 + i, 60 + 15 * i, 0.06, wmax=[None, 5][i % 2], k=4 + i)
           for i in range(4)]
     gs.append(inputs.planted_1k())
+    # 20,000 nodes with 15,000 cut edges: its skeletons have more nodes than LDS holds,
+    # so its queries run on the engine while the others take the resident kernel
+    big = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 96, 0), inputs.equal_sizes(20000, 40),
+                     4.0 / 499, 15000, 3, "big20k")
+    gs.append(big)
     return gs
 
 
-def test_server_queries_match_oracle_and_alone(bcpp):
+@PATHS
+def test_server_queries_match_oracle_and_alone(bcpp, engine_only):
     gs = pool()
-    srv = bcpp.Server(1 << 30, max_inflight=8)
+    srv = bcpp.Server(2 << 30, max_inflight=8)
     gids = [srv.add_graph(g) for g in gs]
     rng = np.random.default_rng(5)
     queries = []
@@ -65,7 +71,7 @@ def test_server_queries_match_oracle_and_alone(bcpp):
         queries.append((gi, S))
     tickets, ns = [], {}
     for gi, S in queries:
-        t = srv.submit(gids[gi], S)
+        t = srv.submit(gids[gi], S, engine_only=engine_only)
         tickets.append(t)
         ns[t] = gs[gi].n
     res = wait_all(srv, tickets, ns)
@@ -75,7 +81,7 @@ def test_server_queries_match_oracle_and_alone(bcpp):
         assert not isinstance(got, Exception), got
         assert_scores(got, oracle.bc(g, S))
         G = bcpp.Graph(g)
-        alone = bcpp.brandes_pp(G, bcpp.partition_sk(G, g.part, g.k, S))
+        alone = bcpp.brandes_pp(G, bcpp.partition_sk(G, g.part, g.k, S), engine_only=engine_only)
         assert np.array_equal(got, alone)
     st = srv.stats()
     assert st["completed"] == len(queries) and st["failed"] == 0
