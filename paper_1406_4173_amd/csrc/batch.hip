@@ -72,13 +72,13 @@ static int batch_plain(bc_batch* b, uint32_t flags, double* d_out) {
     std::vector<uint8_t> resident;
     std::vector<int32_t> g0(n, 0), g1(n, 0), idx(n, -1);
     int64_t steps = 1;
-    const int64_t rmax = (flags & BC_ENGINE_ONLY) ? 0 : resident_max_range();
+    const bool allow_res = !(flags & BC_ENGINE_ONLY);
     for (int32_t gi = 0; gi < b->ng; ++gi) {
         const int32_t lo = b->n_off[gi], hi = b->n_off[gi + 1];
         const int32_t ns = b->s_off[gi + 1] - b->s_off[gi];
         const int32_t first_group = (int32_t)groups.size();
         if (ns >= 2) {
-            const bool res = hi - lo <= rmax;
+            const bool res = allow_res && resident_takes(hi - lo);
             const int32_t per = res ? resident_sources_per_group(ns) : LANES;
             if (!res) steps = std::max(steps, max_steps_bound(hi - lo, LANES, (int64_t)(hi - lo) * G->maxw));
             for (int32_t c = 0; c < ns; c += per) {
@@ -144,7 +144,7 @@ static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
     std::vector<int32_t> g0(n, 0), g1(n, 0), idx(n, -1);
     std::vector<uint8_t> which(n, 0);
     int64_t steps = 1;
-    const int64_t rmax = (flags & BC_ENGINE_ONLY) ? 0 : resident_max_range();
+    const bool allow_res = !(flags & BC_ENGINE_ONLY);
     for (int32_t gi = 0; gi < b->ng; ++gi) {
         const int32_t lo = b->n_off[gi], hi = b->n_off[gi + 1];
         int32_t sk_lo = INT32_MAX, sk_hi = -1, t_lo = INT32_MAX, t_hi = -1;
@@ -167,7 +167,7 @@ static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
         if (src.size() >= 2 && sk_hi > sk_lo) {
             const int32_t N = sk_hi - sk_lo;
             const int32_t tn = t_hi > t_lo ? t_hi - t_lo : 0;
-            const bool res = N <= rmax;
+            const bool res = allow_res && resident_takes(N);
             const size_t per = res ? (size_t)resident_sources_per_group((int64_t)src.size()) : LANES;
             if (!res) steps = std::max(steps, max_steps_bound(N, LANES, (int64_t)(hi - lo) * G->maxw));
             for (size_t c = 0; c < src.size(); c += per) {

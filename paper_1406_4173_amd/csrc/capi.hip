@@ -282,8 +282,7 @@ int plain_run(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, u
         BC_HIP(hipStreamSynchronize(s));
         return BC_OK;
     }
-    if (!(flags & BC_ENGINE_ONLY) && n <= resident_max_range())
-        return plain_resident(g, S, nS, S_dev, scale, out_dev);
+    if (!(flags & BC_ENGINE_ONLY) && resident_takes(n)) return plain_resident(g, S, nS, S_dev, scale, out_dev);
     const int64_t max_dist = (int64_t)(n - 1) * g->maxw;
     const int64_t steps = max_steps_bound(n, LANES, max_dist);
     const int32_t ngroups = (nS + LANES - 1) / LANES;

@@ -73,6 +73,9 @@ struct GroupDesc {
     int32_t t_lo = 0;        // first table row of this group; rows [t_lo, t_lo + tn)
     int32_t tn = 0;
     double* cint = nullptr;  // [tn] this group's share of the interior scores
+    // resident groups too large for LDS: the one-source state in device memory
+    uint32_t* gdist = nullptr;  // [hi-lo]
+    uint64_t* gsig = nullptr;   // [hi-lo]
     int32_t src[LANES];      // source node ids of g, -1 = unused lane
 };
 
@@ -183,6 +186,10 @@ size_t engine_bytes(int32_t slots, int64_t positions);
 // state, and no other engine buffer is used.
 // Largest node range that fits in LDS (0: kernel unavailable or switched off).
 int64_t resident_max_range();
+// Whether the resident kernel takes a group over `range` nodes: in LDS when it fits,
+// else with the state in device memory. Environment BCPP_RESIDENT=lds keeps larger
+// ranges on the engine, BCPP_RESIDENT=0 every range.
+bool resident_takes(int64_t range);
 // Sources per resident group for a source set of nsrc (a function of nsrc only, so a
 // graph is split the same way alone and inside a batch).
 int32_t resident_sources_per_group(int64_t nsrc);
@@ -198,7 +205,9 @@ int run_resident(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups);
 // launch completes, *d_err has ERR_OVERFLOW set if a count reached 2^64.
 struct ResidentLaunch {
     GroupDesc* d_desc[3] = {nullptr, nullptr, nullptr};
+    GroupDesc* d_gdesc = nullptr;  // groups with their state in device memory
     int32_t count[3] = {0, 0, 0};
+    int32_t gcount = 0;
     size_t lds[3] = {0, 0, 0};
     uint32_t* d_err = nullptr;
 };

@@ -23,6 +23,7 @@
 // graphs this kernel takes, so the only HBM traffic is the first touch of the CSR and
 // the per-group score rows.
 #include <algorithm>
+#include <cstring>
 
 #include "engine.h"
 
@@ -53,12 +54,11 @@ __device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
 // queue wq (128 entries) and hands every full queue of 64, and the last partial one,
 // to body(v, valid) with all lanes converged. A step that settles few nodes thus costs
 // one round of neighbour loads per wave instead of one per scan pass. sel is
-// evaluated for SCAN passes before their nodes are handed on, so it must not depend
+// evaluated for SCAN passes (loads in flight together) before their nodes are handed on, so it must not depend
 // on what body does to other nodes in the same step. The queue is private to the
 // wave, whose LDS accesses complete in order.
-constexpr int SCAN = 4;
 constexpr int WQ = 128;
-template <int T, class Sel, class Body>
+template <int T, int SCAN, class Sel, class Body>
 __device__ __forceinline__ void for_selected(int32_t n, int32_t* __restrict__ wq, Sel&& sel, Body&& body) {
     const int lane = threadIdx.x & 63;
     int cnt = 0;
@@ -129,7 +129,25 @@ __device__ __forceinline__ void for_queue_arcs(const int64_t* __restrict__ rp, i
     }
 }
 
-template <int T>
+// State accessors. With the state in device memory (GLOBAL) the distances and counts
+// change through L2 atomics, so every read goes past the CU's L1 (agent-scope atomic
+// load) and never sees a stale line.
+template <bool GLOBAL>
+__device__ __forceinline__ uint32_t ld_d(uint32_t* p) {
+    if constexpr (GLOBAL)
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *p;
+}
+template <bool GLOBAL>
+__device__ __forceinline__ uint64_t ld_s(uint64_t* p) {
+    if constexpr (GLOBAL)
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *p;
+}
+
+template <int T, bool GLOBAL>
 __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ desc,
                                                 uint32_t* __restrict__ err,
                                                 unsigned long long* __restrict__ prof) {
@@ -145,8 +163,11 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
     int32_t* __restrict__ wq = wqueue[tid >> 6];
     const int32_t lo = G.lo;
     const int32_t n = G.hi - G.lo;
-    uint32_t* __restrict__ dist = reinterpret_cast<uint32_t*>(lds);
-    uint64_t* __restrict__ sig = reinterpret_cast<uint64_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15));
+    uint32_t* __restrict__ dist = GLOBAL ? G.gdist : reinterpret_cast<uint32_t*>(lds);
+    uint64_t* __restrict__ sig =
+        GLOBAL ? G.gsig : reinterpret_cast<uint64_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15));
+    auto D_ = [&](int32_t i) { return ld_d<GLOBAL>(&dist[i]); };
+    auto S_ = [&](int32_t i) { return ld_s<GLOBAL>(&sig[i]); };
     const int64_t* __restrict__ rp = G.g.row_ptr;
     const int32_t* __restrict__ col = G.g.col;
     const uint32_t* __restrict__ len = G.g.len;
@@ -181,10 +202,10 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
         bool ovf = false;
         for (int k = 0;; ++k) {
             uint32_t mn = INF32;
-            for_selected<T>(
+            for_selected<T, GLOBAL ? 8 : 4>(
                 n, wq,
                 [&](int32_t v) {
-                    const uint32_t dv = dist[v];
+                    const uint32_t dv = D_(v);
                     if (dv == D) return true;
                     if (dv > D && dv != INF32) mn = min(mn, dv);
                     return false;
@@ -201,9 +222,9 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
                         // parentsall / eq. multiparents); the count adds in with an atomic,
                         // exact for integers, and a wrap of any addition is an overflow
                         if (v != s && L <= D) {
-                            const uint32_t du = dist[u];
+                            const uint32_t du = D_(u);
                             if (du != INF32 && du + L == D) {
-                                uint64_t x = sig[u];
+                                uint64_t x = S_(u);
                                 if (mult) {
                                     const uint64_t m = mult[e];
                                     if (__umul64hi(x, m) != 0) ovf = true;
@@ -217,7 +238,7 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
                         }
                         // offers: all above D, so they never meet the parent test above
                         const uint32_t nv = D + L;
-                        if (nv < dist[u]) {
+                        if (nv < D_(u)) {
                             const uint32_t old = atomicMin(&dist[u], nv);
                             if (nv < old) mn = min(mn, nv);
                         }
@@ -239,7 +260,7 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
                 const int64_t e0 = G.trow[G.t_lo + i], e1 = G.trow[G.t_lo + i + 1];
                 uint32_t dv = INF32;
                 for (int64_t e = e0; e < e1; ++e) {
-                    const uint32_t tf = dist[G.tcol[e] - lo];
+                    const uint32_t tf = D_(G.tcol[e] - lo);
                     if (tf != INF32) dv = min(dv, tf + G.tlen[e]);
                 }
                 uint64_t sv = 0;
@@ -247,9 +268,9 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
                 if (dv != INF32) {
                     for (int64_t e = e0; e < e1; ++e) {
                         const int32_t f = G.tcol[e] - lo;
-                        const uint32_t tf = dist[f];
+                        const uint32_t tf = D_(f);
                         if (tf == INF32 || tf + G.tlen[e] != dv) continue;
-                        const uint64_t a = sig[f], m = G.tsig[e];
+                        const uint64_t a = S_(f), m = G.tsig[e];
                         if (__umul64hi(a, m) != 0) o2 = true;
                         const uint64_t r = sv + a * m;
                         if (r < sv) o2 = true;
@@ -267,10 +288,10 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
         // ----------------------------------------------------------- backward ----
         for (int k = 0; D > 0; ++k) {
             uint32_t mx = 0;
-            for_selected<T>(
+            for_selected<T, GLOBAL ? 8 : 4>(
                 n, wq,
                 [&](int32_t v) {
-                    const uint32_t dv = dist[v];
+                    const uint32_t dv = D_(v);
                     if (dv == D) return true;
                     if (dv < D) mx = max(mx, dv);
                     return false;
@@ -289,9 +310,9 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
                         if (ok) {
                             const int32_t x = col[e] - lo;
                             const uint32_t L = len ? len[e] : 1u;
-                            const uint32_t dx = dist[x];
+                            const uint32_t dx = D_(x);
                             if (dx != INF32 && dx == D + L) {
-                                c = __longlong_as_double((long long)sig[x]);
+                                c = __longlong_as_double((long long)S_(x));
                                 if (mult) c *= (double)mult[e];
                             }
                         }
@@ -307,7 +328,7 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
                         if (b > a) acc += part;
                     });
                     if (valid) {
-                        const double sv = (double)sig[q];
+                        const double sv = (double)S_(q);
                         const double dl = sv * acc;
                         cacc[q] = prev + dl;
                         sig[q] = (uint64_t)__double_as_longlong((ind + dl) / sv);
@@ -329,9 +350,9 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
                 double acc = 0.0;
                 for (int64_t e = e0; e < e1; ++e) {
                     const int32_t f = G.tcol[e] - lo;
-                    const uint32_t tf = dist[f];
+                    const uint32_t tf = D_(f);
                     if (tf == INF32 || tf != dv + G.tlen[e]) continue;
-                    acc += (double)G.tsig[e] * __longlong_as_double((long long)sig[f]);
+                    acc += (double)G.tsig[e] * __longlong_as_double((long long)S_(f));
                 }
                 G.cint[i] += (double)isig[i] * acc;
             }
@@ -367,11 +388,11 @@ int query_limits() {
     const size_t stat = 16 * WQ * 4 + 1024;
     size_t usable = (size_t)v > stat ? (size_t)v - stat : 0;
     if (usable > 65536) {
-        if (hipFuncSetAttribute((const void*)k_resident<1024>,
+        if (hipFuncSetAttribute((const void*)k_resident<1024, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_resident<512>,
+            hipFuncSetAttribute((const void*)k_resident<512, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_resident<256>,
+            hipFuncSetAttribute((const void*)k_resident<256, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess) {
             (void)hipGetLastError();
             usable = 65536 - stat;
@@ -391,7 +412,7 @@ constexpr int64_t MID_RANGE = 6000;
 
 int64_t resident_max_range() {
     if (const char* e = getenv("BCPP_RESIDENT")) {
-        if (atoi(e) == 0) return 0;
+        if (strcmp(e, "0") == 0) return 0;
     }
     if (query_limits() != BC_OK) return 0;
     const size_t cap = limits().lds;
@@ -404,9 +425,18 @@ int32_t resident_sources_per_group(int64_t nsrc) {
     return (int32_t)std::min<int64_t>(LANES, std::max<int64_t>(1, (nsrc + 1023) / 1024));
 }
 
+bool resident_takes(int64_t range) {
+    const char* e = getenv("BCPP_RESIDENT");
+    if (e && strcmp(e, "0") == 0) return false;
+    if (e && strcmp(e, "lds") == 0) return range <= resident_max_range();
+    return query_limits() == BC_OK;
+}
+
 size_t resident_group_bytes(const GroupDesc& G) {
     const int64_t range = (int64_t)G.hi - G.lo;
     size_t b = ((size_t)range * 8 + 255) & ~(size_t)255;
+    if (range > resident_max_range())
+        b += (((size_t)range * 4 + 255) & ~(size_t)255) + (((size_t)range * 8 + 255) & ~(size_t)255);
     if ((G.flags & GF_CENT) && G.tn > 0)
         b += (((size_t)G.tn * 8 + 255) & ~(size_t)255) * 2 + (((size_t)G.tn * 4 + 255) & ~(size_t)255);
     return b + 256;
@@ -416,6 +446,11 @@ bool resident_alloc(Arena& a, GroupDesc& G) {
     const int64_t range = (int64_t)G.hi - G.lo;
     G.cacc = a.take<double>((size_t)std::max<int64_t>(range, 1));
     if (!G.cacc) return false;
+    if (range > resident_max_range()) {
+        G.gdist = a.take<uint32_t>((size_t)range);
+        G.gsig = a.take<uint64_t>((size_t)range);
+        if (!G.gdist || !G.gsig) return false;
+    }
     if ((G.flags & GF_CENT) && G.tn > 0) {
         G.cint = a.take<double>((size_t)G.tn);
         G.dist = a.take<uint32_t>((size_t)G.tn);
@@ -426,22 +461,33 @@ bool resident_alloc(Arena& a, GroupDesc& G) {
 }
 
 size_t resident_launch_bytes(size_t ngroups) {
-    // descriptors of up to three launches and the error word, each rounded to 256 B
-    return ngroups * sizeof(GroupDesc) + 4 * 256 + 512;
+    // descriptors of up to four launches and the error word, each rounded to 256 B
+    return ngroups * sizeof(GroupDesc) + 5 * 256 + 512;
 }
 
 int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, ResidentLaunch* L) {
     *L = ResidentLaunch();
     BC_TRY(query_limits());
     // one launch per size class
-    std::vector<GroupDesc> cls[3];
+    std::vector<GroupDesc> cls[3], glob;
     for (const GroupDesc& G : groups) {
         const int64_t range = (int64_t)G.hi - G.lo;
         const size_t need = lds_bytes(range);
-        if (need > limits().lds) return fail(BC_E_INVAL, "resident: node range does not fit in LDS");
+        if (need > limits().lds) {
+            if (!G.gdist || !G.gsig) return fail(BC_E_INVAL, "resident: no state buffers for a large range");
+            glob.push_back(G);
+            continue;
+        }
         const int c = range <= SMALL_RANGE ? 0 : range <= MID_RANGE ? 1 : 2;
         cls[c].push_back(G);
         L->lds[c] = std::max(L->lds[c], need);
+    }
+    L->gcount = (int32_t)glob.size();
+    if (!glob.empty()) {
+        L->d_gdesc = a.take<GroupDesc>(glob.size());
+        if (!L->d_gdesc) return fail(BC_E_NOMEM, "resident: workspace too small");
+        BC_HIP(hipMemcpyAsync(L->d_gdesc, glob.data(), glob.size() * sizeof(GroupDesc),
+                              hipMemcpyHostToDevice, s));
     }
     L->d_err = a.take<uint32_t>(1);
     if (!L->d_err) return fail(BC_E_NOMEM, "resident: workspace too small");
@@ -459,16 +505,24 @@ int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& group
 
 int resident_launch(hipStream_t s, const ResidentLaunch& L) {
     unsigned long long* prof = profiler().on ? profiler().d_bytes : nullptr;
+    if (L.gcount) {
+        KTimer kt(BC_K_RESIDENT, s);
+        hipLaunchKernelGGL((k_resident<1024, true>), dim3((unsigned)L.gcount), dim3(1024), 0, s, L.d_gdesc,
+                           L.d_err, prof);
+    }
     for (int c = 2; c >= 0; --c) {
         if (!L.count[c]) continue;
         KTimer kt(BC_K_RESIDENT, s);
         const dim3 grid((unsigned)L.count[c]);
         if (c == 2)
-            hipLaunchKernelGGL(k_resident<1024>, grid, dim3(1024), L.lds[c], s, L.d_desc[c], L.d_err, prof);
+            hipLaunchKernelGGL((k_resident<1024, false>), grid, dim3(1024), L.lds[c], s, L.d_desc[c], L.d_err,
+                               prof);
         else if (c == 1)
-            hipLaunchKernelGGL(k_resident<512>, grid, dim3(512), L.lds[c], s, L.d_desc[c], L.d_err, prof);
+            hipLaunchKernelGGL((k_resident<512, false>), grid, dim3(512), L.lds[c], s, L.d_desc[c], L.d_err,
+                               prof);
         else
-            hipLaunchKernelGGL(k_resident<256>, grid, dim3(256), L.lds[c], s, L.d_desc[c], L.d_err, prof);
+            hipLaunchKernelGGL((k_resident<256, false>), grid, dim3(256), L.lds[c], s, L.d_desc[c], L.d_err,
+                               prof);
     }
     BC_HIP(hipGetLastError());
     return BC_OK;

@@ -277,7 +277,7 @@ static int start_bsk(bc_server* sv, Query* q, bool* started) {
         finish_query(sv, q, std::vector<double>(n, 0.0));
         return BC_OK;
     }
-    if (!(q->flags & BC_ENGINE_ONLY) && sk->n_sk <= resident_max_range()) {
+    if (!(q->flags & BC_ENGINE_ONLY) && resident_takes(sk->n_sk)) {
         // one LDS-resident launch on a side stream; the loop polls its event. Every
         // host-to-device copy goes on the loop's own stream (idle here), so nothing
         // below waits for a kernel.

@@ -603,7 +603,7 @@ int pp_run(const bc_graph* gc, const bc_skeleton* sk, uint32_t flags, double* ou
         return BC_OK;
     }
     const int32_t N = sk->n_sk;
-    if (!(flags & BC_ENGINE_ONLY) && N <= resident_max_range()) return pp_resident(g, sk, scale, out_dev);
+    if (!(flags & BC_ENGINE_ONLY) && resident_takes(N)) return pp_resident(g, sk, scale, out_dev);
     const int64_t steps = max_steps_bound(N, LANES, sk->max_dist);
     const int32_t ngroups = (nsrc + LANES - 1) / LANES;
     const uint32_t gflags = GF_BACKWARD | (sk->n_int ? GF_CENT : 0u);
