@@ -32,14 +32,21 @@ namespace bcpp {
 // list keeps its order (each graph's groups contiguous) for the reduction.
 static int run_mixed(Arena& W, hipStream_t s, std::vector<GroupDesc>& groups,
                      const std::vector<uint8_t>& resident, int64_t steps) {
-    std::vector<GroupDesc> E, R;
-    for (size_t i = 0; i < groups.size(); ++i) (resident[i] ? R : E).push_back(groups[i]);
-    for (GroupDesc& D : R)
-        if (!resident_alloc(W, D)) return fail(BC_E_NOMEM, "batch: workspace too small");
-    if (!R.empty()) BC_TRY(run_resident(s, W, R));
+    std::vector<GroupDesc> E;
+    std::vector<const GroupDesc*> R;
+    for (size_t i = 0; i < groups.size(); ++i) {
+        if (!resident[i]) {
+            E.push_back(groups[i]);
+            continue;
+        }
+        if (!resident_alloc(W, groups[i])) return fail(BC_E_NOMEM, "batch: workspace too small");
+        R.push_back(&groups[i]);
+    }
+    if (!R.empty()) BC_TRY(run_resident(s, W, R.data(), R.size()));
     if (!E.empty()) BC_TRY(run_groups(W, s, E, steps));
-    size_t e = 0, r = 0;
-    for (size_t i = 0; i < groups.size(); ++i) groups[i] = resident[i] ? R[r++] : E[e++];
+    size_t e = 0;
+    for (size_t i = 0; i < groups.size(); ++i)
+        if (!resident[i]) groups[i] = E[e++];
     return BC_OK;
 }
 
@@ -70,6 +77,8 @@ static int batch_plain(bc_batch* b, uint32_t flags, double* d_out) {
     const int32_t n = G->n;
     std::vector<GroupDesc> groups;
     std::vector<uint8_t> resident;
+    groups.reserve(b->S_all.size() + (size_t)b->ng);
+    resident.reserve(b->S_all.size() + (size_t)b->ng);
     std::vector<int32_t> g0(n, 0), g1(n, 0), idx(n, -1);
     int64_t steps = 1;
     const bool allow_res = !(flags & BC_ENGINE_ONLY);
@@ -133,14 +142,18 @@ static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
     bc_graph* G = b->G;
     hipStream_t s = G->stream;
     const int32_t n = G->n;
+    PhaseTrace tr("batch Brandes++");
     bc_skeleton* skp = nullptr;
     BC_TRY(partition_impl(G, b->lab.data(), b->nlab, b->S_all.data(), (int32_t)b->S_all.size(), &skp,
                           true));
+    tr.mark("partition");
     std::unique_ptr<bc_skeleton> sk(skp);
     const auto& oi = sk->h_out_idx;
     const auto& ow = sk->h_out_which;
     std::vector<GroupDesc> groups;
     std::vector<uint8_t> resident;
+    groups.reserve(b->S_all.size() + (size_t)b->ng);
+    resident.reserve(b->S_all.size() + (size_t)b->ng);
     std::vector<int32_t> g0(n, 0), g1(n, 0), idx(n, -1);
     std::vector<uint8_t> which(n, 0);
     int64_t steps = 1;
@@ -218,8 +231,11 @@ static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
     BC_HIP(hipMemcpyAsync(d_g1, g1.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
     BC_HIP(hipMemcpyAsync(d_idx, idx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
     BC_HIP(hipMemcpyAsync(d_which, which.data(), n, hipMemcpyHostToDevice, s));
+    tr.mark("groups");
     BC_TRY(run_mixed(W, s, groups, resident, steps));
+    tr.mark("Brandes_SK");
     BC_TRY(reduce_scores(s, W, groups, n, d_g0, d_g1, d_idx, d_which, 0.5, d_out, false));
+    tr.mark("reduce");
     return BC_OK;
 }
 
@@ -299,7 +315,9 @@ int bc_batch_run(bc_batch* b, uint32_t flags, double* const* bc_out) {
     if (n == 0) return BC_OK;
     BC_TRY(G->out.reserve((size_t)n * 8 + 256));
     double* d_out = G->out.take<double>(n);
+    PhaseTrace tr("batch run");
     BC_TRY((flags & BC_BATCH_PP) ? batch_pp(b, flags, d_out) : batch_plain(b, flags, d_out));
+    tr.mark("traversal");
     std::vector<double> all(n);
     BC_HIP(hipMemcpyAsync(all.data(), d_out, (size_t)n * 8, hipMemcpyDeviceToHost, G->stream));
     BC_HIP(hipStreamSynchronize(G->stream));
@@ -308,6 +326,7 @@ int bc_batch_run(bc_batch* b, uint32_t flags, double* const* bc_out) {
         if (!bc_out[i]) continue;
         for (int32_t v = b->n_off[i]; v < b->n_off[i + 1]; ++v) bc_out[i][v - b->n_off[i]] = all[v] * scale;
     }
+    tr.mark("copy out");
     return BC_OK;
 }
 

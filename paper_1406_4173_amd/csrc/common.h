@@ -3,9 +3,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
+#include <algorithm>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/bcpp.h"
@@ -125,6 +129,52 @@ struct Profiler {
 };
 
 Profiler& profiler();
+
+// Host phase trace (environment BCPP_TRACE=1): wall-clock time of named host phases,
+// printed to stderr; off by default and free when off.
+struct PhaseTrace {
+    bool on;
+    const char* what;
+    std::chrono::steady_clock::time_point t0;
+    explicit PhaseTrace(const char* w) : on(trace_on()), what(w) {
+        if (on) t0 = std::chrono::steady_clock::now();
+    }
+    void mark(const char* phase) {
+        if (!on) return;
+        const auto t = std::chrono::steady_clock::now();
+        fprintf(stderr, "[bcpp] %s: %s %.3f ms\n", what, phase,
+                std::chrono::duration<double, std::milli>(t - t0).count());
+        t0 = t;
+    }
+    static bool trace_on() {
+        static const int v = [] {
+            const char* e = getenv("BCPP_TRACE");
+            return e && e[0] == '1';
+        }();
+        return v != 0;
+    }
+};
+
+// Run f(begin, end) over [0, n) split into contiguous chunks on up to 16 host threads
+// (one chunk per thread, at least `grain` items each); serial when n is small.
+template <class F>
+void parallel_for(int64_t n, int64_t grain, F&& f) {
+    const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+    const int64_t T = std::min<int64_t>({hw, (int64_t)16, (n + grain - 1) / std::max<int64_t>(grain, 1)});
+    if (T <= 1) {
+        if (n > 0) f((int64_t)0, n);
+        return;
+    }
+    const int64_t chunk = (n + T - 1) / T;
+    std::vector<std::thread> th;
+    th.reserve((size_t)T);
+    for (int64_t t = 0; t < T; ++t) {
+        const int64_t a = t * chunk, b = std::min(n, a + chunk);
+        if (a >= b) break;
+        th.emplace_back([&f, a, b] { f(a, b); });
+    }
+    for (auto& x : th) x.join();
+}
 
 // Scoped launch timer: records events around the launches in its scope when on.
 struct KTimer {

@@ -199,18 +199,24 @@ bool resident_alloc(Arena& a, GroupDesc& G);
 size_t resident_launch_bytes(size_t ngroups);
 // Run the groups to completion (synchronises); BC_E_OVERFLOW if a count reached 2^64.
 int run_resident(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups);
-// The same in two parts for callers that must not block: resident_upload copies the
-// descriptors (host to device, on s) and clears the error word; resident_launch only
-// enqueues kernels, so it can go on a stream with work still pending. After the
-// launch completes, *d_err has ERR_OVERFLOW set if a count reached 2^64.
+int run_resident(hipStream_t s, Arena& a, const GroupDesc* const* groups, size_t n);
+// The same in two parts for callers that must not block: resident_upload copies
+// compact launch records (host to device, on s) and clears the error word;
+// resident_launch only enqueues kernels, so it can go on a stream with work still
+// pending. After the launch completes, *d_err has ERR_OVERFLOW set if a count reached
+// 2^64. Classes 0-2 hold the state in LDS (256, 512, 1024 threads), class 3 in device
+// memory.
+struct RGroup;
+struct RCtx;
 struct ResidentLaunch {
-    GroupDesc* d_desc[3] = {nullptr, nullptr, nullptr};
-    GroupDesc* d_gdesc = nullptr;  // groups with their state in device memory
-    int32_t count[3] = {0, 0, 0};
-    int32_t gcount = 0;
-    size_t lds[3] = {0, 0, 0};
+    RGroup* d_rg[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t count[4] = {0, 0, 0, 0};
+    size_t lds[4] = {0, 0, 0, 0};
+    const RCtx* d_ctx = nullptr;
+    const int32_t* d_src = nullptr;
     uint32_t* d_err = nullptr;
 };
 int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, ResidentLaunch* L);
+int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, size_t n, ResidentLaunch* L);
 int resident_launch(hipStream_t s, const ResidentLaunch& L);
 }  // namespace bcpp

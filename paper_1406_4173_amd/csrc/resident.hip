@@ -24,6 +24,7 @@
 // the per-group score rows.
 #include <algorithm>
 #include <cstring>
+#include <map>
 
 #include "engine.h"
 
@@ -129,6 +130,33 @@ __device__ __forceinline__ void for_queue_arcs(const int64_t* __restrict__ rp, i
     }
 }
 
+}  // namespace
+
+// Compact launch records: a group (node range, its sources in a shared array, its
+// score rows) and the graph it runs on, stored once for all groups over that graph.
+struct RCtx {
+    EGraph g;
+    const int64_t* trow;
+    const int32_t* tcol;
+    const uint32_t* tlen;
+    const uint64_t* tsig;
+};
+struct RGroup {
+    int32_t ctx, lo, hi, nsrc;
+    int32_t t_lo, tn;
+    uint32_t flags;
+    int32_t pad;
+    int64_t src_off;
+    double* cacc;
+    double* cint;
+    uint32_t* idist;  // [tn] interior d(s,v) of the current source
+    uint64_t* isig;   // [tn] interior sigma(s,v) of the current source
+    uint32_t* gdist;  // [hi-lo] one-source state in device memory (ranges beyond LDS)
+    uint64_t* gsig;
+};
+
+namespace {
+
 // State accessors. With the state in device memory (GLOBAL) the distances and counts
 // change through L2 atomics, so every read goes past the CU's L1 (agent-scope atomic
 // load) and never sees a stale line.
@@ -148,7 +176,9 @@ __device__ __forceinline__ uint64_t ld_s(uint64_t* p) {
 }
 
 template <int T, bool GLOBAL>
-__global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ desc,
+__global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
+                                                const RCtx* __restrict__ ctxs,
+                                                const int32_t* __restrict__ srcs,
                                                 uint32_t* __restrict__ err,
                                                 unsigned long long* __restrict__ prof) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -157,36 +187,37 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
     __shared__ uint32_t ovf_flag;
     __shared__ int32_t wqueue[T / 64][WQ];
 
-    const GroupDesc& G = desc[blockIdx.x];
+    const RGroup& R = rgs[blockIdx.x];
+    const RCtx& C = ctxs[R.ctx];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     int32_t* __restrict__ wq = wqueue[tid >> 6];
-    const int32_t lo = G.lo;
-    const int32_t n = G.hi - G.lo;
-    uint32_t* __restrict__ dist = GLOBAL ? G.gdist : reinterpret_cast<uint32_t*>(lds);
+    const int32_t lo = R.lo;
+    const int32_t n = R.hi - R.lo;
+    uint32_t* __restrict__ dist = GLOBAL ? R.gdist : reinterpret_cast<uint32_t*>(lds);
     uint64_t* __restrict__ sig =
-        GLOBAL ? G.gsig : reinterpret_cast<uint64_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15));
+        GLOBAL ? R.gsig : reinterpret_cast<uint64_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15));
     auto D_ = [&](int32_t i) { return ld_d<GLOBAL>(&dist[i]); };
     auto S_ = [&](int32_t i) { return ld_s<GLOBAL>(&sig[i]); };
-    const int64_t* __restrict__ rp = G.g.row_ptr;
-    const int32_t* __restrict__ col = G.g.col;
-    const uint32_t* __restrict__ len = G.g.len;
-    const uint64_t* __restrict__ mult = G.g.mult;
-    const uint8_t* __restrict__ nflag = G.g.nflag;
-    const bool cent = (G.flags & GF_CENT) != 0 && G.tn > 0;
-    double* __restrict__ cacc = G.cacc;
+    const int64_t* __restrict__ rp = C.g.row_ptr;
+    const int32_t* __restrict__ col = C.g.col;
+    const uint32_t* __restrict__ len = C.g.len;
+    const uint64_t* __restrict__ mult = C.g.mult;
+    const uint8_t* __restrict__ nflag = C.g.nflag;
+    const bool cent = (R.flags & GF_CENT) != 0 && R.tn > 0;
+    double* __restrict__ cacc = R.cacc;
     // interior scratch of the current source: d(s,v) and sigma(s,v) per table row
-    uint32_t* __restrict__ idist = G.dist;
-    uint64_t* __restrict__ isig = G.sigma;
+    uint32_t* __restrict__ idist = R.idist;
+    uint64_t* __restrict__ isig = R.isig;
 
     for (int32_t v = tid; v < n; v += T) cacc[v] = 0.0;
     if (cent)
-        for (int32_t i = tid; i < G.tn; i += T) G.cint[i] = 0.0;
+        for (int32_t i = tid; i < R.tn; i += T) R.cint[i] = 0.0;
     unsigned long long bytes = 0;
     if (tid == 0) ovf_flag = 0u;  // ordered before any use by the barrier below
 
-    for (int b = 0; b < G.nsrc; ++b) {
-        const int32_t s = G.src[b] - lo;
+    for (int b = 0; b < R.nsrc; ++b) {
+        const int32_t s = srcs[R.src_off + b] - lo;
         for (int32_t v = tid; v < n; v += T) {
             dist[v] = (v == s) ? 0u : INF32;
             sig[v] = (v == s) ? 1ull : 0ull;
@@ -256,21 +287,21 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
 
         // ------------------------------------------- interior rows: d and sigma ----
         if (cent) {
-            for (int32_t i = tid; i < G.tn; i += T) {
-                const int64_t e0 = G.trow[G.t_lo + i], e1 = G.trow[G.t_lo + i + 1];
+            for (int32_t i = tid; i < R.tn; i += T) {
+                const int64_t e0 = C.trow[R.t_lo + i], e1 = C.trow[R.t_lo + i + 1];
                 uint32_t dv = INF32;
                 for (int64_t e = e0; e < e1; ++e) {
-                    const uint32_t tf = D_(G.tcol[e] - lo);
-                    if (tf != INF32) dv = min(dv, tf + G.tlen[e]);
+                    const uint32_t tf = D_(C.tcol[e] - lo);
+                    if (tf != INF32) dv = min(dv, tf + C.tlen[e]);
                 }
                 uint64_t sv = 0;
                 bool o2 = false;
                 if (dv != INF32) {
                     for (int64_t e = e0; e < e1; ++e) {
-                        const int32_t f = G.tcol[e] - lo;
+                        const int32_t f = C.tcol[e] - lo;
                         const uint32_t tf = D_(f);
-                        if (tf == INF32 || tf + G.tlen[e] != dv) continue;
-                        const uint64_t a = S_(f), m = G.tsig[e];
+                        if (tf == INF32 || tf + C.tlen[e] != dv) continue;
+                        const uint64_t a = S_(f), m = C.tsig[e];
                         if (__umul64hi(a, m) != 0) o2 = true;
                         const uint64_t r = sv + a * m;
                         if (r < sv) o2 = true;
@@ -343,18 +374,18 @@ __global__ void __launch_bounds__(T) k_resident(const GroupDesc* __restrict__ de
 
         // --------------------------------------------- interior rows: delta ----
         if (cent) {
-            for (int32_t i = tid; i < G.tn; i += T) {
+            for (int32_t i = tid; i < R.tn; i += T) {
                 const uint32_t dv = idist[i];
                 if (dv == INF32) continue;
-                const int64_t e0 = G.trow[G.t_lo + i], e1 = G.trow[G.t_lo + i + 1];
+                const int64_t e0 = C.trow[R.t_lo + i], e1 = C.trow[R.t_lo + i + 1];
                 double acc = 0.0;
                 for (int64_t e = e0; e < e1; ++e) {
-                    const int32_t f = G.tcol[e] - lo;
+                    const int32_t f = C.tcol[e] - lo;
                     const uint32_t tf = D_(f);
-                    if (tf == INF32 || tf != dv + G.tlen[e]) continue;
-                    acc += (double)G.tsig[e] * __longlong_as_double((long long)S_(f));
+                    if (tf == INF32 || tf != dv + C.tlen[e]) continue;
+                    acc += (double)C.tsig[e] * __longlong_as_double((long long)S_(f));
                 }
-                G.cint[i] += (double)isig[i] * acc;
+                R.cint[i] += (double)isig[i] * acc;
             }
         }
         __syncthreads();
@@ -461,83 +492,119 @@ bool resident_alloc(Arena& a, GroupDesc& G) {
 }
 
 size_t resident_launch_bytes(size_t ngroups) {
-    // descriptors of up to four launches and the error word, each rounded to 256 B
-    return ngroups * sizeof(GroupDesc) + 5 * 256 + 512;
+    // records, contexts and sources of up to five uploads, each rounded to 256 B
+    return ngroups * (sizeof(RGroup) + sizeof(RCtx) + LANES * 4) + 8 * 256 + 512;
 }
 
-int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, ResidentLaunch* L) {
+int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, size_t ng, ResidentLaunch* L) {
     *L = ResidentLaunch();
     BC_TRY(query_limits());
-    // one launch per size class
-    std::vector<GroupDesc> cls[3], glob;
-    for (const GroupDesc& G : groups) {
+    // one launch per size class; class 3 keeps its state in device memory
+    std::vector<RGroup> cls[4];
+    std::vector<RCtx> ctx;
+    std::vector<int32_t> src;
+    std::map<std::pair<const void*, const void*>, int32_t> ctx_of;
+    for (size_t i = 0; i < ng; ++i) {
+        const GroupDesc& G = *groups[i];
         const int64_t range = (int64_t)G.hi - G.lo;
         const size_t need = lds_bytes(range);
+        int c;
         if (need > limits().lds) {
             if (!G.gdist || !G.gsig) return fail(BC_E_INVAL, "resident: no state buffers for a large range");
-            glob.push_back(G);
-            continue;
+            c = 3;
+        } else {
+            c = range <= SMALL_RANGE ? 0 : range <= MID_RANGE ? 1 : 2;
+            L->lds[c] = std::max(L->lds[c], need);
         }
-        const int c = range <= SMALL_RANGE ? 0 : range <= MID_RANGE ? 1 : 2;
-        cls[c].push_back(G);
-        L->lds[c] = std::max(L->lds[c], need);
-    }
-    L->gcount = (int32_t)glob.size();
-    if (!glob.empty()) {
-        L->d_gdesc = a.take<GroupDesc>(glob.size());
-        if (!L->d_gdesc) return fail(BC_E_NOMEM, "resident: workspace too small");
-        BC_HIP(hipMemcpyAsync(L->d_gdesc, glob.data(), glob.size() * sizeof(GroupDesc),
-                              hipMemcpyHostToDevice, s));
+        const auto key = std::make_pair((const void*)G.g.row_ptr, (const void*)G.trow);
+        auto it = ctx_of.find(key);
+        if (it == ctx_of.end()) {
+            it = ctx_of.emplace(key, (int32_t)ctx.size()).first;
+            ctx.push_back(RCtx{G.g, G.trow, G.tcol, G.tlen, G.tsig});
+        }
+        RGroup r{};
+        r.ctx = it->second;
+        r.lo = G.lo;
+        r.hi = G.hi;
+        r.nsrc = G.nsrc;
+        r.t_lo = G.t_lo;
+        r.tn = G.tn;
+        r.flags = G.flags;
+        r.src_off = (int64_t)src.size();
+        src.insert(src.end(), G.src, G.src + G.nsrc);
+        r.cacc = G.cacc;
+        r.cint = G.cint;
+        r.idist = G.dist;
+        r.isig = G.sigma;
+        r.gdist = G.gdist;
+        r.gsig = G.gsig;
+        cls[c].push_back(r);
     }
     L->d_err = a.take<uint32_t>(1);
-    if (!L->d_err) return fail(BC_E_NOMEM, "resident: workspace too small");
+    RCtx* d_ctx = a.take<RCtx>(std::max<size_t>(ctx.size(), 1));
+    int32_t* d_src = a.take<int32_t>(std::max<size_t>(src.size(), 1));
+    if (!L->d_err || !d_ctx || !d_src) return fail(BC_E_NOMEM, "resident: workspace too small");
     BC_HIP(hipMemsetAsync(L->d_err, 0, sizeof(uint32_t), s));
-    for (int c = 0; c < 3; ++c) {
+    if (!ctx.empty()) BC_HIP(hipMemcpyAsync(d_ctx, ctx.data(), ctx.size() * sizeof(RCtx), hipMemcpyHostToDevice, s));
+    if (!src.empty()) BC_HIP(hipMemcpyAsync(d_src, src.data(), src.size() * 4, hipMemcpyHostToDevice, s));
+    L->d_ctx = d_ctx;
+    L->d_src = d_src;
+    for (int c = 0; c < 4; ++c) {
         L->count[c] = (int32_t)cls[c].size();
         if (cls[c].empty()) continue;
-        L->d_desc[c] = a.take<GroupDesc>(cls[c].size());
-        if (!L->d_desc[c]) return fail(BC_E_NOMEM, "resident: workspace too small");
-        BC_HIP(hipMemcpyAsync(L->d_desc[c], cls[c].data(), cls[c].size() * sizeof(GroupDesc),
-                              hipMemcpyHostToDevice, s));
+        L->d_rg[c] = a.take<RGroup>(cls[c].size());
+        if (!L->d_rg[c]) return fail(BC_E_NOMEM, "resident: workspace too small");
+        BC_HIP(hipMemcpyAsync(L->d_rg[c], cls[c].data(), cls[c].size() * sizeof(RGroup), hipMemcpyHostToDevice,
+                              s));
     }
     return BC_OK;
 }
 
+int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, ResidentLaunch* L) {
+    std::vector<const GroupDesc*> ptr(groups.size());
+    for (size_t i = 0; i < groups.size(); ++i) ptr[i] = &groups[i];
+    return resident_upload(s, a, ptr.data(), ptr.size(), L);
+}
+
 int resident_launch(hipStream_t s, const ResidentLaunch& L) {
     unsigned long long* prof = profiler().on ? profiler().d_bytes : nullptr;
-    if (L.gcount) {
-        KTimer kt(BC_K_RESIDENT, s);
-        hipLaunchKernelGGL((k_resident<1024, true>), dim3((unsigned)L.gcount), dim3(1024), 0, s, L.d_gdesc,
-                           L.d_err, prof);
-    }
-    for (int c = 2; c >= 0; --c) {
+    for (int c = 3; c >= 0; --c) {
         if (!L.count[c]) continue;
         KTimer kt(BC_K_RESIDENT, s);
         const dim3 grid((unsigned)L.count[c]);
-        if (c == 2)
-            hipLaunchKernelGGL((k_resident<1024, false>), grid, dim3(1024), L.lds[c], s, L.d_desc[c], L.d_err,
-                               prof);
+        if (c == 3)
+            hipLaunchKernelGGL((k_resident<1024, true>), grid, dim3(1024), 0, s, L.d_rg[c], L.d_ctx, L.d_src,
+                               L.d_err, prof);
+        else if (c == 2)
+            hipLaunchKernelGGL((k_resident<1024, false>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
+                               L.d_src, L.d_err, prof);
         else if (c == 1)
-            hipLaunchKernelGGL((k_resident<512, false>), grid, dim3(512), L.lds[c], s, L.d_desc[c], L.d_err,
-                               prof);
+            hipLaunchKernelGGL((k_resident<512, false>), grid, dim3(512), L.lds[c], s, L.d_rg[c], L.d_ctx,
+                               L.d_src, L.d_err, prof);
         else
-            hipLaunchKernelGGL((k_resident<256, false>), grid, dim3(256), L.lds[c], s, L.d_desc[c], L.d_err,
-                               prof);
+            hipLaunchKernelGGL((k_resident<256, false>), grid, dim3(256), L.lds[c], s, L.d_rg[c], L.d_ctx,
+                               L.d_src, L.d_err, prof);
     }
     BC_HIP(hipGetLastError());
     return BC_OK;
 }
 
-int run_resident(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups) {
-    if (groups.empty()) return BC_OK;
+int run_resident(hipStream_t s, Arena& a, const GroupDesc* const* groups, size_t ng) {
+    if (ng == 0) return BC_OK;
     ResidentLaunch L;
-    BC_TRY(resident_upload(s, a, groups, &L));
+    BC_TRY(resident_upload(s, a, groups, ng, &L));
     BC_TRY(resident_launch(s, L));
     uint32_t herr = 0;
     BC_HIP(hipMemcpyAsync(&herr, L.d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     BC_HIP(hipStreamSynchronize(s));
     if (herr & ERR_OVERFLOW) return fail(BC_E_OVERFLOW, "a shortest-path count reached 2^64");
     return BC_OK;
+}
+
+int run_resident(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups) {
+    std::vector<const GroupDesc*> ptr(groups.size());
+    for (size_t i = 0; i < groups.size(); ++i) ptr[i] = &groups[i];
+    return run_resident(s, a, ptr.data(), ptr.size());
 }
 
 }  // namespace bcpp

@@ -146,6 +146,7 @@ __global__ void k_table(const GroupDesc* __restrict__ desc, const DskInfo* __res
 
 int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const int32_t* Sx,
                      int32_t nS, bool given_singletons) {
+    PhaseTrace tr("prepare");
     g = gr;
     n = g->n;
     if (n > 0 && !part) return fail(BC_E_INVAL, "null partition");
@@ -169,12 +170,15 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
         is_t[S[i]] = 1;
     }
     fr.assign(n, 0);
-    for (int32_t v = 0; v < n; ++v)
-        for (int64_t e = rp[v]; e < rp[v + 1]; ++e)
-            if (lab[cl[e]] != lab[v]) {
-                fr[v] = 1;
-                break;
-            }
+    parallel_for(n, 16384, [&](int64_t a, int64_t b) {
+        for (int64_t v = a; v < b; ++v)
+            for (int64_t e = rp[v]; e < rp[v + 1]; ++e)
+                if (lab[cl[e]] != lab[v]) {
+                    fr[v] = 1;
+                    break;
+                }
+    });
+    tr.mark("validate, P', frontiers");
     // ---- renumbering: parts contiguous, frontier first
     psize.assign(nlab + 1, 0);
     pnf.assign(nlab, 0);
@@ -204,50 +208,59 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
     nsk = (int32_t)fbase[nlab];
     auto skid = [&](int32_t v) -> int32_t { return (int32_t)(fbase[lab[v]] + (nid[v] - poff[lab[v]])); };
 
-    // ---- intra-part CSR (renumbered) and the cut arcs R by skeleton id
+    tr.mark("renumbering");
+    // ---- intra-part CSR (renumbered) and the cut arcs R by skeleton id: count per
+    // renumbered row, prefix sums, then fill (rows in parallel)
     irp.assign(n + 1, 0);
-    icol.clear();
-    iw.clear();
-    icol.reserve(g->nnz);
-    if (wt) iw.reserve(g->nnz);
     rptr.assign(nsk + 1, 0);
-    rcol.clear();
-    rw.clear();
-    std::vector<std::pair<int32_t, uint32_t>> tmp;
-    for (int32_t r = 0; r < n; ++r) {
-        const int32_t v = old[r];
-        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
-            const int32_t u = cl[e];
-            if (lab[u] == lab[v]) {
-                icol.push_back(nid[u]);
-                if (wt) iw.push_back((uint32_t)wt[e]);
-            }
+    parallel_for(n, 8192, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; ++r) {
+            const int32_t v = old[r];
+            int64_t ci = 0, cr = 0;
+            for (int64_t e = rp[v]; e < rp[v + 1]; ++e) (lab[cl[e]] == lab[v] ? ci : cr)++;
+            irp[r + 1] = ci;
+            if (fr[v]) rptr[skid(v) + 1] = cr;
         }
-        irp[r + 1] = (int64_t)icol.size();
-        if (fr[v]) {
-            const int32_t f = skid(v);
-            const int64_t a0 = (int64_t)rcol.size();
+    });
+    for (int32_t r = 0; r < n; ++r) irp[r + 1] += irp[r];
+    for (int32_t f = 0; f < nsk; ++f) rptr[f + 1] += rptr[f];
+    icol.resize((size_t)irp[n]);
+    iw.resize(wt ? (size_t)irp[n] : 0);
+    rcol.resize((size_t)rptr[nsk]);
+    rw.resize((size_t)rptr[nsk]);
+    parallel_for(n, 8192, [&](int64_t a, int64_t b) {
+        std::vector<std::pair<int32_t, uint32_t>> tmp;
+        for (int64_t r = a; r < b; ++r) {
+            const int32_t v = old[r];
+            int64_t oi = irp[r];
             for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
                 const int32_t u = cl[e];
-                if (lab[u] != lab[v]) {
-                    rcol.push_back(skid(u));
-                    rw.push_back(wt ? (uint32_t)wt[e] : 1u);
+                if (lab[u] == lab[v]) {
+                    icol[oi] = nid[u];
+                    if (wt) iw[oi] = (uint32_t)wt[e];
+                    ++oi;
                 }
             }
-            // rows sorted by skeleton id, so that reverse arcs can be found by bisection
-            const int64_t a1 = (int64_t)rcol.size();
+            if (!fr[v]) continue;
+            // cut arcs of a frontier row, sorted by skeleton id (reverse arcs are found
+            // by bisection)
             tmp.clear();
-            for (int64_t e = a0; e < a1; ++e) tmp.push_back({rcol[e], rw[e]});
-            std::sort(tmp.begin(), tmp.end());
-            for (int64_t e = a0; e < a1; ++e) {
-                rcol[e] = tmp[e - a0].first;
-                rw[e] = tmp[e - a0].second;
+            for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+                const int32_t u = cl[e];
+                if (lab[u] != lab[v]) tmp.push_back({skid(u), wt ? (uint32_t)wt[e] : 1u});
             }
-            rptr[f + 1] = a1;  // frontier ids come in renumbered order
+            std::sort(tmp.begin(), tmp.end());
+            int64_t o = rptr[skid(v)];
+            for (auto& t : tmp) {
+                rcol[o] = t.first;
+                rw[o] = t.second;
+                ++o;
+            }
         }
-    }
+    });
     nR = (int64_t)rcol.size();
 
+    tr.mark("intra CSR, R arcs");
     // ---- Dijkstra_SK groups: every part with >= 2 nodes and a frontier
     groups.clear();
     info.clear();
@@ -295,6 +308,7 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
     for (int32_t v = 0; v < n; ++v)
         if (fr[v]) out_idx[v] = skid(v);
     nint = (int32_t)int_local.size();
+    tr.mark("groups, interior rows");
     return BC_OK;
 }
 
@@ -495,8 +509,10 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
 
 int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
                    bc_skeleton** out, bool given_singletons) {
+    PhaseTrace tr("partition");
     SkBuild b;
     BC_TRY(b.prepare(g, part, k, S, nS, given_singletons));
+    tr.mark("prepare (host)");
     bc_graph* gm = const_cast<bc_graph*>(g);
     Arena& W = gm->work;
     hipStream_t s = g->stream;
@@ -504,13 +520,16 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     for (auto& G : b.groups) positions += (int64_t)G.hi - G.lo;
     BC_TRY(W.reserve(b.temp_bytes() + engine_bytes(std::max<int32_t>((int32_t)b.groups.size(), 1), positions)));
     BC_TRY(b.upload(W, s));
+    tr.mark("upload");
     if (!b.groups.empty()) BC_TRY(run_groups_prealloc(W, s, b.groups));
+    tr.mark("Dijkstra_SK");
     auto sk = std::make_unique<bc_skeleton>();
     BC_TRY(b.assemble(W, s, sk.get(), [&](size_t bytes, Arena*& A) -> int {
         BC_TRY(sk->store.reserve(bytes));
         A = &sk->store;
         return BC_OK;
     }));
+    tr.mark("assemble");
     *out = sk.release();
     return BC_OK;
 }
