@@ -18,6 +18,9 @@
 //   interior  delta(s|v) of the interior rows (eq. localcentrality).
 // A group's node scores (cacc) and interior scores (cint) are owned by its workgroup
 // and accumulated in source order, so results do not depend on what else runs.
+// Dijkstra_SK groups (Sec. 4) run the forward sweep only, with path counts restricted
+// to non-frontier parents or the source (eq. frontierparents), and write d(f,v) and
+// sigma(f,v) of every node of the part to the group's [node][64] output lanes.
 //
 // The graph's CSR is read from global memory; it is small enough to stay in L2 for the
 // graphs this kernel takes, so the only HBM traffic is the first touch of the CSR and
@@ -210,7 +213,12 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     uint32_t* __restrict__ idist = R.idist;
     uint64_t* __restrict__ isig = R.isig;
 
-    for (int32_t v = tid; v < n; v += T) cacc[v] = 0.0;
+    // Dijkstra_SK groups (no GF_BACKWARD): forward only, restricted path counts, and
+    // d and sigma of every node written out per source lane
+    const bool bwd = (R.flags & GF_BACKWARD) != 0;
+    const bool restrict_ = (R.flags & GF_RESTRICT) != 0;
+    if (bwd)
+        for (int32_t v = tid; v < n; v += T) cacc[v] = 0.0;
     if (cent)
         for (int32_t i = tid; i < R.tn; i += T) R.cint[i] = 0.0;
     unsigned long long bytes = 0;
@@ -242,11 +250,11 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                     return false;
                 },
                 [&](int32_t q, bool valid) {
-                    if (prof && valid) bytes += 20ull;
+                    if (prof && valid) bytes += 12ull;
                     for_queue_arcs(rp, lo, q, valid, [&](int owner, int64_t e, bool ok, int, int, int) {
                         const int32_t v = __shfl(q, owner, 64);
                         if (!ok) return;
-                        if (prof) bytes += 32ull;
+                        if (prof) bytes += 12ull;
                         const int32_t u = col[e] - lo;
                         const uint32_t L = len ? len[e] : 1u;
                         // u is a parent of v if it settled at D - L in an earlier step (eq.
@@ -254,7 +262,10 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         // exact for integers, and a wrap of any addition is an overflow
                         if (v != s && L <= D) {
                             const uint32_t du = D_(u);
-                            if (du != INF32 && du + L == D) {
+                            // Dijkstra_SK (eq. frontierparents): a frontier parent other
+                            // than the source is tight but adds no paths
+                            if (du != INF32 && du + L == D &&
+                                !(restrict_ && u != s && nflag && (nflag[lo + u] & NF_BLOCKED))) {
                                 uint64_t x = S_(u);
                                 if (mult) {
                                     const uint64_t m = mult[e];
@@ -284,6 +295,15 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             D = nx;
         }
         if (ovf) ovf_flag = 1u;
+        if (!bwd) {
+            // (the last step ended with a barrier: every count is final)
+            for (int32_t v = tid; v < n; v += T) {
+                idist[(int64_t)v * 64 + b] = D_(v);
+                isig[(int64_t)v * 64 + b] = S_(v);
+            }
+            __syncthreads();
+            continue;
+        }
 
         // ------------------------------------------- interior rows: d and sigma ----
         if (cent) {
@@ -329,6 +349,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                 },
                 [&](int32_t q, bool valid) {
                     double prev = 0.0, ind = 0.0, acc = 0.0;
+                    if (prof && valid) bytes += 8ull;
                     if (valid) {
                         prev = cacc[q];
                         ind = (nflag && (nflag[lo + q] & NF_TARGET)) ? 1.0 : 0.0;
@@ -339,6 +360,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         const int seg = max(__shfl(excl, owner, 64) - r, 0);
                         double c = 0.0;
                         if (ok) {
+                            if (prof) bytes += 20ull;
                             const int32_t x = col[e] - lo;
                             const uint32_t L = len ? len[e] : 1u;
                             const uint32_t dx = D_(x);

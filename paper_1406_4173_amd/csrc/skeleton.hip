@@ -518,10 +518,30 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     hipStream_t s = g->stream;
     int64_t positions = 0;
     for (auto& G : b.groups) positions += (int64_t)G.hi - G.lo;
-    BC_TRY(W.reserve(b.temp_bytes() + engine_bytes(std::max<int32_t>((int32_t)b.groups.size(), 1), positions)));
+    // Dijkstra_SK groups run on the resident kernel (parts larger than LDS keep their
+    // one-source state in device memory), or on the engine when it is switched off
+    bool res = !b.groups.empty();
+    size_t extra = 0;
+    for (auto& G : b.groups) {
+        res = res && resident_takes((int64_t)G.hi - G.lo);
+        if ((int64_t)G.hi - G.lo > resident_max_range()) extra += (size_t)(G.hi - G.lo) * 12 + 512;
+    }
+    extra += resident_launch_bytes(b.groups.size());
+    BC_TRY(W.reserve(b.temp_bytes() + std::max(extra, engine_bytes(std::max<int32_t>((int32_t)b.groups.size(), 1),
+                                                                   positions))));
     BC_TRY(b.upload(W, s));
     tr.mark("upload");
-    if (!b.groups.empty()) BC_TRY(run_groups_prealloc(W, s, b.groups));
+    if (res) {
+        for (auto& G : b.groups) {
+            if ((int64_t)G.hi - G.lo <= resident_max_range()) continue;
+            G.gdist = W.take<uint32_t>((size_t)(G.hi - G.lo));
+            G.gsig = W.take<uint64_t>((size_t)(G.hi - G.lo));
+            if (!G.gdist || !G.gsig) return fail(BC_E_NOMEM, "partition: workspace too small");
+        }
+        BC_TRY(run_resident(s, W, b.groups));
+    } else if (!b.groups.empty()) {
+        BC_TRY(run_groups_prealloc(W, s, b.groups));
+    }
     tr.mark("Dijkstra_SK");
     auto sk = std::make_unique<bc_skeleton>();
     BC_TRY(b.assemble(W, s, sk.get(), [&](size_t bytes, Arena*& A) -> int {

@@ -68,6 +68,19 @@ def test_skeleton_structure_small_graphs(bcpp):
         skeleton_matches_oracle(bcpp, g, g.part, g.k, g.S)
 
 
+def test_skeleton_structure_engine_dijkstra_sk(bcpp, monkeypatch):
+    # the same skeletons with Dijkstra_SK on the multi-group engine instead of the
+    # resident kernel
+    monkeypatch.setenv("BCPP_RESIDENT", "0")
+    for seed in range(20):
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(2, 60))
+        g = inputs.random_graph(3000 + seed, n, float(rng.choice([0.05, 0.1, 0.3])),
+                                wmax=[None, 3, 7][seed % 3], k=int(rng.integers(1, 8)),
+                                ns=int(rng.integers(0, max(1, n // 4))))
+        skeleton_matches_oracle(bcpp, g, g.part, g.k, g.S)
+
+
 def test_skeleton_structure_planted(bcpp):
     g = inputs.planted_1k()
     S = inputs.random_targets(21, g.n, 40)
