@@ -80,8 +80,9 @@ struct Block {
     bool live = false;
 };
 
-// Q_RES: Brandes_SK + Centrality running as one LDS-resident launch on a side stream
-enum { Q_QUEUED = 0, Q_DSK = 1, Q_BSK = 2, Q_DONE = 3, Q_FAILED = 4, Q_RES = 5 };
+// Q_RDSK / Q_RES: Dijkstra_SK, or Brandes_SK + Centrality, running as resident
+// launches on a side stream (Q_DSK / Q_BSK: the same on the shared engine)
+enum { Q_QUEUED = 0, Q_DSK = 1, Q_BSK = 2, Q_DONE = 3, Q_FAILED = 4, Q_RES = 5, Q_RDSK = 6 };
 
 struct Query {
     uint64_t ticket = 0;
@@ -177,6 +178,8 @@ static void free_block(bc_server* sv, Block& b, Arena& a) {
     a = Arena();
 }
 
+static hipStream_t next_side_stream(bc_server* sv) { return sv->rs[sv->rnext++ % bc_server::NRS]; }
+
 static int free_slots(bc_server* sv) {
     int c = 0;
     for (auto o : sv->slot_owner) c += o == 0;
@@ -256,6 +259,10 @@ static void finish_query(bc_server* sv, Query* q, std::vector<double>&& res) {
 static int start_bsk(bc_server* sv, Query* q, bool* started) {
     *started = false;
     hipStream_t s = sv->stream;
+    if (q->ev) {
+        (void)hipEventDestroy(q->ev);
+        q->ev = nullptr;
+    }
     if (!q->sk) {
         auto sk = std::make_unique<bc_skeleton>();
         BC_TRY(q->build->assemble(q->a_tmp, s, sk.get(), [&](size_t bytes, Arena*& A) -> int {
@@ -297,7 +304,7 @@ static int start_bsk(bc_server* sv, Query* q, bool* started) {
         q->d_err = L.d_err;
         q->d_out = q->a_bsk.take<double>(std::max(n, 1));
         if (!q->d_out) return fail(BC_E_NOMEM, "server: block too small");
-        hipStream_t r = sv->rs[sv->rnext++ % bc_server::NRS];
+        hipStream_t r = next_side_stream(sv);
         BC_HIP(hipEventRecord(sv->asm_ev, s));
         BC_HIP(hipStreamWaitEvent(r, sv->asm_ev, 0));
         BC_TRY(resident_launch(r, L));
@@ -389,6 +396,36 @@ static int admit(bc_server* sv, Query* q) {
     if (!q->build) return fail(BC_E_DEVICE, "server: query was not prepared");
     SkBuild& b = *q->build;
     q->groups = b.groups;
+    bool res = !(q->flags & BC_ENGINE_ONLY) && !q->groups.empty();
+    for (auto& G : q->groups) res = res && resident_takes((int64_t)G.hi - G.lo);
+    if (res) {
+        // Dijkstra_SK as one resident launch on a side stream; parts larger than LDS
+        // keep their one-source state in the query's block
+        size_t need = b.temp_bytes() + resident_launch_bytes(q->groups.size()) + 8192;
+        for (auto& G : q->groups)
+            if ((int64_t)G.hi - G.lo > resident_max_range()) need += (size_t)(G.hi - G.lo) * 12 + 512;
+        if (need > sv->pool.cap) return fail(BC_E_NOMEM, "server: query needs more than the configured budget");
+        if (!alloc_block(sv, need, q->tmp, q->a_tmp)) return BC_E_AGAIN;
+        BC_TRY(b.upload(q->a_tmp, sv->stream));
+        for (auto& G : b.groups) {
+            if ((int64_t)G.hi - G.lo <= resident_max_range()) continue;
+            G.gdist = q->a_tmp.take<uint32_t>((size_t)(G.hi - G.lo));
+            G.gsig = q->a_tmp.take<uint64_t>((size_t)(G.hi - G.lo));
+            if (!G.gdist || !G.gsig) return fail(BC_E_NOMEM, "server: block too small");
+        }
+        q->groups = b.groups;
+        ResidentLaunch L;
+        BC_TRY(resident_upload(sv->stream, q->a_tmp, q->groups, &L));
+        q->d_err = L.d_err;
+        hipStream_t r = next_side_stream(sv);
+        BC_HIP(hipEventRecord(sv->asm_ev, sv->stream));
+        BC_HIP(hipStreamWaitEvent(r, sv->asm_ev, 0));
+        BC_TRY(resident_launch(r, L));
+        BC_HIP(hipEventCreateWithFlags(&q->ev, hipEventDisableTiming));
+        BC_HIP(hipEventRecord(q->ev, r));
+        q->state = Q_RDSK;
+        return BC_OK;
+    }
     const size_t need = b.temp_bytes() + 4096;
     int64_t pos = 0;
     for (auto& G : q->groups) pos += positions_of(G);
@@ -451,6 +488,7 @@ static void server_loop(bc_server* sv) {
     std::deque<Query*> waiting;     // not yet admitted
     std::vector<Query*> bsk_wait;   // Dijkstra_SK done, Brandes_SK memory not free yet
     std::vector<Query*> res_run;    // resident launches in flight
+    std::vector<Query*> res_run_new;
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(sv->mu);
@@ -473,9 +511,39 @@ static void server_loop(bc_server* sv) {
                 continue;
             }
             res_run.erase(res_run.begin() + i);
-            const int rc = e == hipSuccess ? finish_res(sv, q) : fail(BC_E_DEVICE, "server: resident launch failed");
-            if (rc != BC_OK) fail_query(sv, q, rc, bc_last_error());
+            if (e != hipSuccess) {
+                fail_query(sv, q, BC_E_DEVICE, "server: resident launch failed");
+                continue;
+            }
+            if (q->state == Q_RES) {
+                const int rc = finish_res(sv, q);
+                if (rc != BC_OK) fail_query(sv, q, rc, bc_last_error());
+                continue;
+            }
+            // Dijkstra_SK done: check its overflow flag, then assembly and Brandes_SK
+            uint32_t err = 0;
+            if (hipMemcpyAsync(&err, q->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, sv->cs) != hipSuccess ||
+                hipStreamSynchronize(sv->cs) != hipSuccess) {
+                fail_query(sv, q, BC_E_DEVICE, "server: device copy failed");
+                continue;
+            }
+            if (err & ERR_OVERFLOW) {
+                fail_query(sv, q, BC_E_OVERFLOW, "a shortest-path count reached 2^64");
+                continue;
+            }
+            bool started = false;
+            const int rc = start_bsk(sv, q, &started);
+            if (rc == BC_E_AGAIN) {
+                bsk_wait.push_back(q);
+                continue;
+            }
+            if (rc != BC_OK)
+                fail_query(sv, q, rc, bc_last_error());
+            else if (started)
+                (q->state == Q_RES ? res_run_new : active).push_back(q);
         }
+        res_run.insert(res_run.end(), res_run_new.begin(), res_run_new.end());
+        res_run_new.clear();
         // Brandes_SK starts for queries whose skeleton is ready (they go first)
         for (size_t i = 0; i < bsk_wait.size();) {
             Query* q = bsk_wait[i];
@@ -502,7 +570,10 @@ static void server_loop(bc_server* sv) {
                 fail_query(sv, q, rc, bc_last_error());
                 continue;
             }
-            if (q->state == Q_DSK || q->state == Q_BSK) active.push_back(q);
+            if (q->state == Q_RDSK)
+                res_run.push_back(q);
+            else if (q->state == Q_DSK || q->state == Q_BSK)
+                active.push_back(q);
         }
         if (active.empty()) continue;
         // one engine step for every installed group of every admitted query
@@ -708,7 +779,8 @@ int bc_server_stats_get(bc_server* s, bc_server_stats* out) {
     out->queued = (int64_t)s->incoming.size();
     int64_t inflight = 0;
     for (auto& kv : s->queries)
-        inflight += (kv.second->state == Q_DSK || kv.second->state == Q_BSK || kv.second->state == Q_RES);
+        inflight += (kv.second->state == Q_DSK || kv.second->state == Q_BSK || kv.second->state == Q_RES ||
+                     kv.second->state == Q_RDSK);
     out->inflight = inflight;
     out->iterations = s->n_iters;
     std::vector<double> l = s->lat_ms;
