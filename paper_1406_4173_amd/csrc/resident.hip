@@ -30,6 +30,7 @@
 #include <map>
 
 #include "engine.h"
+#include "tuned.h"
 
 namespace bcpp {
 
@@ -456,10 +457,20 @@ int query_limits() {
     return BC_OK;
 }
 
-// ranges up to SMALL_RANGE nodes run with 256 threads per workgroup, up to MID_RANGE
-// with 512 (several workgroups per CU), larger ones with 1024
-constexpr int64_t SMALL_RANGE = 2048;
-constexpr int64_t MID_RANGE = 6000;
+// Launch shapes: the tuned table, or for a tuning sweep the environment overrides
+// BCPP_TUNE_SMALL, BCPP_TUNE_MID (range thresholds of the 256- and 512-thread classes)
+// and BCPP_TUNE_SPG_DIV (sources per group = ceil(|S| / div)).
+int64_t tune_value(const char* name, int64_t dflt) {
+    const char* e = getenv(name);
+    if (!e || !*e) return dflt;
+    const long long v = atoll(e);
+    return v > 0 ? (int64_t)v : dflt;
+}
+struct SizeClasses {
+    int64_t small = tune_value("BCPP_TUNE_SMALL", tuned_small_range);
+    int64_t mid = tune_value("BCPP_TUNE_MID", tuned_mid_range);
+    int of(int64_t range) const { return range <= small ? 0 : range <= mid ? 1 : 2; }
+};
 
 }  // namespace
 
@@ -475,7 +486,8 @@ int64_t resident_max_range() {
 }
 
 int32_t resident_sources_per_group(int64_t nsrc) {
-    return (int32_t)std::min<int64_t>(LANES, std::max<int64_t>(1, (nsrc + 1023) / 1024));
+    const int64_t div = tune_value("BCPP_TUNE_SPG_DIV", tuned_spg_div);
+    return (int32_t)std::min<int64_t>(LANES, std::max<int64_t>(1, (nsrc + div - 1) / div));
 }
 
 bool resident_takes(int64_t range) {
@@ -526,6 +538,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
     std::vector<RCtx> ctx;
     std::vector<int32_t> src;
     std::map<std::pair<const void*, const void*>, int32_t> ctx_of;
+    const SizeClasses sc;
     for (size_t i = 0; i < ng; ++i) {
         const GroupDesc& G = *groups[i];
         const int64_t range = (int64_t)G.hi - G.lo;
@@ -535,7 +548,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
             if (!G.gdist || !G.gsig) return fail(BC_E_INVAL, "resident: no state buffers for a large range");
             c = 3;
         } else {
-            c = range <= SMALL_RANGE ? 0 : range <= MID_RANGE ? 1 : 2;
+            c = sc.of(range);
             L->lds[c] = std::max(L->lds[c], need);
         }
         const auto key = std::make_pair((const void*)G.g.row_ptr, (const void*)G.trow);

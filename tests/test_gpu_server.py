@@ -111,11 +111,12 @@ def test_server_failure_is_isolated(bcpp):
 
 def test_server_budget_too_small_for_a_query(bcpp):
     srv = bcpp.Server(64 << 20, max_inflight=2)
-    g = inputs.sbm_10k()
+    g = inputs.pareto_100k()
     small = inputs.random_graph(8300, 50, 0.1, wmax=3, k=3)
     gid = srv.add_graph(g)
     sid = srv.add_graph(small)
-    t_big = srv.submit(gid, g.S)          # 10,000 sources over 10,000 nodes: far over 64 MiB
+    # 2,000 sources over a 74,000-node skeleton: hundreds of MB of per-group state
+    t_big = srv.submit(gid, g.S)
     t_small = srv.submit(sid, small.S)
     res = wait_all(srv, [t_big, t_small], {t_big: g.n, t_small: small.n})
     assert isinstance(res[t_big], bcpp.BcError) and res[t_big].code == bcpp.BC_E_NOMEM
