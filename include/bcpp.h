@@ -59,6 +59,11 @@ typedef enum bc_status {
  * (one source at a time per workgroup, its state in LDS), which is used otherwise.
  * Both compute the same d and sigma; scores agree within the stated tolerance. */
 #define BC_ENGINE_ONLY 0x2u
+/* Batch runs of plain Brandes: run eagerly instead of replaying the batch's HIP graph.
+ * (The first plain run of a batch builds its groups, buffers and launch records once
+ * and captures the launches into a graph; later runs replay it. Results are the same
+ * bit for bit either way.) */
+#define BC_NO_GRAPH 0x4u
 
 typedef struct bc_csr {
     int32_t n;              /* nodes */
@@ -159,8 +164,8 @@ int bc_brandes_pp_dev(const bc_graph* g, const bc_skeleton* sk, uint32_t flags,
 /* ---------------------------------------------------------------- batching ---- */
 
 /* Many independent graphs in one device run: each graph g_i with its own partition
- * and targets. All graphs' groups of sources (and, for Brandes++, all parts) advance
- * together in one persistent sequence of launches. */
+ * and targets. All graphs' groups of sources (and, for Brandes++, all parts) run in
+ * the same launches; plain Brandes over the batch replays one captured HIP graph. */
 int bc_batch_create(int32_t ngraphs, const bc_csr* graphs, const int32_t* const* parts,
                     const int32_t* ks, const int32_t* const* S, const int32_t* nS,
                     void* hip_stream, bc_batch** out);

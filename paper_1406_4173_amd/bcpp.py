@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbcpp.so")
 BC_OK, BC_E_INVAL, BC_E_OVERFLOW, BC_E_NOMEM, BC_E_DEVICE, BC_E_AGAIN, BC_E_NOTFOUND = range(7)
 BC_ORDERED = 0x1
 BC_ENGINE_ONLY = 0x2
+BC_NO_GRAPH = 0x4
 BC_BATCH_PLAIN = 0x0
 BC_BATCH_PP = 0x100
 KERNELS = ["select", "settle", "push", "backward", "centrality", "sched", "other", "resident"]
@@ -287,10 +288,12 @@ class Batch:
                                      ctypes.byref(h)))
         self.h = h
 
-    def run(self, pp: bool = True, engine_only: bool = False):
+    def run(self, pp: bool = True, engine_only: bool = False, graph: bool = True):
+        """graph=False runs plain Brandes eagerly instead of replaying the captured graph."""
         outs = [np.empty(n, np.float64) for n in self.ns]
         ptrs = (ctypes.c_void_p * len(outs))(*[o.ctypes.data for o in outs])
-        fl = (BC_BATCH_PP if pp else BC_BATCH_PLAIN) | (BC_ENGINE_ONLY if engine_only else 0)
+        fl = ((BC_BATCH_PP if pp else BC_BATCH_PLAIN) | (BC_ENGINE_ONLY if engine_only else 0) |
+              (0 if graph else BC_NO_GRAPH))
         _check(lib().bc_batch_run(self.h, fl, ctypes.cast(ptrs, _P)))
         return outs
 

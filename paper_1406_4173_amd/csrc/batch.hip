@@ -14,6 +14,36 @@
 #include "engine.h"
 #include "graph.h"
 
+namespace bcpp {
+// A batch's plain Brandes as a captured HIP graph. The batch never changes, so its
+// groups, their buffers, the launch records and the reduction pointers are built once;
+// each run replays the graph, which runs every kernel again (clear the error word, the
+// resident launches, the reduction) and copies the scores and the error word to pinned
+// host memory. Nothing in the graph is a memset node.
+struct PlainPlan {
+    bool ready = false;
+    Arena mem;
+    std::vector<GroupDesc> groups;
+    hipStream_t stream = nullptr;  // capture needs a stream of its own
+    double* h_out = nullptr;       // pinned
+    uint32_t* h_err = nullptr;     // pinned
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    PlainPlan() = default;
+    PlainPlan(const PlainPlan&) = delete;
+    PlainPlan& operator=(const PlainPlan&) = delete;
+    ~PlainPlan() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (h_out) (void)hipHostFree(h_out);
+        if (h_err) (void)hipHostFree(h_err);
+        mem.release();
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+}  // namespace bcpp
+
 struct bc_batch {
     int32_t ng = 0;
     std::vector<int32_t> n_off;  // [ng+1] node offset of each graph in the union
@@ -22,7 +52,11 @@ struct bc_batch {
     std::vector<int32_t> lab;    // P' labels of the union (targets singleton)
     int32_t nlab = 0;
     bc_graph* G = nullptr;       // the union graph
-    ~bc_batch() { delete G; }
+    std::unique_ptr<bcpp::PlainPlan> plan;  // plain Brandes, captured on first use
+    ~bc_batch() {
+        plan.reset();
+        delete G;
+    }
 };
 
 namespace bcpp {
@@ -138,6 +172,111 @@ static int batch_plain(bc_batch* b, uint32_t flags, double* d_out) {
     return BC_OK;
 }
 
+__global__ void k_clear_word(uint32_t* __restrict__ p) {
+    if (threadIdx.x == 0) p[0] = 0u;
+}
+
+// Build the plain plan and capture its graph (first plain run of the batch).
+static int build_plain_plan(bc_batch* b) {
+    bc_graph* G = b->G;
+    hipStream_t s0 = G->stream;
+    const int32_t n = G->n;
+    auto P = std::make_unique<PlainPlan>();
+    std::vector<int32_t> g0(n, 0), g1(n, 0), idx(n, -1);
+    P->groups.reserve(b->S_all.size() + (size_t)b->ng);
+    for (int32_t gi = 0; gi < b->ng; ++gi) {
+        const int32_t lo = b->n_off[gi], hi = b->n_off[gi + 1];
+        const int32_t ns = b->s_off[gi + 1] - b->s_off[gi];
+        const int32_t first_group = (int32_t)P->groups.size();
+        if (ns >= 2) {
+            const int32_t per = resident_sources_per_group(ns);
+            for (int32_t c = 0; c < ns; c += per) {
+                GroupDesc D;
+                D.lo = lo;
+                D.hi = hi;
+                D.flags = GF_BACKWARD;
+                D.nsrc = std::min(per, ns - c);
+                for (int l = 0; l < LANES; ++l) D.src[l] = l < D.nsrc ? b->S_all[b->s_off[gi] + c + l] : -1;
+                P->groups.push_back(D);
+            }
+        }
+        for (int32_t v = lo; v < hi; ++v) {
+            g0[v] = first_group;
+            g1[v] = (int32_t)P->groups.size();
+            idx[v] = v - lo;
+        }
+    }
+    size_t need = resident_launch_bytes(P->groups.size()) + 2 * (P->groups.size() * 8 + 256) +
+                  (size_t)n * 21 + (1 << 20);
+    for (const GroupDesc& D : P->groups) need += resident_group_bytes(D);
+    BC_TRY(P->mem.reserve(need));
+    uint8_t* d_flag = P->mem.take<uint8_t>(std::max(n, 1));
+    int32_t* d_g0 = P->mem.take<int32_t>(std::max(n, 1));
+    int32_t* d_g1 = P->mem.take<int32_t>(std::max(n, 1));
+    int32_t* d_idx = P->mem.take<int32_t>(std::max(n, 1));
+    double* d_out = P->mem.take<double>(std::max(n, 1));
+    if (!d_flag || !d_g0 || !d_g1 || !d_idx || !d_out) return fail(BC_E_NOMEM, "batch: workspace too small");
+    std::vector<uint8_t> flag(n, 0);
+    for (int32_t v : b->S_all) flag[v] = (uint8_t)NF_TARGET;
+    BC_HIP(hipMemcpyAsync(d_flag, flag.data(), n, hipMemcpyHostToDevice, s0));
+    BC_HIP(hipMemcpyAsync(d_g0, g0.data(), (size_t)n * 4, hipMemcpyHostToDevice, s0));
+    BC_HIP(hipMemcpyAsync(d_g1, g1.data(), (size_t)n * 4, hipMemcpyHostToDevice, s0));
+    BC_HIP(hipMemcpyAsync(d_idx, idx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s0));
+    for (GroupDesc& D : P->groups) {
+        D.g.row_ptr = G->d_row_ptr;
+        D.g.col = G->d_col;
+        D.g.len = G->d_len;
+        D.g.nflag = d_flag;
+        if (!resident_alloc(P->mem, D)) return fail(BC_E_NOMEM, "batch: workspace too small");
+    }
+    ResidentLaunch L;
+    ReducePtrs R;
+    BC_TRY(resident_upload(s0, P->mem, P->groups, &L));
+    BC_TRY(reduce_upload(s0, P->mem, P->groups, &R));
+    BC_HIP(hipHostMalloc((void**)&P->h_out, (size_t)std::max(n, 1) * 8));
+    BC_HIP(hipHostMalloc((void**)&P->h_err, sizeof(uint32_t)));
+    BC_HIP(hipStreamSynchronize(s0));
+    BC_HIP(hipStreamCreate(&P->stream));
+    // capture; launch timing is off while capturing (its events are not graph nodes)
+    hipStream_t s = P->stream;
+    const bool prof_on = profiler().on;
+    profiler().on = false;
+    BC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int rc = BC_OK;
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, s, L.d_err);
+    if (hipGetLastError() != hipSuccess) rc = fail(BC_E_DEVICE, "batch: capture failed");
+    if (rc == BC_OK) rc = resident_launch(s, L);
+    if (rc == BC_OK) rc = reduce_launch(s, R, n, d_g0, d_g1, d_idx, nullptr, 0.5, d_out, false);
+    if (rc == BC_OK && (hipMemcpyAsync(P->h_out, d_out, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                        hipMemcpyAsync(P->h_err, L.d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess))
+        rc = fail(BC_E_DEVICE, "batch: capture of the copies failed");
+    const hipError_t ec = hipStreamEndCapture(s, &P->graph);
+    profiler().on = prof_on;
+    BC_TRY(rc);
+    if (ec != hipSuccess) return fail(BC_E_DEVICE, std::string("batch: capture failed: ") + hipGetErrorString(ec));
+    BC_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+    P->ready = true;
+    b->plan = std::move(P);
+    return BC_OK;
+}
+
+// Plain Brandes over the batch by replaying its captured graph.
+static int batch_plain_graph(bc_batch* b, double scale, double* const* bc_out) {
+    if (!b->plan) BC_TRY(build_plain_plan(b));
+    PlainPlan& P = *b->plan;
+    PhaseTrace tr("batch plain (graph)");
+    BC_HIP(hipGraphLaunch(P.exec, P.stream));
+    BC_HIP(hipStreamSynchronize(P.stream));
+    tr.mark("replay");
+    if (*P.h_err & ERR_OVERFLOW) return fail(BC_E_OVERFLOW, "a shortest-path count reached 2^64");
+    for (int32_t i = 0; i < b->ng; ++i) {
+        if (!bc_out[i]) continue;
+        for (int32_t v = b->n_off[i]; v < b->n_off[i + 1]; ++v)
+            bc_out[i][v - b->n_off[i]] = P.h_out[v] * scale;
+    }
+    return BC_OK;
+}
+
 static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
     bc_graph* G = b->G;
     hipStream_t s = G->stream;
@@ -188,7 +327,7 @@ static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
                 D.g.row_ptr = sk->d_row_ptr;
                 D.g.col = sk->d_col;
                 D.g.len = sk->d_len;
-                D.g.mult = sk->d_mult;
+                D.g.mult = sk_mult(sk.get());
                 D.g.nflag = sk->d_nflag;
                 D.g.twin = sk->d_twin;
                 D.lo = sk_lo;
@@ -313,6 +452,11 @@ int bc_batch_run(bc_batch* b, uint32_t flags, double* const* bc_out) {
     bc_graph* G = b->G;
     const int32_t n = G->n;
     if (n == 0) return BC_OK;
+    if (!(flags & (BC_BATCH_PP | BC_ENGINE_ONLY | BC_NO_GRAPH))) {
+        bool res = true;
+        for (int32_t i = 0; i < b->ng; ++i) res = res && resident_takes(b->n_off[i + 1] - b->n_off[i]);
+        if (res) return batch_plain_graph(b, (flags & BC_ORDERED) ? 2.0 : 1.0, bc_out);
+    }
     BC_TRY(G->out.reserve((size_t)n * 8 + 256));
     double* d_out = G->out.take<double>(n);
     PhaseTrace tr("batch run");

@@ -60,6 +60,11 @@ struct bc_skeleton {
 };
 
 namespace bcpp {
+// Multiplicities of a skeleton's arcs, or nullptr (all 1) when it has no clique arcs:
+// then every arc is a cut arc <w, 1> and the traversals skip the multiplications.
+inline const uint64_t* sk_mult(const bc_skeleton* sk) {
+    return sk->stats.clique_arcs == 0 ? nullptr : sk->d_mult;
+}
 int graph_create(const bc_csr* csr, hipStream_t stream, bc_graph** out);
 int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
                    bc_skeleton** out, bool given_singletons);

@@ -562,7 +562,7 @@ std::vector<GroupDesc> bsk_groups(const bc_skeleton* sk, const int32_t* src, int
         D.g.row_ptr = sk->d_row_ptr;
         D.g.col = sk->d_col;
         D.g.len = sk->d_len;
-        D.g.mult = sk->d_mult;
+        D.g.mult = sk_mult(sk);
         D.g.nflag = sk->d_nflag;
         D.g.twin = sk->d_twin;
         D.lo = lo;
@@ -596,7 +596,7 @@ std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk) {
         G.g.row_ptr = sk->d_row_ptr;
         G.g.col = sk->d_col;
         G.g.len = sk->d_len;
-        G.g.mult = sk->d_mult;
+        G.g.mult = sk_mult(sk);
         G.g.nflag = sk->d_nflag;
         G.lo = 0;
         G.hi = sk->n_sk;
@@ -670,7 +670,7 @@ int pp_run(const bc_graph* gc, const bc_skeleton* sk, uint32_t flags, double* ou
             G.g.row_ptr = sk->d_row_ptr;
             G.g.col = sk->d_col;
             G.g.len = sk->d_len;
-            G.g.mult = sk->d_mult;
+            G.g.mult = sk_mult(sk);
             G.g.nflag = sk->d_nflag;
             G.g.twin = sk->d_twin;
             G.lo = 0;
@@ -726,7 +726,7 @@ int sk_sssp_run(const bc_skeleton* sk, const int32_t* src, int32_t nsrc, int64_t
         G.g.row_ptr = sk->d_row_ptr;
         G.g.col = sk->d_col;
         G.g.len = sk->d_len;
-        G.g.mult = sk->d_mult;
+        G.g.mult = sk_mult(sk);
         G.lo = 0;
         G.hi = N;
         const int32_t first = g0 * LANES;

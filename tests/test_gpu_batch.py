@@ -81,3 +81,21 @@ def test_batch_256_full(bcpp):
         res = B.run(pp=pp)
         for g, got in zip(gs, res):
             assert_scores(got, oracle.bc(g, g.S))
+
+
+def test_batch_plain_graph_replays_match_eager(bcpp):
+    # plain Brandes over a batch replays one captured HIP graph; every replay must equal
+    # the eager run bit for bit, with other eager work and synchronisations in between
+    gs = inputs.batch_256(24)
+    B = bcpp.Batch(gs)
+    eager = B.run(pp=False, graph=False)
+    for g, got in zip(gs, eager):
+        assert_scores(got, oracle.bc(g, g.S))
+    other = inputs.planted_1k()
+    Go = bcpp.Graph(other)
+    for rep in range(4):
+        res = B.run(pp=False)
+        for a, b in zip(res, eager):
+            assert np.array_equal(a, b), f"replay {rep} differs from the eager run"
+        bcpp.brandes_plain(Go, other.S[: 40 + rep])
+        bcpp.Batch(gs[:3]).run(pp=True)
