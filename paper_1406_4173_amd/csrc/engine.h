@@ -76,6 +76,9 @@ struct GroupDesc {
     // resident groups too large for LDS: the one-source state in device memory
     uint32_t* gdist = nullptr;  // [hi-lo]
     uint64_t* gsig = nullptr;   // [hi-lo]
+    // resident backward groups: the forward's per-wave queue record and step distances
+    int32_t* rlist = nullptr;
+    uint32_t* steps = nullptr;  // [hi-lo+1]
     int32_t src[LANES];      // source node ids of g, -1 = unused lane
 };
 

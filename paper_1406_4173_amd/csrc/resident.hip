@@ -42,12 +42,6 @@ __device__ __forceinline__ uint32_t wmin_u32(uint32_t v) {
     return v;
 }
 
-__device__ __forceinline__ uint32_t wmax_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
-}
-
 __device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o, 64);
@@ -157,6 +151,8 @@ struct RGroup {
     uint64_t* isig;   // [tn] interior sigma(s,v) of the current source
     uint32_t* gdist;  // [hi-lo] one-source state in device memory (ranges beyond LDS)
     uint64_t* gsig;
+    int32_t* rlist;   // backward groups: per-wave record of the forward's queues
+    uint32_t* steps;  // backward groups: distance of each forward step
 };
 
 namespace {
@@ -187,7 +183,6 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                                 unsigned long long* __restrict__ prof) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ uint32_t fwd_next[3];  // rotating: step k writes [k%3], clears [(k+1)%3]
-    __shared__ uint32_t bwd_prev[3];
     __shared__ uint32_t ovf_flag;
     __shared__ int32_t wqueue[T / 64][WQ];
 
@@ -218,6 +213,11 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     // d and sigma of every node written out per source lane
     const bool bwd = (R.flags & GF_BACKWARD) != 0;
     const bool restrict_ = (R.flags & GF_RESTRICT) != 0;
+    // this wave's record region (backward groups): nodes, then step numbers, then ends
+    const int32_t wcap = 64 * ((n + T - 1) / T);
+    int32_t* __restrict__ rnodes = bwd ? R.rlist + (int64_t)(tid >> 6) * 3 * wcap : nullptr;
+    int32_t* __restrict__ rsegk = bwd ? rnodes + wcap : nullptr;
+    int32_t* __restrict__ rsege = bwd ? rnodes + 2 * wcap : nullptr;
     if (bwd)
         for (int32_t v = tid; v < n; v += T) cacc[v] = 0.0;
     if (cent)
@@ -231,17 +231,21 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             dist[v] = (v == s) ? 0u : INF32;
             sig[v] = (v == s) ? 1ull : 0ull;
         }
-        if (tid == 0) {
-            fwd_next[0] = fwd_next[1] = fwd_next[2] = INF32;
-            bwd_prev[0] = bwd_prev[1] = bwd_prev[2] = 0u;
-        }
+        if (tid == 0) fwd_next[0] = fwd_next[1] = fwd_next[2] = INF32;
         __syncthreads();
 
         // ------------------------------------------------------------ forward ----
+        // Backward groups record, per wave, the nodes each step queued (in queue order)
+        // and a (step, end) entry for every step in which the wave queued any; the
+        // backward sweep replays these in reverse instead of scanning again. A wave
+        // only ever queues nodes of its own scan passes, so its region holds at most
+        // 64 * ceil(n / T) nodes and as many entries.
         uint32_t D = 0;
         bool ovf = false;
+        int32_t wcur = 0, wseg = 0, wstep0 = 0, nsteps = 0;
         for (int k = 0;; ++k) {
             uint32_t mn = INF32;
+            if (bwd && tid == 0) R.steps[k] = D;
             for_selected<T, GLOBAL ? 8 : 4>(
                 n, wq,
                 [&](int32_t v) {
@@ -252,6 +256,10 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                 },
                 [&](int32_t q, bool valid) {
                     if (prof && valid) bytes += 12ull;
+                    if (bwd) {
+                        if (valid) rnodes[wcur + lane] = q;
+                        wcur += (int32_t)__popcll(__ballot(valid));
+                    }
                     for_queue_arcs(rp, lo, q, valid, [&](int owner, int64_t e, bool ok, int, int, int) {
                         const int32_t v = __shfl(q, owner, 64);
                         if (!ok) return;
@@ -287,11 +295,20 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         }
                     });
                 });
+            if (bwd && wcur != wstep0) {
+                if (lane == 0) {
+                    rsegk[wseg] = k;
+                    rsege[wseg] = wcur;
+                }
+                ++wseg;
+                wstep0 = wcur;
+            }
             mn = wmin_u32(mn);
             if (lane == 0 && mn != INF32) atomicMin(&fwd_next[k % 3], mn);
             if (tid == 0) fwd_next[(k + 1) % 3] = INF32;
             __syncthreads();
             const uint32_t nx = fwd_next[k % 3];
+            nsteps = k + 1;
             if (nx == INF32) break;
             D = nx;
         }
@@ -338,17 +355,12 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         __syncthreads();
 
         // ----------------------------------------------------------- backward ----
-        for (int k = 0; D > 0; ++k) {
-            uint32_t mx = 0;
-            for_selected<T, GLOBAL ? 8 : 4>(
-                n, wq,
-                [&](int32_t v) {
-                    const uint32_t dv = D_(v);
-                    if (dv == D) return true;
-                    if (dv < D) mx = max(mx, dv);
-                    return false;
-                },
-                [&](int32_t q, bool valid) {
+        // steps in reverse (step 0 is the source alone); each wave replays the queues it
+        // recorded for the step, so a node meets the same lanes as in the forward sweep
+        int32_t seg = wseg - 1;
+        for (int k = nsteps - 1; k >= 1; --k) {
+            D = R.steps[k];
+            auto body = [&](int32_t q, bool valid) {
                     double prev = 0.0, ind = 0.0, acc = 0.0;
                     if (prof && valid) bytes += 8ull;
                     if (valid) {
@@ -387,12 +399,16 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         cacc[q] = prev + dl;
                         sig[q] = (uint64_t)__double_as_longlong((ind + dl) / sv);
                     }
-                });
-            mx = wmax_u32(mx);
-            if (lane == 0 && mx != 0u) atomicMax(&bwd_prev[k % 3], mx);
-            if (tid == 0) bwd_prev[(k + 1) % 3] = 0u;
+                };
+            if (seg >= 0 && rsegk[seg] == k) {
+                const int32_t beg = seg > 0 ? rsege[seg - 1] : 0, end = rsege[seg];
+                for (int32_t c = beg; c < end; c += 64) {
+                    const bool valid = c + lane < end;
+                    body(valid ? rnodes[c + lane] : 0, valid);
+                }
+                --seg;
+            }
             __syncthreads();
-            D = bwd_prev[k % 3];
         }
 
         // --------------------------------------------- interior rows: delta ----
@@ -490,6 +506,9 @@ int32_t resident_sources_per_group(int64_t nsrc) {
     return (int32_t)std::min<int64_t>(LANES, std::max<int64_t>(1, (nsrc + div - 1) / div));
 }
 
+// Ints of a backward group's forward record: 3 * T * ceil(range / T) for any T <= 1024.
+size_t record_ints(int64_t range) { return 3 * ((size_t)range + 1024) + 64; }
+
 bool resident_takes(int64_t range) {
     const char* e = getenv("BCPP_RESIDENT");
     if (e && strcmp(e, "0") == 0) return false;
@@ -504,6 +523,8 @@ size_t resident_group_bytes(const GroupDesc& G) {
         b += (((size_t)range * 4 + 255) & ~(size_t)255) + (((size_t)range * 8 + 255) & ~(size_t)255);
     if ((G.flags & GF_CENT) && G.tn > 0)
         b += (((size_t)G.tn * 8 + 255) & ~(size_t)255) * 2 + (((size_t)G.tn * 4 + 255) & ~(size_t)255);
+    if (G.flags & GF_BACKWARD)
+        b += ((record_ints(range) * 4 + 255) & ~(size_t)255) + (((size_t)(range + 1) * 4 + 255) & ~(size_t)255);
     return b + 256;
 }
 
@@ -515,6 +536,11 @@ bool resident_alloc(Arena& a, GroupDesc& G) {
         G.gdist = a.take<uint32_t>((size_t)range);
         G.gsig = a.take<uint64_t>((size_t)range);
         if (!G.gdist || !G.gsig) return false;
+    }
+    if (G.flags & GF_BACKWARD) {
+        G.rlist = a.take<int32_t>(record_ints(range));
+        G.steps = a.take<uint32_t>((size_t)range + 1);
+        if (!G.rlist || !G.steps) return false;
     }
     if ((G.flags & GF_CENT) && G.tn > 0) {
         G.cint = a.take<double>((size_t)G.tn);
@@ -573,6 +599,10 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         r.isig = G.sigma;
         r.gdist = G.gdist;
         r.gsig = G.gsig;
+        r.rlist = G.rlist;
+        r.steps = G.steps;
+        if ((G.flags & GF_BACKWARD) && (!G.rlist || !G.steps))
+            return fail(BC_E_INVAL, "resident: no record buffers for a backward group");
         cls[c].push_back(r);
     }
     L->d_err = a.take<uint32_t>(1);
