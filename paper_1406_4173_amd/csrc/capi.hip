@@ -441,6 +441,12 @@ int bc_brandes_plain_dev(const bc_graph* gc, const int32_t* S_dev, int32_t nS, u
 void bc_profile_enable(int on) {
     Profiler& p = profiler();
     p.on = on != 0;
+    // events are created here, outside any timed region, not on first use
+    while (p.on && p.pool.size() + p.pending.size() * 2 < 8192) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) break;
+        p.pool.push_back(e);
+    }
     if (p.on && !p.d_bytes) {
         if (hipMalloc((void**)&p.d_bytes, BC_K_COUNT * sizeof(unsigned long long)) == hipSuccess)
             (void)hipMemset(p.d_bytes, 0, BC_K_COUNT * sizeof(unsigned long long));

@@ -23,6 +23,7 @@ struct bc_graph {
     bcpp::Arena store;  // graph arrays
     bcpp::Arena work;   // per-call workspace
     bcpp::Arena out;    // staging for host-pointer outputs
+    bcpp::Arena pre;    // scratch of the skeleton build's first phase (one build at a time)
 };
 
 struct bc_skeleton {

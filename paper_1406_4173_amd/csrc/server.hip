@@ -1,15 +1,17 @@
 // Served form: a request loop on its own host thread with continuous batching.
 //
 // Graphs are registered once and stay resident. A query (graph id, target set) goes
-// through: queued -> host preparation of P' (Build_SK host part) -> admission, when its
-// device bytes fit the free part of the HBM budget and the engine has free group slots
-// -> Dijkstra_SK groups installed into the shared engine -> skeleton assembly ->
-// Brandes_SK + Centrality groups installed into the shared engine -> scores copied to
-// the host. The engine iterates over all installed groups of all admitted queries;
-// groups of a query admitted later join at the next iteration, and a query's slots
-// and memory return to the pool as soon as it finishes. Each query's arithmetic is
-// the same as when it runs alone (its groups hold the same sources in the same order),
-// so its result does not depend on what else is in flight.
+// through: queued -> admission, when its device bytes fit the free part of the HBM
+// budget: Build_SK's first phase on the device (P', frontiers, per-part counts), the
+// query's block, the second phase (renumbering, intra-part CSR, cut arcs) -> Dijkstra_SK
+// as one resident launch on a side stream -> skeleton assembly -> Brandes_SK +
+// Centrality as one resident launch on a side stream -> scores copied to the host.
+// Launches of different queries overlap on the device (the side streams), and a
+// query's memory returns to the pool as soon as it finishes. With BC_ENGINE_ONLY a
+// query's groups go into the shared multi-group engine instead, which iterates over
+// all installed groups of all such queries. Each query's arithmetic is the same as
+// when it runs alone (its groups hold the same sources in the same order), so its
+// result does not depend on what else is in flight.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -148,9 +150,6 @@ struct bc_server {
     unsigned rnext = 0;
     hipStream_t cs = nullptr;
     hipEvent_t asm_ev = nullptr;
-    // host preparation of queries (P', renumbering) runs on its own thread
-    std::thread prep_th;
-    std::deque<uint64_t> prepared;
 
     ~bc_server();
 };
@@ -392,8 +391,30 @@ static int finish_res(bc_server* sv, Query* q) {
     return BC_OK;
 }
 
+static int admit_prepared(bc_server* sv, Query* q);
+
+// Admission: Build_SK's first phase on the device (into the graph's scratch, which the
+// next query's build reuses, so a query that cannot be admitted now drops its build and
+// redoes it later), then the query's block and the second phase.
 static int admit(bc_server* sv, Query* q) {
-    if (!q->build) return fail(BC_E_DEVICE, "server: query was not prepared");
+    const bc_graph* g = nullptr;
+    const int32_t* part = nullptr;
+    int32_t k = 0;
+    {
+        // graph objects and partition buffers never move once registered
+        std::lock_guard<std::mutex> lk(sv->mu);
+        g = sv->graphs[q->gid].get();
+        part = sv->parts[q->gid].data();
+        k = sv->ks[q->gid];
+    }
+    q->build = std::make_unique<SkBuild>();
+    int rc = q->build->prepare(g, part, k, q->S.data(), (int32_t)q->S.size(), false);
+    if (rc == BC_OK) rc = admit_prepared(sv, q);
+    if (rc == BC_E_AGAIN) q->build.reset();
+    return rc;
+}
+
+static int admit_prepared(bc_server* sv, Query* q) {
     SkBuild& b = *q->build;
     q->groups = b.groups;
     bool res = !(q->flags & BC_ENGINE_ONLY) && !q->groups.empty();
@@ -443,45 +464,6 @@ static int admit(bc_server* sv, Query* q) {
     return BC_OK;
 }
 
-// Host preparation thread: P', frontiers, renumbering and the Dijkstra_SK groups of
-// each submitted query, so that the device loop never waits on it.
-static void prep_loop(bc_server* sv) {
-    for (;;) {
-        uint64_t ticket = 0;
-        Query* q = nullptr;
-        const bc_graph* g = nullptr;
-        const int32_t* part = nullptr;
-        int32_t k = 0;
-        {
-            std::unique_lock<std::mutex> lk(sv->mu);
-            sv->cv.wait(lk, [&] { return sv->stop || !sv->incoming.empty(); });
-            if (sv->stop) return;
-            ticket = sv->incoming.front();
-            sv->incoming.pop_front();
-            auto it = sv->queries.find(ticket);
-            if (it == sv->queries.end()) continue;
-            q = it->second.get();
-            // graph objects and partition buffers never move once registered
-            g = sv->graphs[q->gid].get();
-            part = sv->parts[q->gid].data();
-            k = sv->ks[q->gid];
-        }
-        auto b = std::make_unique<SkBuild>();
-        const int rc = b->prepare(g, part, k, q->S.data(), (int32_t)q->S.size(), false);
-        std::lock_guard<std::mutex> lk(sv->mu);
-        if (rc != BC_OK) {
-            q->state = Q_FAILED;
-            q->status = rc;
-            q->err = bc_last_error();
-            sv->n_failed++;
-            continue;
-        }
-        q->build = std::move(b);
-        sv->prepared.push_back(ticket);
-        sv->cv.notify_all();
-    }
-}
-
 static void server_loop(bc_server* sv) {
     (void)hipSetDevice(sv->device);
     std::vector<Query*> active;     // admitted, not finished
@@ -492,13 +474,13 @@ static void server_loop(bc_server* sv) {
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            if (active.empty() && waiting.empty() && bsk_wait.empty() && sv->prepared.empty() && !sv->stop)
+            if (active.empty() && waiting.empty() && bsk_wait.empty() && sv->incoming.empty() && !sv->stop)
                 sv->cv.wait_for(lk, res_run.empty() ? std::chrono::microseconds(20000)
                                                     : std::chrono::microseconds(200));
             if (sv->stop) break;
-            while (!sv->prepared.empty()) {
-                auto it = sv->queries.find(sv->prepared.front());
-                sv->prepared.pop_front();
+            while (!sv->incoming.empty()) {
+                auto it = sv->queries.find(sv->incoming.front());
+                sv->incoming.pop_front();
                 if (it != sv->queries.end()) waiting.push_back(it->second.get());
             }
         }
@@ -649,7 +631,6 @@ bc_server::~bc_server() {
     }
     cv.notify_all();
     if (th.joinable()) th.join();
-    if (prep_th.joinable()) prep_th.join();
     if (stream) (void)hipStreamSynchronize(stream);
     for (hipStream_t r : rs)
         if (r) (void)hipStreamSynchronize(r);
@@ -702,7 +683,6 @@ int bc_server_create(size_t hbm_budget_bytes, int32_t max_inflight, bc_server** 
     sv->pool.init(sv->d_pool, hbm_budget_bytes);
     bc_server* raw = sv.get();
     sv->th = std::thread([raw] { server_loop(raw); });
-    sv->prep_th = std::thread([raw] { prep_loop(raw); });
     *out = sv.release();
     return BC_OK;
 }
@@ -776,11 +756,13 @@ int bc_server_stats_get(bc_server* s, bc_server_stats* out) {
     out->submitted = s->n_submitted;
     out->completed = s->n_completed;
     out->failed = s->n_failed;
-    out->queued = (int64_t)s->incoming.size();
-    int64_t inflight = 0;
-    for (auto& kv : s->queries)
-        inflight += (kv.second->state == Q_DSK || kv.second->state == Q_BSK || kv.second->state == Q_RES ||
-                     kv.second->state == Q_RDSK);
+    int64_t inflight = 0, queued = 0;
+    for (auto& kv : s->queries) {
+        const int st = kv.second->state;
+        inflight += (st == Q_DSK || st == Q_BSK || st == Q_RES || st == Q_RDSK);
+        queued += st == Q_QUEUED;
+    }
+    out->queued = queued;
     out->inflight = inflight;
     out->iterations = s->n_iters;
     std::vector<double> l = s->lat_ms;

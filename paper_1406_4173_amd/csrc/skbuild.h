@@ -1,5 +1,16 @@
-// Build_SK in stages, so that a caller can run the Dijkstra_SK groups on an engine of
-// its own (the serving loop shares one engine among queries).
+// Build_SK on the device, in stages, so that a caller can run the Dijkstra_SK groups
+// where it likes (the serving loop runs them as launches of their own).
+//
+//   prepare  validation on the host, then phase 1 on the graph's stream in the
+//            graph's scratch arena: P' labels and target flags, frontier flags, and per
+//            part of P' its size, frontier count and intra-part arc count, copied back;
+//            on the host from those: part offsets, Dijkstra_SK groups, interior row
+//            bases and the exact device bytes of phase 2.
+//   upload   phase 2 into the caller's arena: renumbering (a stable radix sort on
+//            (part, not frontier)), intra-part CSR and cut-arc rows (count, scan,
+//            fill), blocked flags, interior rows, output maps, group states. After it
+//            nothing refers to the scratch arena, so the next prepare may reuse it.
+//   assemble after the Dijkstra_SK groups: skeleton rows, clique arcs, tables.
 #pragma once
 
 #include <functional>
@@ -20,53 +31,53 @@ struct DskInfo {
 
 struct SkBuild {
     const bc_graph* g = nullptr;
-    int32_t n = 0;
+    int32_t n = 0, nS = 0;
     int64_t nlab = 0;
     bool weighted = false;
-    std::vector<int32_t> S;         // targets (original ids)
-    std::vector<int32_t> lab;       // P' labels
-    std::vector<uint8_t> fr, is_t;  // frontier and target flags
-    std::vector<int64_t> psize, pnf, poff, fbase;
-    std::vector<int32_t> nid, old;  // renumbering (parts contiguous, frontier first)
-    int32_t nsk = 0;
-    std::vector<int64_t> irp;  // intra-part CSR, renumbered
-    std::vector<int32_t> icol;
-    std::vector<uint32_t> iw;
-    std::vector<int64_t> rptr;  // cut arcs by skeleton id, rows sorted
-    std::vector<int32_t> rcol;
-    std::vector<uint32_t> rw;
-    int64_t nR = 0;
+    std::vector<int32_t> S;  // targets (original ids)
+    // per part of P' (host copies of phase 1, and their prefix sums)
+    std::vector<int32_t> psize, pnf;
+    std::vector<uint64_t> parc;                 // intra-part arcs
+    std::vector<int64_t> poff, fbase, aoff;     // node, skeleton-id and arc offsets
+    std::vector<int32_t> p_g0, p_ng, ibase;     // groups and interior rows of each part
+    int32_t nsk = 0, nint = 0;
+    int64_t n_intra = 0, nR = 0;
     std::vector<GroupDesc> groups;  // Dijkstra_SK groups
     std::vector<DskInfo> info;
-    std::vector<int32_t> int_local, int_g0, int_ng, int_node;  // interior table rows
-    std::vector<int32_t> out_idx;
-    std::vector<uint8_t> out_which;
-    int32_t nint = 0;
     int64_t largest = 0, kprime = 0, clique_pairs = 0, table_pairs = 0;
-    // device temporaries (set by upload)
-    int64_t* d_irp = nullptr;
+    size_t cub_bytes = 0;  // scratch of the device sort and scans
+    // phase 1 (graph scratch arena)
+    int32_t* p_lab = nullptr;
+    uint8_t* p_ist = nullptr;
+    uint8_t* p_fr = nullptr;
+    int32_t* p_S = nullptr;
+    // phase 2 (caller's arena)
+    int32_t* d_old = nullptr;  // renumbered position -> original node
+    int32_t* d_nid = nullptr;  // original node -> renumbered position
+    int64_t* d_irp = nullptr;  // intra-part CSR, renumbered
     int32_t* d_icol = nullptr;
     uint32_t* d_iw = nullptr;
     uint8_t* d_blk = nullptr;
-    int64_t* d_rptr = nullptr;
+    int32_t* d_rdeg = nullptr;  // cut arcs per skeleton node
+    int64_t* d_rptr = nullptr;  // cut arcs by skeleton id, rows sorted
     int32_t* d_rcol = nullptr;
     uint32_t* d_rw = nullptr;
-    int32_t* d_rdeg = nullptr;
     int32_t* d_cdeg = nullptr;
     DskInfo* d_info = nullptr;
-    int32_t *d_il = nullptr, *d_ig0 = nullptr, *d_ing = nullptr, *d_tdeg = nullptr;
+    int32_t *d_il = nullptr, *d_ig0 = nullptr, *d_ing = nullptr, *d_tdeg = nullptr, *d_inode = nullptr;
+    int32_t* d_out_idx = nullptr;
+    uint8_t* d_out_which = nullptr;
+    int32_t* d_nodes = nullptr;  // skeleton id -> original node
+    uint8_t* d_sflag = nullptr;  // skeleton id -> NF_TARGET
+    int32_t* d_srcsk = nullptr;  // target -> skeleton id, or -1 (isolated target)
     uint32_t* d_maxlen = nullptr;
+    uint32_t* d_rmax = nullptr;
     GroupDesc* d_desc = nullptr;
 
-    // Host part: P', frontiers, renumbering, intra-part CSR, cut arcs, groups.
     int prepare(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
                 bool given_singletons);
-    // Device bytes of upload(): temporaries plus the Dijkstra_SK group states.
+    // Device bytes of upload(): phase 2 arrays plus the Dijkstra_SK group states.
     size_t temp_bytes() const;
-    // Upper bound of the skeleton's own device bytes (all clique pairs and table
-    // entries kept).
-    size_t skeleton_bytes_bound() const;
-    // Copy the temporaries to the device and carve the group states out of W.
     int upload(Arena& W, hipStream_t s);
     // After the Dijkstra_SK groups have run: count, size and fill the skeleton.
     // get_store(bytes, arena) must hand back an arena with at least `bytes` free.

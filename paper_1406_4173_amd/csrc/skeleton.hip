@@ -11,6 +11,8 @@
 #include <memory>
 #include <numeric>
 
+#include <hipcub/hipcub.hpp>
+
 #include "engine.h"
 #include "graph.h"
 #include "skbuild.h"
@@ -144,11 +146,205 @@ __global__ void k_table(const GroupDesc* __restrict__ desc, const DskInfo* __res
 
 // ------------------------------------------------------------ partition_sk -----
 
-int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const int32_t* Sx,
-                     int32_t nS, bool given_singletons) {
+// Phase 1: P' labels (targets become singleton parts k + i, Sec. 5 "Target nodes in
+// the skeleton"), target flags, frontier flags (a neighbour in another part, Sec. 4),
+// and per part of P' its size, frontier count and intra-part arc count.
+__global__ void k_p1_labels(int32_t n, const int32_t* __restrict__ part, int32_t* __restrict__ lab,
+                            uint8_t* __restrict__ ist) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    lab[v] = part[v];
+    ist[v] = 0;
+}
+
+__global__ void k_p1_targets(int32_t nS, const int32_t* __restrict__ S, int32_t k, int given,
+                             int32_t* __restrict__ lab, uint8_t* __restrict__ ist) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nS) return;
+    if (!given) lab[S[i]] = k + i;
+    ist[S[i]] = 1;
+}
+
+__global__ void k_p1_frontier(int32_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                              const int32_t* __restrict__ lab, uint8_t* __restrict__ fr,
+                              int32_t* __restrict__ psize, int32_t* __restrict__ pnf,
+                              unsigned long long* __restrict__ parc, unsigned long long* __restrict__ ncross) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long cross = 0;
+    if (v < n) {
+        const int32_t p = lab[v];
+        unsigned long long intra = 0;
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+            if (lab[col[e]] == p)
+                ++intra;
+            else
+                ++cross;
+        }
+        fr[v] = cross ? 1 : 0;
+        atomicAdd(&psize[p], 1);
+        if (cross) atomicAdd(&pnf[p], 1);
+        if (intra) atomicAdd(&parc[p], intra);
+    }
+    for (int o = 32; o > 0; o >>= 1) cross += (unsigned long long)__shfl_xor((long long)cross, o, 64);
+    if ((threadIdx.x & 63) == 0 && cross) atomicAdd(ncross, cross);
+}
+
+// Phase 2: renumbering key (part, then frontier before interior; ties keep node order
+// in the stable sort) and the inverse map.
+__global__ void k_p2_keys(int32_t n, const int32_t* __restrict__ lab, const uint8_t* __restrict__ fr,
+                          unsigned long long* __restrict__ key, int32_t* __restrict__ val) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    key[v] = (unsigned long long)lab[v] * 2ull + (fr[v] ? 0ull : 1ull);
+    val[v] = (int32_t)v;
+}
+
+__global__ void k_p2_nid(int32_t n, const int32_t* __restrict__ old, int32_t* __restrict__ nid) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) nid[old[r]] = (int32_t)r;
+}
+
+// skeleton id of frontier node v: the part's first skeleton id plus v's offset in the
+// part's node range (frontier nodes come first)
+__device__ __forceinline__ int32_t skid_of(int32_t v, const int32_t* lab, const int32_t* nid,
+                                           const int64_t* poff, const int64_t* fbase) {
+    const int32_t p = lab[v];
+    return (int32_t)(fbase[p] + (nid[v] - poff[p]));
+}
+
+// Per renumbered row: intra-part arcs, and for frontier rows the cut arcs.
+__global__ void k_p2_count(int32_t n, const int32_t* __restrict__ old, const int64_t* __restrict__ rp,
+                           const int32_t* __restrict__ col, const int32_t* __restrict__ lab,
+                           const uint8_t* __restrict__ fr, const int64_t* __restrict__ poff,
+                           const int64_t* __restrict__ fbase, int64_t* __restrict__ icnt,
+                           int64_t* __restrict__ rcnt, int32_t* __restrict__ rdeg) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t v = old[r];
+    const int32_t p = lab[v];
+    int64_t ci = 0, cr = 0;
+    for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+        if (lab[col[e]] == p)
+            ++ci;
+        else
+            ++cr;
+    }
+    icnt[r] = ci;
+    if (fr[v]) {
+        const int64_t f = fbase[p] + (r - poff[p]);
+        rcnt[f] = cr;
+        rdeg[f] = (int32_t)cr;
+    }
+}
+
+// Fill the rows counted above. Intra arcs keep the original row's order; cut arcs are
+// inserted sorted by skeleton id (reverse arcs are found by bisection). Largest
+// cut-arc length into *rmax.
+__global__ void k_p2_fill(int32_t n, const int32_t* __restrict__ old, const int32_t* __restrict__ nid,
+                          const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                          const uint32_t* __restrict__ w, const int32_t* __restrict__ lab,
+                          const uint8_t* __restrict__ fr, const int64_t* __restrict__ poff,
+                          const int64_t* __restrict__ fbase, const int64_t* __restrict__ irp,
+                          const int64_t* __restrict__ rptr, int32_t* __restrict__ icol,
+                          uint32_t* __restrict__ iw, int32_t* __restrict__ rcol, uint32_t* __restrict__ rw,
+                          uint32_t* __restrict__ rmax) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t v = old[r];
+    const int32_t p = lab[v];
+    int64_t o = irp[r];
+    for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+        const int32_t u = col[e];
+        if (lab[u] != p) continue;
+        icol[o] = nid[u];
+        if (iw) iw[o] = w ? w[e] : 1u;
+        ++o;
+    }
+    if (!fr[v]) return;
+    const int64_t f = fbase[p] + (r - poff[p]);
+    const int64_t a = rptr[f];
+    int64_t b = a;
+    uint32_t mx = 0;
+    for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+        const int32_t u = col[e];
+        if (lab[u] == p) continue;
+        const int32_t q = skid_of(u, lab, nid, poff, fbase);
+        const uint32_t L = w ? w[e] : 1u;
+        int64_t j = b;
+        while (j > a && rcol[j - 1] > q) {
+            rcol[j] = rcol[j - 1];
+            rw[j] = rw[j - 1];
+            --j;
+        }
+        rcol[j] = q;
+        rw[j] = L;
+        ++b;
+        mx = max(mx, L);
+    }
+    if (mx) atomicMax(rmax, mx);
+}
+
+// Per renumbered row: blocked flag (frontier nodes, eq. frontierparents), output map
+// (skeleton id, interior table row or none), skeleton node lists, interior rows.
+__global__ void k_p2_rows(int32_t n, const int32_t* __restrict__ old, const int32_t* __restrict__ lab,
+                          const uint8_t* __restrict__ fr, const uint8_t* __restrict__ ist,
+                          const int64_t* __restrict__ poff, const int64_t* __restrict__ fbase,
+                          const int32_t* __restrict__ pnf, const int32_t* __restrict__ pg0,
+                          const int32_t* __restrict__ png, const int32_t* __restrict__ ibase,
+                          uint8_t* __restrict__ blk, int32_t* __restrict__ il, int32_t* __restrict__ ig0,
+                          int32_t* __restrict__ ing, int32_t* __restrict__ inode, int32_t* __restrict__ out_idx,
+                          uint8_t* __restrict__ out_which, int32_t* __restrict__ nodes,
+                          uint8_t* __restrict__ sflag) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t v = old[r];
+    const int32_t p = lab[v];
+    const int64_t loc = r - poff[p];
+    blk[r] = fr[v] ? (uint8_t)NF_BLOCKED : 0;
+    if (fr[v]) {
+        const int64_t f = fbase[p] + loc;
+        out_idx[v] = (int32_t)f;
+        out_which[v] = 0;
+        nodes[f] = v;
+        sflag[f] = ist[v] ? (uint8_t)NF_TARGET : 0;
+    } else if (png[p] > 0) {
+        const int64_t i = ibase[p] + (loc - pnf[p]);
+        il[i] = (int32_t)loc;
+        ig0[i] = pg0[p];
+        ing[i] = png[p];
+        inode[i] = v;
+        out_idx[v] = (int32_t)i;
+        out_which[v] = 1;
+    } else {
+        out_idx[v] = -1;
+        out_which[v] = 0;
+    }
+}
+
+__global__ void k_p2_src(int32_t nS, const int32_t* __restrict__ S, const uint8_t* __restrict__ fr,
+                         const int32_t* __restrict__ lab, const int32_t* __restrict__ nid,
+                         const int64_t* __restrict__ poff, const int64_t* __restrict__ fbase,
+                         int32_t* __restrict__ srcsk) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nS) return;
+    const int32_t v = S[i];
+    srcsk[i] = fr[v] ? skid_of(v, lab, nid, poff, fbase) : -1;
+}
+
+static unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>((n + 255) / 256, 1); }
+
+static int key_bits(int64_t nlab) {
+    int b = 1;
+    while (b < 63 && ((int64_t)1 << b) < 2 * nlab + 2) ++b;
+    return b;
+}
+
+int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const int32_t* Sx, int32_t nSx,
+                     bool given_singletons) {
     PhaseTrace tr("prepare");
     g = gr;
     n = g->n;
+    nS = nSx;
     if (n > 0 && !part) return fail(BC_E_INVAL, "null partition");
     if (n > 0 && k < 1) return fail(BC_E_INVAL, "k must be >= 1");
     for (int32_t v = 0; v < n; ++v)
@@ -156,199 +352,216 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
             return fail(BC_E_INVAL, "partition label out of range at node " + std::to_string(v));
     BC_TRY(validate_targets(n, Sx, nS));
     S.assign(Sx, Sx + nS);
-    const int64_t* rp = g->h_row_ptr.data();
-    const int32_t* cl = g->h_col.data();
-    const int32_t* wt = g->h_w.empty() ? nullptr : g->h_w.data();
-    weighted = wt != nullptr;
-
-    // ---- P' (Step 1, "Target nodes in the skeleton") and frontiers (Sec. 4)
+    weighted = g->d_len != nullptr;
     nlab = (int64_t)k + (given_singletons ? 0 : nS);
-    lab.assign(part, part + n);
-    is_t.assign(n, 0);
-    for (int32_t i = 0; i < nS; ++i) {
-        if (!given_singletons) lab[S[i]] = k + i;
-        is_t[S[i]] = 1;
-    }
-    fr.assign(n, 0);
-    parallel_for(n, 16384, [&](int64_t a, int64_t b) {
-        for (int64_t v = a; v < b; ++v)
-            for (int64_t e = rp[v]; e < rp[v + 1]; ++e)
-                if (lab[cl[e]] != lab[v]) {
-                    fr[v] = 1;
-                    break;
-                }
-    });
-    tr.mark("validate, P', frontiers");
-    // ---- renumbering: parts contiguous, frontier first
-    psize.assign(nlab + 1, 0);
+    if (nlab >= INT32_MAX) return fail(BC_E_INVAL, "too many parts");
+    hipStream_t s = g->stream;
+    tr.mark("validate");
+
+    // ---- phase 1 on the device
+    psize.assign(nlab, 0);
     pnf.assign(nlab, 0);
-    for (int32_t v = 0; v < n; ++v) {
-        psize[lab[v]]++;
-        pnf[lab[v]] += fr[v];
+    parc.assign(nlab, 0);
+    uint64_t cross = 0;
+    if (n > 0) {
+        bc_graph* gm = const_cast<bc_graph*>(g);
+        Arena& P = gm->pre;
+        const size_t need = (size_t)n * 4 * 2 + (size_t)n * 2 + (size_t)nS * 4 + (size_t)nlab * 16 + 16 * 256;
+        BC_TRY(P.reserve(need));
+        int32_t* d_part = P.take<int32_t>(n);
+        p_lab = P.take<int32_t>(n);
+        p_ist = P.take<uint8_t>(n);
+        p_fr = P.take<uint8_t>(n);
+        p_S = P.take<int32_t>(std::max(nS, 1));
+        int32_t* d_psize = P.take<int32_t>(nlab);
+        int32_t* d_pnf = P.take<int32_t>(nlab);
+        unsigned long long* d_parc = P.take<unsigned long long>(nlab);
+        unsigned long long* d_cross = P.take<unsigned long long>(1);
+        if (!d_cross) return fail(BC_E_NOMEM, "partition: scratch too small");
+        BC_HIP(hipMemcpyAsync(d_part, part, (size_t)n * 4, hipMemcpyHostToDevice, s));
+        if (nS) BC_HIP(hipMemcpyAsync(p_S, S.data(), (size_t)nS * 4, hipMemcpyHostToDevice, s));
+        BC_HIP(hipMemsetAsync(d_psize, 0, (size_t)nlab * 4, s));
+        BC_HIP(hipMemsetAsync(d_pnf, 0, (size_t)nlab * 4, s));
+        BC_HIP(hipMemsetAsync(d_parc, 0, (size_t)nlab * 8, s));
+        BC_HIP(hipMemsetAsync(d_cross, 0, 8, s));
+        {
+            KTimer kt(BC_K_OTHER, s);
+            hipLaunchKernelGGL(k_p1_labels, dim3(blocks_for(n)), dim3(256), 0, s, n, d_part, p_lab, p_ist);
+            if (nS)
+                hipLaunchKernelGGL(k_p1_targets, dim3(blocks_for(nS)), dim3(256), 0, s, nS, p_S, k,
+                                   given_singletons ? 1 : 0, p_lab, p_ist);
+            hipLaunchKernelGGL(k_p1_frontier, dim3(blocks_for(n)), dim3(256), 0, s, n, g->d_row_ptr, g->d_col,
+                               p_lab, p_fr, d_psize, d_pnf, d_parc, d_cross);
+        }
+        BC_HIP(hipGetLastError());
+        BC_HIP(hipMemcpyAsync(psize.data(), d_psize, (size_t)nlab * 4, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(pnf.data(), d_pnf, (size_t)nlab * 4, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(parc.data(), d_parc, (size_t)nlab * 8, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(&cross, d_cross, 8, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipStreamSynchronize(s));
     }
+    tr.mark("phase 1 (device)");
+
+    // ---- per part on the host: offsets, Dijkstra_SK groups, interior rows
     poff.assign(nlab + 1, 0);
     fbase.assign(nlab + 1, 0);
+    aoff.assign(nlab + 1, 0);
     for (int64_t p = 0; p < nlab; ++p) {
         poff[p + 1] = poff[p] + psize[p];
         fbase[p + 1] = fbase[p] + pnf[p];
-    }
-    std::vector<int64_t> fcur(nlab), icur(nlab);
-    for (int64_t p = 0; p < nlab; ++p) {
-        fcur[p] = poff[p];
-        icur[p] = poff[p] + pnf[p];
-    }
-    nid.assign(n, 0);
-    old.assign(n, 0);
-    for (int32_t v = 0; v < n; ++v) {
-        const int32_t p = lab[v];
-        const int64_t r = fr[v] ? fcur[p]++ : icur[p]++;
-        nid[v] = (int32_t)r;
-        old[r] = v;
+        aoff[p + 1] = aoff[p] + (int64_t)parc[p];
     }
     nsk = (int32_t)fbase[nlab];
-    auto skid = [&](int32_t v) -> int32_t { return (int32_t)(fbase[lab[v]] + (nid[v] - poff[lab[v]])); };
-
-    tr.mark("renumbering");
-    // ---- intra-part CSR (renumbered) and the cut arcs R by skeleton id: count per
-    // renumbered row, prefix sums, then fill (rows in parallel)
-    irp.assign(n + 1, 0);
-    rptr.assign(nsk + 1, 0);
-    parallel_for(n, 8192, [&](int64_t a, int64_t b) {
-        for (int64_t r = a; r < b; ++r) {
-            const int32_t v = old[r];
-            int64_t ci = 0, cr = 0;
-            for (int64_t e = rp[v]; e < rp[v + 1]; ++e) (lab[cl[e]] == lab[v] ? ci : cr)++;
-            irp[r + 1] = ci;
-            if (fr[v]) rptr[skid(v) + 1] = cr;
-        }
-    });
-    for (int32_t r = 0; r < n; ++r) irp[r + 1] += irp[r];
-    for (int32_t f = 0; f < nsk; ++f) rptr[f + 1] += rptr[f];
-    icol.resize((size_t)irp[n]);
-    iw.resize(wt ? (size_t)irp[n] : 0);
-    rcol.resize((size_t)rptr[nsk]);
-    rw.resize((size_t)rptr[nsk]);
-    parallel_for(n, 8192, [&](int64_t a, int64_t b) {
-        std::vector<std::pair<int32_t, uint32_t>> tmp;
-        for (int64_t r = a; r < b; ++r) {
-            const int32_t v = old[r];
-            int64_t oi = irp[r];
-            for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
-                const int32_t u = cl[e];
-                if (lab[u] == lab[v]) {
-                    icol[oi] = nid[u];
-                    if (wt) iw[oi] = (uint32_t)wt[e];
-                    ++oi;
-                }
-            }
-            if (!fr[v]) continue;
-            // cut arcs of a frontier row, sorted by skeleton id (reverse arcs are found
-            // by bisection)
-            tmp.clear();
-            for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
-                const int32_t u = cl[e];
-                if (lab[u] != lab[v]) tmp.push_back({skid(u), wt ? (uint32_t)wt[e] : 1u});
-            }
-            std::sort(tmp.begin(), tmp.end());
-            int64_t o = rptr[skid(v)];
-            for (auto& t : tmp) {
-                rcol[o] = t.first;
-                rw[o] = t.second;
-                ++o;
-            }
-        }
-    });
-    nR = (int64_t)rcol.size();
-
-    tr.mark("intra CSR, R arcs");
-    // ---- Dijkstra_SK groups: every part with >= 2 nodes and a frontier
+    n_intra = aoff[nlab];
+    nR = (int64_t)cross;
     groups.clear();
     info.clear();
-    std::vector<int32_t> p_g0(nlab, 0), p_ng(nlab, 0);
+    p_g0.assign(nlab, 0);
+    p_ng.assign(nlab, 0);
+    ibase.assign(nlab, 0);
     largest = kprime = clique_pairs = table_pairs = 0;
+    int64_t rows = 0;
     for (int64_t p = 0; p < nlab; ++p) {
         if (psize[p] > 0) kprime++;
-        largest = std::max(largest, psize[p]);
+        largest = std::max<int64_t>(largest, psize[p]);
         if (psize[p] < 2 || pnf[p] == 0) continue;
-        clique_pairs += pnf[p] * (pnf[p] - 1);
-        table_pairs += pnf[p] * (psize[p] - pnf[p]);
+        clique_pairs += (int64_t)pnf[p] * (pnf[p] - 1);
+        table_pairs += (int64_t)pnf[p] * (psize[p] - pnf[p]);
         p_g0[p] = (int32_t)groups.size();
         for (int64_t c = 0; c < pnf[p]; c += LANES) {
             GroupDesc G;
             G.lo = (int32_t)poff[p];
             G.hi = (int32_t)(poff[p] + psize[p]);
-            G.arcs = irp[G.hi] - irp[G.lo];
-            G.flags = GF_RESTRICT | (wt ? 0u : GF_UNIT);
+            G.arc_lo = aoff[p];
+            G.arcs = (int64_t)parc[p];
+            G.flags = GF_RESTRICT | (weighted ? 0u : GF_UNIT);
             G.ring_len = g->maxw + 1;
             G.nsrc = (int32_t)std::min<int64_t>(LANES, pnf[p] - c);
             for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? (int32_t)(poff[p] + c + b) : -1;
             groups.push_back(G);
-            info.push_back({(int32_t)pnf[p], (int32_t)c, G.nsrc, (int32_t)fbase[p]});
+            info.push_back({pnf[p], (int32_t)c, G.nsrc, (int32_t)fbase[p]});
         }
         p_ng[p] = (int32_t)groups.size() - p_g0[p];
+        ibase[p] = (int32_t)rows;
+        rows += psize[p] - pnf[p];
     }
-    // interior rows: non-frontier nodes of parts with groups, in renumbered order
-    int_local.clear();
-    int_g0.clear();
-    int_ng.clear();
-    int_node.clear();
-    out_idx.assign(n, -1);
-    out_which.assign(n, 0);
-    for (int64_t p = 0; p < nlab; ++p) {
-        if (p_ng[p] == 0) continue;
-        for (int64_t r = poff[p] + pnf[p]; r < poff[p + 1]; ++r) {
-            out_idx[old[r]] = (int32_t)int_local.size();
-            out_which[old[r]] = 1;
-            int_local.push_back((int32_t)(r - poff[p]));
-            int_g0.push_back(p_g0[p]);
-            int_ng.push_back(p_ng[p]);
-            int_node.push_back(old[r]);
-        }
+    if (rows >= INT32_MAX) return fail(BC_E_INVAL, "too many interior nodes");
+    nint = (int32_t)rows;
+    // scratch of the device sort and scans
+    cub_bytes = 0;
+    if (n > 0) {
+        size_t b = 0;
+        BC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, (unsigned long long*)nullptr,
+                                                  (unsigned long long*)nullptr, (int32_t*)nullptr,
+                                                  (int32_t*)nullptr, n, 0, key_bits(nlab), s));
+        cub_bytes = std::max(cub_bytes, b);
+        BC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, n + 1, s));
+        cub_bytes = std::max(cub_bytes, b);
+        BC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, nsk + 1, s));
+        cub_bytes = std::max(cub_bytes, b);
     }
-    for (int32_t v = 0; v < n; ++v)
-        if (fr[v]) out_idx[v] = skid(v);
-    nint = (int32_t)int_local.size();
     tr.mark("groups, interior rows");
     return BC_OK;
 }
 
 size_t SkBuild::temp_bytes() const {
-    const int32_t ng = (int32_t)groups.size();
+    const size_t ng = groups.size();
     size_t need = 0;
     for (const auto& G : groups) need += group_bytes(G, 0);
-    need += (size_t)(n + 1) * 8 + icol.size() * 4 + iw.size() * 4 + (size_t)n +
-            (size_t)(nsk + 1) * 8 * 2 + (size_t)nR * 8 + (size_t)nsk * 8 + (size_t)ng * sizeof(DskInfo) +
-            (size_t)ng * sizeof(GroupDesc) + (size_t)nint * 16 + 64 * 256;
+    const size_t N = (size_t)std::max(n, 1), K = (size_t)std::max(nsk, 1), I = (size_t)std::max(nint, 1);
+    need += N * (8 + 8 + 4 + 4 + 4 + 8 + 8 + 1 + 4 + 1) + 16 +  // keys, vals, old, nid, counts, irp, blk, out
+            (size_t)n_intra * (weighted ? 8 : 4) + (size_t)nR * 8 + K * (8 + 4 + 8 + 4 + 4 + 1) + 16 +
+            ng * (sizeof(DskInfo) + sizeof(GroupDesc)) + I * 20 + (size_t)std::max(nS, 1) * 4 +
+            (size_t)(nlab + 1) * (8 * 2 + 4 * 4) + cub_bytes + 48 * 256;
     return need;
 }
 
-size_t SkBuild::skeleton_bytes_bound() const {
-    const int64_t M = nR + clique_pairs, T = table_pairs;
-    return (size_t)(nsk + 1) * 8 + (size_t)M * (4 + 4 + 8 + 8) + (size_t)nsk + (size_t)(nint + 1) * 8 +
-           (size_t)T * (4 + 4 + 8) + (size_t)nsk * 4 + (size_t)nint * 4 + (size_t)n * 5 + 32 * 256;
-}
-
 int SkBuild::upload(Arena& W, hipStream_t s) {
+    PhaseTrace tr("upload");
     const int32_t ng = (int32_t)groups.size();
+    const int64_t NL = std::max<int64_t>(nlab, 1);
+    unsigned long long* keys = W.take<unsigned long long>(std::max(n, 1));
+    unsigned long long* keys2 = W.take<unsigned long long>(std::max(n, 1));
+    int32_t* vals = W.take<int32_t>(std::max(n, 1));
+    d_old = W.take<int32_t>(std::max(n, 1));
+    d_nid = W.take<int32_t>(std::max(n, 1));
+    int64_t* icnt = W.take<int64_t>(n + 1);
     d_irp = W.take<int64_t>(n + 1);
-    d_icol = W.take<int32_t>(std::max<size_t>(icol.size(), 1));
-    d_iw = weighted ? W.take<uint32_t>(std::max<size_t>(iw.size(), 1)) : nullptr;
+    d_icol = W.take<int32_t>(std::max<int64_t>(n_intra, 1));
+    d_iw = weighted ? W.take<uint32_t>(std::max<int64_t>(n_intra, 1)) : nullptr;
     d_blk = W.take<uint8_t>(std::max(n, 1));
+    int64_t* rcnt = W.take<int64_t>(nsk + 1);
+    d_rdeg = W.take<int32_t>(std::max(nsk, 1));
     d_rptr = W.take<int64_t>(nsk + 1);
     d_rcol = W.take<int32_t>(std::max<int64_t>(nR, 1));
     d_rw = W.take<uint32_t>(std::max<int64_t>(nR, 1));
-    d_rdeg = W.take<int32_t>(std::max(nsk, 1));
     d_cdeg = W.take<int32_t>(std::max(nsk, 1));
     d_info = W.take<DskInfo>(std::max(ng, 1));
     d_il = W.take<int32_t>(std::max(nint, 1));
     d_ig0 = W.take<int32_t>(std::max(nint, 1));
     d_ing = W.take<int32_t>(std::max(nint, 1));
     d_tdeg = W.take<int32_t>(std::max(nint, 1));
+    d_inode = W.take<int32_t>(std::max(nint, 1));
+    d_out_idx = W.take<int32_t>(std::max(n, 1));
+    d_out_which = W.take<uint8_t>(std::max(n, 1));
+    d_nodes = W.take<int32_t>(std::max(nsk, 1));
+    d_sflag = W.take<uint8_t>(std::max(nsk, 1));
+    d_srcsk = W.take<int32_t>(std::max(nS, 1));
+    int64_t* d_poff = W.take<int64_t>(NL + 1);
+    int64_t* d_fbase = W.take<int64_t>(NL + 1);
+    int32_t* d_pnf = W.take<int32_t>(NL);
+    int32_t* d_pg0 = W.take<int32_t>(NL);
+    int32_t* d_png = W.take<int32_t>(NL);
+    int32_t* d_ibase = W.take<int32_t>(NL);
     d_maxlen = W.take<uint32_t>(1);
+    d_rmax = W.take<uint32_t>(1);
+    void* cub = W.take<unsigned char>(std::max<size_t>(cub_bytes, 1));
     d_desc = W.take<GroupDesc>(std::max(ng, 1));
-    if (!d_irp || !d_icol || !d_blk || !d_rptr || !d_rcol || !d_rw || !d_rdeg || !d_cdeg || !d_info ||
-        !d_il || !d_ig0 || !d_ing || !d_tdeg || !d_maxlen || !d_desc || (weighted && !d_iw))
+    if (!keys || !keys2 || !vals || !d_old || !d_nid || !icnt || !d_irp || !d_icol || (weighted && !d_iw) ||
+        !d_blk || !rcnt || !d_rdeg || !d_rptr || !d_rcol || !d_rw || !d_cdeg || !d_info || !d_il || !d_ig0 ||
+        !d_ing || !d_tdeg || !d_inode || !d_out_idx || !d_out_which || !d_nodes || !d_sflag || !d_srcsk ||
+        !d_poff || !d_fbase || !d_pnf || !d_pg0 || !d_png || !d_ibase || !d_maxlen || !d_rmax || !cub ||
+        !d_desc)
         return fail(BC_E_NOMEM, "partition: workspace too small");
+    auto h2d = [&](void* d, const void* h, size_t b) -> int {
+        if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s));
+        return BC_OK;
+    };
+    BC_TRY(h2d(d_poff, poff.data(), (size_t)(nlab + 1) * 8));
+    BC_TRY(h2d(d_fbase, fbase.data(), (size_t)(nlab + 1) * 8));
+    BC_TRY(h2d(d_pnf, pnf.data(), (size_t)nlab * 4));
+    BC_TRY(h2d(d_pg0, p_g0.data(), (size_t)nlab * 4));
+    BC_TRY(h2d(d_png, p_ng.data(), (size_t)nlab * 4));
+    BC_TRY(h2d(d_ibase, ibase.data(), (size_t)nlab * 4));
+    BC_TRY(h2d(d_info, info.data(), (size_t)ng * sizeof(DskInfo)));
+    if (nsk) BC_HIP(hipMemsetAsync(d_cdeg, 0, (size_t)nsk * 4, s));
+    BC_HIP(hipMemsetAsync(d_maxlen, 0, 4, s));
+    BC_HIP(hipMemsetAsync(d_rmax, 0, 4, s));
+    BC_HIP(hipMemsetAsync(icnt + n, 0, 8, s));
+    BC_HIP(hipMemsetAsync(rcnt + nsk, 0, 8, s));
+    if (n > 0) {
+        KTimer kt(BC_K_OTHER, s);
+        size_t cb = cub_bytes;
+        hipLaunchKernelGGL(k_p2_keys, dim3(blocks_for(n)), dim3(256), 0, s, n, p_lab, p_fr, keys, vals);
+        BC_HIP(hipcub::DeviceRadixSort::SortPairs(cub, cb, keys, keys2, vals, d_old, n, 0, key_bits(nlab), s));
+        hipLaunchKernelGGL(k_p2_nid, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, d_nid);
+        hipLaunchKernelGGL(k_p2_count, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, g->d_row_ptr, g->d_col,
+                           p_lab, p_fr, d_poff, d_fbase, icnt, rcnt, d_rdeg);
+        cb = cub_bytes;
+        BC_HIP(hipcub::DeviceScan::ExclusiveSum(cub, cb, icnt, d_irp, n + 1, s));
+        cb = cub_bytes;
+        BC_HIP(hipcub::DeviceScan::ExclusiveSum(cub, cb, rcnt, d_rptr, nsk + 1, s));
+        hipLaunchKernelGGL(k_p2_fill, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, d_nid, g->d_row_ptr,
+                           g->d_col, g->d_len, p_lab, p_fr, d_poff, d_fbase, d_irp, d_rptr, d_icol, d_iw,
+                           d_rcol, d_rw, d_rmax);
+        hipLaunchKernelGGL(k_p2_rows, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, p_lab, p_fr, p_ist, d_poff,
+                           d_fbase, d_pnf, d_pg0, d_png, d_ibase, d_blk, d_il, d_ig0, d_ing, d_inode, d_out_idx,
+                           d_out_which, d_nodes, d_sflag);
+        if (nS)
+            hipLaunchKernelGGL(k_p2_src, dim3(blocks_for(nS)), dim3(256), 0, s, nS, p_S, p_fr, p_lab, d_nid,
+                               d_poff, d_fbase, d_srcsk);
+    }
+    BC_HIP(hipGetLastError());
     for (auto& G : groups) {
         G.g.row_ptr = d_irp;
         G.g.col = d_icol;
@@ -356,31 +569,11 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
         G.g.nflag = d_blk;
         if (!group_alloc(W, G, 0)) return fail(BC_E_NOMEM, "partition: group state does not fit");
     }
-    std::vector<uint8_t> blk(n);
-    for (int32_t r = 0; r < n; ++r) blk[r] = fr[old[r]] ? (uint8_t)NF_BLOCKED : 0;
-    std::vector<int32_t> rdeg(nsk);
-    for (int32_t f = 0; f < nsk; ++f) rdeg[f] = (int32_t)(rptr[f + 1] - rptr[f]);
-    auto h2d = [&](void* d, const void* h, size_t b) -> int {
-        if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s));
-        return BC_OK;
-    };
-    BC_TRY(h2d(d_irp, irp.data(), (size_t)(n + 1) * 8));
-    BC_TRY(h2d(d_icol, icol.data(), icol.size() * 4));
-    if (weighted) BC_TRY(h2d(d_iw, iw.data(), iw.size() * 4));
-    BC_TRY(h2d(d_blk, blk.data(), n));
-    BC_TRY(h2d(d_rptr, rptr.data(), (size_t)(nsk + 1) * 8));
-    BC_TRY(h2d(d_rcol, rcol.data(), (size_t)nR * 4));
-    BC_TRY(h2d(d_rw, rw.data(), (size_t)nR * 4));
-    BC_TRY(h2d(d_rdeg, rdeg.data(), (size_t)nsk * 4));
-    BC_TRY(h2d(d_info, info.data(), (size_t)ng * sizeof(DskInfo)));
-    BC_TRY(h2d(d_il, int_local.data(), (size_t)nint * 4));
-    BC_TRY(h2d(d_ig0, int_g0.data(), (size_t)nint * 4));
-    BC_TRY(h2d(d_ing, int_ng.data(), (size_t)nint * 4));
     BC_TRY(h2d(d_desc, groups.data(), (size_t)ng * sizeof(GroupDesc)));
-    if (nsk) BC_HIP(hipMemsetAsync(d_cdeg, 0, (size_t)nsk * 4, s));
-    BC_HIP(hipMemsetAsync(d_maxlen, 0, 4, s));
-    // the host copies above are staged by the runtime; wait so the caller may reuse them
+    // host arrays above are staged by the runtime; after this the scratch arena of the
+    // graph is no longer read
     BC_HIP(hipStreamSynchronize(s));
+    tr.mark("phase 2 (device)");
     return BC_OK;
 }
 
@@ -396,14 +589,17 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
                                d_ig0, d_ing, d_tdeg, nullptr, nullptr, nullptr, nullptr);
     }
     BC_HIP(hipGetLastError());
-    std::vector<int32_t> cdeg(nsk, 0), tdeg(nint, 0);
-    if (nsk) BC_HIP(hipMemcpyAsync(cdeg.data(), d_cdeg, (size_t)nsk * 4, hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> cdeg(nsk, 0), rdeg(nsk, 0), tdeg(nint, 0);
+    if (nsk) {
+        BC_HIP(hipMemcpyAsync(cdeg.data(), d_cdeg, (size_t)nsk * 4, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(rdeg.data(), d_rdeg, (size_t)nsk * 4, hipMemcpyDeviceToHost, s));
+    }
     if (nint && ng) BC_HIP(hipMemcpyAsync(tdeg.data(), d_tdeg, (size_t)nint * 4, hipMemcpyDeviceToHost, s));
     BC_HIP(hipStreamSynchronize(s));
     std::vector<int64_t> srow(nsk + 1, 0), trow(nint + 1, 0);
     int64_t ncl = 0;
     for (int32_t f = 0; f < nsk; ++f) {
-        srow[f + 1] = srow[f] + (rptr[f + 1] - rptr[f]) + cdeg[f];
+        srow[f + 1] = srow[f] + rdeg[f] + cdeg[f];
         ncl += cdeg[f];
     }
     for (int32_t i = 0; i < nint; ++i) trow[i + 1] = trow[i] + tdeg[i];
@@ -431,27 +627,21 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
     sk->d_out_idx = A.take<int32_t>(std::max(n, 1));
     sk->d_out_which = A.take<uint8_t>(std::max(n, 1));
     if (!sk->d_out_which) return fail(BC_E_NOMEM, "skeleton store too small");
-    auto skid = [&](int32_t v) -> int32_t { return (int32_t)(fbase[lab[v]] + (nid[v] - poff[lab[v]])); };
-    std::vector<uint8_t> sflag(nsk, 0);
-    std::vector<int32_t> nodes(nsk);
-    for (int32_t r = 0; r < n; ++r) {
-        const int32_t v = old[r];
-        if (!fr[v]) continue;
-        const int32_t f = skid(v);
-        nodes[f] = v;
-        if (is_t[v]) sflag[f] = (uint8_t)NF_TARGET;
-    }
     auto h2d = [&](void* d, const void* h, size_t b) -> int {
         if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s));
         return BC_OK;
     };
+    auto d2d = [&](void* d, const void* h, size_t b) -> int {
+        if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyDeviceToDevice, s));
+        return BC_OK;
+    };
     BC_TRY(h2d(sk->d_row_ptr, srow.data(), (size_t)(nsk + 1) * 8));
     BC_TRY(h2d(sk->d_trow, trow.data(), (size_t)(nint + 1) * 8));
-    BC_TRY(h2d(sk->d_nflag, sflag.data(), nsk));
-    BC_TRY(h2d(sk->d_nodes, nodes.data(), (size_t)nsk * 4));
-    BC_TRY(h2d(sk->d_tnode, int_node.data(), (size_t)nint * 4));
-    BC_TRY(h2d(sk->d_out_idx, out_idx.data(), (size_t)n * 4));
-    BC_TRY(h2d(sk->d_out_which, out_which.data(), n));
+    BC_TRY(d2d(sk->d_nflag, d_sflag, nsk));
+    BC_TRY(d2d(sk->d_nodes, d_nodes, (size_t)nsk * 4));
+    BC_TRY(d2d(sk->d_tnode, d_inode, (size_t)nint * 4));
+    BC_TRY(d2d(sk->d_out_idx, d_out_idx, (size_t)n * 4));
+    BC_TRY(d2d(sk->d_out_which, d_out_which, n));
     {
         KTimer kt(BC_K_OTHER, s);
         if (nsk)
@@ -469,22 +659,27 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
                                sk->d_col, sk->d_twin);
     }
     BC_HIP(hipGetLastError());
-    uint32_t clique_max = 0;
+    uint32_t clique_max = 0, rmax = 0;
+    std::vector<int32_t> srcsk(nS);
+    sk->h_out_idx.resize(n);
+    sk->h_out_which.resize(n);
     BC_HIP(hipMemcpyAsync(&clique_max, d_maxlen, 4, hipMemcpyDeviceToHost, s));
+    BC_HIP(hipMemcpyAsync(&rmax, d_rmax, 4, hipMemcpyDeviceToHost, s));
+    if (nS) BC_HIP(hipMemcpyAsync(srcsk.data(), d_srcsk, (size_t)nS * 4, hipMemcpyDeviceToHost, s));
+    if (n) {
+        BC_HIP(hipMemcpyAsync(sk->h_out_idx.data(), d_out_idx, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(sk->h_out_which.data(), d_out_which, n, hipMemcpyDeviceToHost, s));
+    }
     BC_HIP(hipStreamSynchronize(s));
-    uint32_t rmax = 1;
-    for (uint32_t x : rw) rmax = std::max(rmax, x);
 
     sk->graph = g;
     sk->n = n;
-    sk->max_len = (int32_t)std::max(rmax, clique_max);
+    sk->max_len = (int32_t)std::max<uint32_t>({1u, rmax, clique_max});
     // Brandes_SK sources: targets that have a neighbour (isolated targets reach nobody)
     sk->h_src.clear();
-    for (int32_t v : S)
-        if (fr[v]) sk->h_src.push_back(skid(v));
+    for (int32_t f : srcsk)
+        if (f >= 0) sk->h_src.push_back(f);
     sk->h_row_ptr = srow;
-    sk->h_out_idx = out_idx;
-    sk->h_out_which = out_which;
     sk->n_sk = nsk;
     sk->n_int = nint;
     sk->m_arcs = M;
