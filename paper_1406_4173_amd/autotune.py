@@ -3,7 +3,7 @@
 Usage (on a machine with the GPU): python -m paper_1406_4173_amd.autotune [--out PATH]
 then rebuild (python -m paper_1406_4173_amd.build_lib).
 
-Two choices are tuned, both fixed per build so that a graph gets the same launch
+Three choices are tuned, all fixed per build so that a graph gets the same launch
 shape alone, inside a batch or in the server (results then agree bit for bit):
 
 * threads per workgroup by node range: every graph of a sweep over community graphs
@@ -12,7 +12,10 @@ shape alone, inside a batch or in the server (results then agree bit for bit):
   range thresholds are placed between the sizes where the best choice changes;
 * sources per group, ceil(|S| / div): div in {256, 512, 1024, 2048, 4096} timed on the
   10,000-node stochastic block model (S = V) and the 256-graph batch, and the div with
-  the smallest sum of times relative to each workload's best is kept.
+  the smallest sum of times relative to each workload's best is kept;
+* the dense-step threshold of bucket frontiers (a step with more than range >> shift
+  bucket bits scans the range): shifts 1 to 6, and 63 (scan nearly always), timed the
+  same way on three 10,000 to 100,000-node graphs and the batch's Brandes++ pass.
 
 The timed call is plain target-set Brandes on the device (bc_brandes_plain_dev, or a
 batch run); the sweep uses the library only through its Python binding.
@@ -56,7 +59,7 @@ def _force_threads(T):
 
 
 def _clear():
-    for k in ("BCPP_TUNE_SMALL", "BCPP_TUNE_MID", "BCPP_TUNE_SPG_DIV"):
+    for k in ("BCPP_TUNE_SMALL", "BCPP_TUNE_MID", "BCPP_TUNE_SPG_DIV", "BCPP_TUNE_DENSE_SHIFT"):
         os.environ.pop(k, None)
 
 
@@ -120,14 +123,39 @@ def sweep_spg(bcpp, inputs, torch, log):
     return min(rows, key=lambda d: rows[d][0] / ba + rows[d][1] / bb)
 
 
-def write_header(path, small, mid, div, log):
+def sweep_dense(bcpp, inputs, torch, log):
+    """Bucket steps with more than range >> shift bits scan the range instead; the
+    shift only moves time (both visits queue the same nodes in the same order)."""
+    work = []
+    for name in ("sbm_10k", "smallcut_100k", "pareto_100k"):
+        g = getattr(inputs, name)()
+        G = bcpp.Graph(g)
+        S = torch.tensor(g.S, dtype=torch.int32, device="cuda")
+        out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        work.append((name + " plain", lambda G=G, S=S, out=out: bcpp.brandes_plain_dev(G, S, out)))
+    gs = inputs.batch_256()
+    work.append(("batch_256 pp", lambda: bcpp.Batch(gs).run(pp=True)))
+    rows = {}
+    for shift in (1, 2, 3, 4, 6, 63):
+        os.environ["BCPP_TUNE_DENSE_SHIFT"] = str(shift)
+        rows[shift] = [_time(f, torch.cuda.synchronize, reps=2) for _, f in work]
+        log.append(f"dense shift {shift:2d}: " + "  ".join(
+            f"{name} {t*1e3:8.3f} ms" for (name, _), t in zip(work, rows[shift])))
+        print(log[-1], flush=True)
+    _clear()
+    best = [min(r[i] for r in rows.values()) for i in range(len(work))]
+    return min(rows, key=lambda k: sum(t / b for t, b in zip(rows[k], best)))
+
+
+def write_header(path, small, mid, div, dense, log):
     lines = [
         "// Launch shapes of the resident kernel. Written by paper_1406_4173_amd/autotune.py from",
         "// timings on one MI355X; edit by re-running it, not by hand.",
         "//",
         "// Node ranges up to tuned_small_range run with 256 threads per workgroup, up to",
         "// tuned_mid_range with 512, larger ones with 1024. A group holds",
-        "// ceil(|S| / tuned_spg_div) sources (1..64).",
+        "// ceil(|S| / tuned_spg_div) sources (1..64). A bucket step of a range of n nodes",
+        "// with more than n >> tuned_dense_shift bits scans the range instead.",
         "//",
         "// Timings of the sweep (best of 3, plain target-set Brandes on the device):",
     ]
@@ -140,6 +168,7 @@ def write_header(path, small, mid, div, log):
         f"constexpr int64_t tuned_small_range = {small};",
         f"constexpr int64_t tuned_mid_range = {mid};",
         f"constexpr int64_t tuned_spg_div = {div};",
+        f"constexpr int64_t tuned_dense_shift = {dense};",
         "}  // namespace bcpp",
         "",
     ]
@@ -161,9 +190,12 @@ def main():
     small, mid, choice = sweep_threads(bcpp, inputs, torch, log)
     log.append("best threads per size: " + ", ".join(f"{n}: {t}" for n, t in choice.items()))
     div = sweep_spg(bcpp, inputs, torch, log)
-    log.append(f"chosen: small range {small}, mid range {mid}, sources-per-group divisor {div}")
+    os.environ["BCPP_TUNE_SPG_DIV"] = str(div)
+    dense = sweep_dense(bcpp, inputs, torch, log)
+    log.append(f"chosen: small range {small}, mid range {mid}, sources-per-group divisor {div}, "
+               f"dense shift {dense}")
     print(log[-1], flush=True)
-    write_header(args.out, small, mid, div, log)
+    write_header(args.out, small, mid, div, dense, log)
     print("wrote", args.out)
 
 

@@ -50,6 +50,7 @@ struct bc_batch {
     std::vector<int32_t> s_off;  // [ng+1] offset of each graph's targets in S_all
     std::vector<int32_t> S_all;  // targets, union ids, graph-major
     std::vector<int32_t> lab;    // P' labels of the union (targets singleton)
+    std::vector<int32_t> maxw;   // [ng] each graph's largest weight (1 for unit weights)
     int32_t nlab = 0;
     bc_graph* G = nullptr;       // the union graph
     std::unique_ptr<bcpp::PlainPlan> plan;  // plain Brandes, captured on first use
@@ -130,7 +131,7 @@ static int batch_plain(bc_batch* b, uint32_t flags, double* d_out) {
                 D.hi = hi;
                 D.arc_lo = G->h_row_ptr[lo];
                 D.arcs = G->h_row_ptr[hi] - G->h_row_ptr[lo];
-                D.ring_len = G->maxw + 1;
+                D.ring_len = b->maxw[gi] + 1;
                 D.flags = GF_BACKWARD | (G->unit ? GF_UNIT : 0u);
                 D.nsrc = std::min(per, ns - c);
                 for (int l = 0; l < LANES; ++l)
@@ -195,6 +196,7 @@ static int build_plain_plan(bc_batch* b) {
                 D.lo = lo;
                 D.hi = hi;
                 D.flags = GF_BACKWARD;
+                D.ring_len = b->maxw[gi] + 1;
                 D.nsrc = std::min(per, ns - c);
                 for (int l = 0; l < LANES; ++l) D.src[l] = l < D.nsrc ? b->S_all[b->s_off[gi] + c + l] : -1;
                 P->groups.push_back(D);
@@ -401,6 +403,7 @@ int bc_batch_create(int32_t ngraphs, const bc_csr* graphs, const int32_t* const*
         int32_t mw = 1;
         BC_TRY(validate_csr(&graphs[i], &mw));
         maxw = std::max(maxw, mw);
+        b->maxw.push_back(mw);
         ntot += graphs[i].n;
         atot += graphs[i].nnz;
         if (graphs[i].w) any_w = true; else all_w = false;

@@ -243,6 +243,7 @@ int plain_resident(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_d
         G.lo = 0;
         G.hi = n;
         G.flags = GF_BACKWARD;
+        G.ring_len = g->maxw + 1;
         const int32_t first = j * spg;
         G.nsrc = std::min(spg, nS - first);
         for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? S[first + b] : -1;

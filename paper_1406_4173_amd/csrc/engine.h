@@ -52,9 +52,10 @@ struct GroupDesc {
     uint32_t* nd = nullptr;     // [hi-lo] smallest pending distance over unsettled lanes
     uint64_t* done = nullptr;   // [hi-lo] lanes settled at the node
     // offers: ring[node][D mod ring_len] = lanes offered distance D by a settled
-    // neighbour (ring_len = longest arc + 1, so pending offers never share a slot)
+    // neighbour (ring_len = longest arc + 1, so pending offers never share a slot;
+    // 0 = not known: the engine refuses such a group, the resident kernel scans)
     uint64_t* ring = nullptr;
-    int32_t ring_len = 2;
+    int32_t ring_len = 0;
     double* cacc = nullptr;     // [hi-lo] this group's share of the scores
     uint64_t* tmask = nullptr;  // [arcs] per arc u->x: lanes in which u is a tight parent of x
     int32_t* hist = nullptr;    // settled nodes in step order (backward only)

@@ -90,6 +90,78 @@ __device__ __forceinline__ void for_selected(int32_t n, int32_t* __restrict__ wq
     if (cnt > 0) body(lane < cnt ? wq[lane] : 0, lane < cnt);
 }
 
+// Visit the nodes whose bits are set in row (W words of a bucket bitmap) and for which
+// keep(v) holds, clearing the row. Word i holds nodes 32i .. 32i+31; wave w takes the
+// words of the 64-node blocks b with b % NW == w, 32 blocks (64 words, one per lane) per
+// pass, and queues the kept nodes in increasing order. Those are the queues, and the
+// body calls, that for_selected builds from the same selection, so a step may use
+// either one without changing any result. A pass places its set bits in order with a
+// scan of the per-lane bit counts; output slot P then finds its word by a binary search
+// over the lanes and its bit by a search over the word's bit counts, so no lane loops
+// over the bits of a dense word while the others wait.
+template <int T, class Keep, class Body>
+__device__ __forceinline__ void for_bucket(uint32_t* __restrict__ row, int32_t W, int32_t* __restrict__ wq,
+                                           Keep&& keep, Body&& body) {
+    constexpr int NW = T / 64;
+    const int lane = threadIdx.x & 63;
+    const int32_t nblk = (W + 1) >> 1;
+    int cnt = 0;
+    for (int32_t b0 = threadIdx.x >> 6; b0 < nblk; b0 += NW * 32) {
+        const int32_t i = 2 * (b0 + NW * (lane >> 1)) + (lane & 1);
+        uint32_t bits = 0u;
+        if (i < W) {
+            bits = row[i];
+            if (bits) row[i] = 0u;
+        }
+        const unsigned long long any = __ballot(bits != 0u);
+        if (any == 0ull) continue;
+        const int pc = __popc(bits);
+        int incl = pc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        const int excl = incl - pc;
+        const int total = __shfl(incl, 63, 64);
+        for (int q = 0; q < total; q += 64) {
+            const int P = q + lane;
+            // the last lane whose first slot is at or before P holds slot P
+            int l = 0;
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1)
+                if (__shfl(excl, l + st, 64) <= P) l += st;
+            uint32_t w = (uint32_t)__shfl((int)bits, l, 64);
+            int r = P - __shfl(excl, l, 64), pos = 0;
+#pragma unroll
+            for (int h = 16; h > 0; h >>= 1) {
+                const int c = __popc(w & ((1u << h) - 1u));
+                if (r >= c) {
+                    r -= c;
+                    w >>= h;
+                    pos += h;
+                }
+            }
+            const int32_t v = (2 * (b0 + NW * (l >> 1)) + (l & 1)) * 32 + pos;
+            const bool hit = P < total && keep(v);
+            const unsigned long long m = __ballot(hit);
+            if (m == 0ull) continue;
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (hit) wq[cnt + rank] = v;
+            cnt += __popcll(m);
+            if (cnt >= 64) {
+                body(wq[lane], true);
+                const int rest = cnt - 64;
+                const int32_t t = lane < rest ? wq[64 + lane] : 0;
+                if (lane < rest) wq[lane] = t;
+                cnt = rest;
+            }
+        }
+    }
+    if (cnt > 0) body(lane < cnt ? wq[lane] : 0, lane < cnt);
+}
+
 // Arc expansion of a queue: lane i holds queued node q (valid) whose arcs are
 // [rp[lo+q], rp[lo+q+1]). Round r hands the queue's arcs r .. r+63, in node order, one
 // per lane, to f(owner, e, ok, incl, excl, r): owner = queue slot of the arc's node,
@@ -143,7 +215,9 @@ struct RGroup {
     int32_t ctx, lo, hi, nsrc;
     int32_t t_lo, tn;
     uint32_t flags;
-    int32_t pad;
+    int32_t lg;     // bucket bitmaps: log2 of the bucket count (>= longest arc + 1); -1 = scan
+    int32_t dense;  // a bucket step with more bits than this scans the range instead
+    int32_t pad_;
     int64_t src_off;
     double* cacc;
     double* cint;
@@ -213,7 +287,24 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     // d and sigma of every node written out per source lane
     const bool bwd = (R.flags & GF_BACKWARD) != 0;
     const bool restrict_ = (R.flags & GF_RESTRICT) != 0;
-    // this wave's record region (backward groups): nodes, then step numbers, then ends
+    // Bucket bitmaps (state in device memory and R.lg >= 0), in LDS: bucket d mod 2^lg
+    // holds one bit per node offered distance d (the pending distances D+1 .. D+longest
+    // arc never share a bucket), and a counter of bits set per bucket and per parity of
+    // d >> lg. A sparse step reads and clears its bucket instead of reading every node's
+    // distance from L2; the next step is the nearest distance whose counter is non-zero.
+    // Offers made during a step go to other buckets, and to the other counter copy of
+    // the bucket being retired, so no write races the retiring. (With the state in LDS a
+    // scan step costs a few LDS reads per thread, less than the bitmaps' atomics and the
+    // occupancy their LDS would take.)
+    const bool bucket = GLOBAL && R.lg >= 0;
+    const int lg = bucket ? R.lg : 0;
+    const uint32_t RM = bucket ? (1u << lg) - 1u : 0u;
+    const int32_t W = (n + 31) >> 5;
+    uint32_t* __restrict__ bm = reinterpret_cast<uint32_t*>(lds);  // [RM+1][W]
+    uint32_t* __restrict__ bc = bm + (size_t)(RM + 1) * W;         // [RM+1][2]
+    auto cidx = [&](uint32_t d) { return ((d & RM) << 1) | ((d >> lg) & 1u); };
+    // this wave's record region (backward groups): nodes, then step numbers, then ends;
+    // a wave queues only nodes of its own 64-node blocks (b % (T / 64) == wave)
     const int32_t wcap = 64 * ((n + T - 1) / T);
     int32_t* __restrict__ rnodes = bwd ? R.rlist + (int64_t)(tid >> 6) * 3 * wcap : nullptr;
     int32_t* __restrict__ rsegk = bwd ? rnodes + wcap : nullptr;
@@ -232,6 +323,11 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             sig[v] = (v == s) ? 1ull : 0ull;
         }
         if (tid == 0) fwd_next[0] = fwd_next[1] = fwd_next[2] = INF32;
+        if (bucket) {
+            const int32_t tot = (int32_t)(RM + 1) * W;
+            for (int32_t i = tid; i < tot; i += T) bm[i] = (i == (s >> 5)) ? (1u << (s & 31)) : 0u;
+            for (int32_t i = tid; i < 2 * (int32_t)(RM + 1); i += T) bc[i] = (i == 0) ? 1u : 0u;
+        }
         __syncthreads();
 
         // ------------------------------------------------------------ forward ----
@@ -242,18 +338,13 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         // 64 * ceil(n / T) nodes and as many entries.
         uint32_t D = 0;
         bool ovf = false;
+        // A bucket step can find only stale bits; it queues nothing and does not count
+        // as a step, so the record holds at most one step per distinct final distance.
         int32_t wcur = 0, wseg = 0, wstep0 = 0, nsteps = 0;
-        for (int k = 0;; ++k) {
+        for (int it = 0, k = 0;; ++it) {
             uint32_t mn = INF32;
             if (bwd && tid == 0) R.steps[k] = D;
-            for_selected<T, GLOBAL ? 8 : 4>(
-                n, wq,
-                [&](int32_t v) {
-                    const uint32_t dv = D_(v);
-                    if (dv == D) return true;
-                    if (dv > D && dv != INF32) mn = min(mn, dv);
-                    return false;
-                },
+            auto fbody =
                 [&](int32_t q, bool valid) {
                     if (prof && valid) bytes += 12ull;
                     if (bwd) {
@@ -291,11 +382,41 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         const uint32_t nv = D + L;
                         if (nv < D_(u)) {
                             const uint32_t old = atomicMin(&dist[u], nv);
-                            if (nv < old) mn = min(mn, nv);
+                            if (nv < old) {
+                                if (bucket) {
+                                    const uint32_t bit = 1u << (u & 31);
+                                    const uint32_t ow = atomicOr(&bm[(size_t)(nv & RM) * W + (u >> 5)], bit);
+                                    if (!(ow & bit)) atomicAdd(&bc[cidx(nv)], 1u);
+                                } else {
+                                    mn = min(mn, nv);
+                                }
+                            }
                         }
                     });
-                });
-            if (bwd && wcur != wstep0) {
+                };
+            if (bucket) {
+                // both visits queue the same nodes in the same order, so the choice (made
+                // on a count that stale bits inflate by a racy amount) changes no result
+                uint32_t* row = bm + (size_t)(D & RM) * W;
+                if (bc[cidx(D)] > (uint32_t)R.dense) {
+                    for_selected<T, GLOBAL ? 8 : 4>(n, wq, [&](int32_t v) { return D_(v) == D; }, fbody);
+                    for (int32_t i = tid; i < W; i += T) row[i] = 0u;
+                } else {
+                    for_bucket<T>(row, W, wq, [&](int32_t v) { return D_(v) == D; }, fbody);
+                }
+            } else {
+                for_selected<T, GLOBAL ? 8 : 4>(
+                    n, wq,
+                    [&](int32_t v) {
+                        const uint32_t dv = D_(v);
+                        if (dv == D) return true;
+                        if (dv > D && dv != INF32) mn = min(mn, dv);
+                        return false;
+                    },
+                    fbody);
+            }
+            const bool mine = bwd && wcur != wstep0;
+            if (mine) {
                 if (lane == 0) {
                     rsegk[wseg] = k;
                     rsege[wseg] = wcur;
@@ -303,12 +424,29 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                 ++wseg;
                 wstep0 = wcur;
             }
+            if (bucket) {
+                // fwd_next[it % 3] != INF32: some wave queued a node in this step
+                if (mine && lane == 0) fwd_next[it % 3] = 0u;
+                if (tid == 0) fwd_next[(it + 1) % 3] = INF32;
+                __syncthreads();
+                if (!bwd || fwd_next[it % 3] != INF32) nsteps = ++k;
+                if (tid == 0) bc[cidx(D)] = 0u;
+                uint32_t nx = INF32;
+                for (uint32_t j = 1; j <= RM; ++j)
+                    if (bc[cidx(D + j)]) {
+                        nx = D + j;
+                        break;
+                    }
+                if (nx == INF32) break;
+                D = nx;
+                continue;
+            }
+            nsteps = ++k;
             mn = wmin_u32(mn);
-            if (lane == 0 && mn != INF32) atomicMin(&fwd_next[k % 3], mn);
-            if (tid == 0) fwd_next[(k + 1) % 3] = INF32;
+            if (lane == 0 && mn != INF32) atomicMin(&fwd_next[it % 3], mn);
+            if (tid == 0) fwd_next[(it + 1) % 3] = INF32;
             __syncthreads();
-            const uint32_t nx = fwd_next[k % 3];
-            nsteps = k + 1;
+            const uint32_t nx = fwd_next[it % 3];
             if (nx == INF32) break;
             D = nx;
         }
@@ -438,6 +576,19 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
 
 size_t lds_bytes(int64_t range) { return (((size_t)range * 4 + 15) & ~(size_t)15) + (size_t)range * 8; }
 
+// Bucket bitmaps of a group: log2 of the bucket count for arcs up to ring_len - 1 long
+// (at most 64 buckets), or -1 when the longest arc is unknown or too long.
+int bucket_lg(int32_t ring_len) {
+    if (ring_len < 2 || ring_len > 64) return -1;
+    int lg = 0;
+    while ((1 << lg) < ring_len) ++lg;
+    return lg;
+}
+size_t bucket_bytes(int64_t range, int lg) {
+    const size_t R2 = (size_t)1 << lg;
+    return (R2 * (size_t)((range + 31) / 32) + 2 * R2) * 4;
+}
+
 struct ResidentLimits {
     bool init = false;
     size_t lds = 0;  // usable dynamic LDS per workgroup
@@ -458,7 +609,9 @@ int query_limits() {
     const size_t stat = 16 * WQ * 4 + 1024;
     size_t usable = (size_t)v > stat ? (size_t)v - stat : 0;
     if (usable > 65536) {
-        if (hipFuncSetAttribute((const void*)k_resident<1024, false>,
+        if (hipFuncSetAttribute((const void*)k_resident<1024, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_resident<1024, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
             hipFuncSetAttribute((const void*)k_resident<512, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
@@ -485,6 +638,7 @@ int64_t tune_value(const char* name, int64_t dflt) {
 struct SizeClasses {
     int64_t small = tune_value("BCPP_TUNE_SMALL", tuned_small_range);
     int64_t mid = tune_value("BCPP_TUNE_MID", tuned_mid_range);
+    int64_t dense_shift = tune_value("BCPP_TUNE_DENSE_SHIFT", tuned_dense_shift);
     int of(int64_t range) const { return range <= small ? 0 : range <= mid ? 1 : 2; }
 };
 
@@ -568,15 +722,21 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
     for (size_t i = 0; i < ng; ++i) {
         const GroupDesc& G = *groups[i];
         const int64_t range = (int64_t)G.hi - G.lo;
-        const size_t need = lds_bytes(range);
-        int c;
-        if (need > limits().lds) {
+        const size_t state = lds_bytes(range);
+        const int lg0 = bucket_lg(G.ring_len);
+        const size_t bb = lg0 >= 0 ? bucket_bytes(range, lg0) : 0;
+        int c, lg = -1;
+        size_t need;
+        if (state > limits().lds) {
             if (!G.gdist || !G.gsig) return fail(BC_E_INVAL, "resident: no state buffers for a large range");
             c = 3;
+            lg = (lg0 >= 0 && bb <= limits().lds) ? lg0 : -1;
+            need = lg >= 0 ? bb : 0;
         } else {
             c = sc.of(range);
-            L->lds[c] = std::max(L->lds[c], need);
+            need = state;
         }
+        L->lds[c] = std::max(L->lds[c], need);
         const auto key = std::make_pair((const void*)G.g.row_ptr, (const void*)G.trow);
         auto it = ctx_of.find(key);
         if (it == ctx_of.end()) {
@@ -584,6 +744,8 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
             ctx.push_back(RCtx{G.g, G.trow, G.tcol, G.tlen, G.tsig});
         }
         RGroup r{};
+        r.lg = lg;
+        r.dense = (int32_t)(range >> sc.dense_shift);
         r.ctx = it->second;
         r.lo = G.lo;
         r.hi = G.hi;
@@ -638,8 +800,8 @@ int resident_launch(hipStream_t s, const ResidentLaunch& L) {
         KTimer kt(BC_K_RESIDENT, s);
         const dim3 grid((unsigned)L.count[c]);
         if (c == 3)
-            hipLaunchKernelGGL((k_resident<1024, true>), grid, dim3(1024), 0, s, L.d_rg[c], L.d_ctx, L.d_src,
-                               L.d_err, prof);
+            hipLaunchKernelGGL((k_resident<1024, true>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
+                               L.d_src, L.d_err, prof);
         else if (c == 2)
             hipLaunchKernelGGL((k_resident<1024, false>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
                                L.d_src, L.d_err, prof);

@@ -795,6 +795,7 @@ std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk) {
         G.g.nflag = sk->d_nflag;
         G.lo = 0;
         G.hi = sk->n_sk;
+        G.ring_len = sk->max_len + 1;
         G.flags = GF_BACKWARD | (sk->n_int ? GF_CENT : 0u);
         G.trow = sk->d_trow;
         G.tcol = sk->d_tcol;

@@ -32,4 +32,5 @@ namespace bcpp {
 constexpr int64_t tuned_small_range = 4000;
 constexpr int64_t tuned_mid_range = 6500;
 constexpr int64_t tuned_spg_div = 256;
+constexpr int64_t tuned_dense_shift = 2;
 }  // namespace bcpp

@@ -170,3 +170,26 @@ def test_plain_dev_entry_point(bcpp):
     bcpp.brandes_plain_dev(G, S_dev, out)
     torch.cuda.synchronize()
     assert_scores(out.cpu().numpy(), oracle.bc(g, S))
+
+
+@pytest.mark.parametrize("wmax,intra", [(None, 0.9), (4, 0.99), (12, 0.95), (100, 0.95)],
+                         ids=["unit", "w4-chain", "w12", "w100-no-buckets"])
+def test_plain_bucket_and_scan_steps_agree(bcpp, monkeypatch, wmax, intra):
+    """A range too large for LDS keeps bucket bitmaps of the pending distances (arcs up
+    to 63 long): a step with few bits reads its bucket, a dense one scans the range.
+    Both queue the same nodes in the same order, so every threshold (0: always the
+    bucket, 63: always the scan) gives the same bits, and those match the oracle."""
+    rng = inputs.rng_for(inputs.SEED_BASE + 91, 0 if wmax is None else wmax)
+    g = inputs._community_graph(rng, 20000, 400, 8.0, intra, wmax, "bucket20k")
+    S = np.sort(rng.choice(g.n, 160, replace=False)).astype(np.int32)
+    G = bcpp.Graph(g)
+    got = {}
+    for shift in ("0", "63", None):
+        if shift is None:
+            monkeypatch.delenv("BCPP_TUNE_DENSE_SHIFT", raising=False)
+        else:
+            monkeypatch.setenv("BCPP_TUNE_DENSE_SHIFT", shift)
+        got[shift] = bcpp.brandes_plain(G, S)
+    assert np.array_equal(got["0"], got["63"])
+    assert np.array_equal(got["0"], got[None])
+    assert_scores(got[None], oracle.bc(g, S))

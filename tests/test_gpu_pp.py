@@ -194,3 +194,20 @@ def test_pp_pareto_100k(bcpp):
     want = oracle.bc(g, g.S)
     assert_scores(bcpp.brandes_pp(G, sk), want)
     assert_scores(bcpp.brandes_plain(G, g.S), want)
+
+
+def test_pp_bucket_and_scan_steps_agree(bcpp, monkeypatch):
+    """Brandes++ on a skeleton too large for LDS (bucket frontiers in Brandes_SK): the
+    dense-step threshold moves time only, never a bit of the result."""
+    rng = inputs.rng_for(inputs.SEED_BASE + 92)
+    g = inputs._community_graph(rng, 40000, 800, 8.0, 0.94, 4, "bucket40k")
+    g.S = np.sort(rng.choice(g.n, 120, replace=False)).astype(np.int32)
+    G = bcpp.Graph(g)
+    sk = bcpp.partition_sk(G, g.part, g.k, g.S)
+    assert sk.stats()["n_sk"] > 13000
+    got = {}
+    for shift in ("0", "63"):
+        monkeypatch.setenv("BCPP_TUNE_DENSE_SHIFT", shift)
+        got[shift] = bcpp.brandes_pp(G, sk)
+    assert np.array_equal(got["0"], got["63"])
+    assert_scores(got["0"], oracle.bc(g, g.S))
