@@ -3,22 +3,25 @@
 Usage (on a machine with the GPU): python -m paper_1406_4173_amd.autotune [--out PATH]
 then rebuild (python -m paper_1406_4173_amd.build_lib).
 
-Three choices are tuned, all fixed per build so that a graph gets the same launch
-shape alone, inside a batch or in the server (results then agree bit for bit):
+Four values are tuned, all fixed per build so that a graph gets the same launch shape
+alone, inside a batch or in the server (results then agree bit for bit):
 
-* threads per workgroup by node range: every graph of a sweep over community graphs
-  of 500 to 12,000 nodes (unit and integer weights) is timed with 256, 512 and 1024
-  threads per workgroup (through the BCPP_TUNE_SMALL / BCPP_TUNE_MID overrides); the
-  range thresholds are placed between the sizes where the best choice changes;
-* sources per group, ceil(|S| / div): div in {256, 512, 1024, 2048, 4096} timed on the
-  10,000-node stochastic block model (S = V) and the 256-graph batch, and the div with
-  the smallest sum of times relative to each workload's best is kept;
-* the dense-step threshold of bucket frontiers (a step with more than range >> shift
-  bucket bits scans the range): shifts 1 to 6, and 63 (scan nearly always), timed the
-  same way on three 10,000 to 100,000-node graphs and the batch's Brandes++ pass.
+* threads per workgroup by node range (256 up to tuned_small_range, 512 up to
+  tuned_mid_range, 1024 above) and sources per group, ceil(|S| / div). The two
+  interact: the divisor sets how many groups a launch has and so how many a compute
+  unit holds, which decides whether wide or narrow workgroups fill it. They are
+  therefore chosen together, from a grid of threshold pairs and divisors, each timed
+  on the workloads they serve: the 10,000-node stochastic block model and the
+  1,000-node planted partition (plain Brandes and Brandes++), and the 256-graph batch
+  (both passes). The grid point with the smallest sum of times relative to each
+  workload's best is kept;
+* the dense-step threshold of bucket frontiers (ranges whose state lives in device
+  memory; a step with more than range >> shift bucket bits scans the range): shifts 1
+  to 6, and 63 (scan nearly always), timed the same way on the two 100,000-node graphs.
 
-The timed call is plain target-set Brandes on the device (bc_brandes_plain_dev, or a
-batch run); the sweep uses the library only through its Python binding.
+Every timing is the best of a few runs of a call through the Python binding, with the
+choice under test set through the BCPP_TUNE_* overrides the library reads at each
+launch; batches are rebuilt per grid point, since a batch captures its plain pass once.
 """
 from __future__ import annotations
 
@@ -45,96 +48,59 @@ def _time(fn, sync, reps=3):
     return best
 
 
-def _force_threads(T):
-    """Environment overrides that put every LDS range into the class of T threads."""
-    if T == 256:
-        os.environ["BCPP_TUNE_SMALL"] = str(BIG)
-        os.environ["BCPP_TUNE_MID"] = str(BIG)
-    elif T == 512:
-        os.environ["BCPP_TUNE_SMALL"] = "1"
-        os.environ["BCPP_TUNE_MID"] = str(BIG)
-    else:
-        os.environ["BCPP_TUNE_SMALL"] = "1"
-        os.environ["BCPP_TUNE_MID"] = "1"
-
-
 def _clear():
     for k in ("BCPP_TUNE_SMALL", "BCPP_TUNE_MID", "BCPP_TUNE_SPG_DIV", "BCPP_TUNE_DENSE_SHIFT"):
         os.environ.pop(k, None)
 
 
-def sweep_threads(bcpp, inputs, torch, log):
-    sizes = [500, 1500, 3000, 5000, 8000, 12000]
-    best = {}
-    for n in sizes:
-        for wmax in (None, 10):
-            rng = inputs.rng_for(inputs.SEED_BASE + 77, n, 0 if wmax is None else 1)
-            g = inputs._community_graph(rng, n, max(4, n // 250), 10.0, 0.9, wmax, f"tune{n}")
-            G = bcpp.Graph(g)
-            ns = min(n, 1024)
-            S = torch.tensor(np.sort(rng.choice(n, ns, replace=False)).astype(np.int32), device="cuda")
-            out = torch.empty(n, dtype=torch.float64, device="cuda")
-            row = {}
-            for T in (256, 512, 1024):
-                _force_threads(T)
-                row[T] = _time(lambda: bcpp.brandes_plain_dev(G, S, out), torch.cuda.synchronize)
-            _clear()
-            key = (n, "unit" if wmax is None else f"1..{wmax}")
-            best[key] = row
-            log.append(f"n={n:6d} w={key[1]:5s} " + "  ".join(f"T={T}: {row[T]*1e3:8.3f} ms" for T in row))
-            print(log[-1], flush=True)
-    # per size: the thread count with the smallest summed time over the weight kinds
-    choice = {}
-    for n in sizes:
-        tot = {T: sum(best[k][T] for k in best if k[0] == n) for T in (256, 512, 1024)}
-        choice[n] = min(tot, key=tot.get)
-    # thresholds: the largest size still won by 256 (then 512), placed half way to
-    # the next size; a class never won gets an empty range
-    small = 0
-    mid = 0
-    for i, n in enumerate(sizes):
-        nxt = sizes[i + 1] if i + 1 < len(sizes) else n * 2
-        if choice[n] == 256:
-            small = (n + nxt) // 2
-        if choice[n] in (256, 512):
-            mid = (n + nxt) // 2
-    mid = max(mid, small)
-    return small, mid, choice
+SHAPE_PAIRS = [(BIG, BIG), (6500, BIG), (4000, 6500), (2500, 6500), (2500, 2500), (1000, 4000),
+               (0, 6500), (0, 2500), (0, 0)]
+SHAPE_DIVS = (256, 1024, 4096)
 
 
-def sweep_spg(bcpp, inputs, torch, log):
-    g = inputs.sbm_10k()
-    G = bcpp.Graph(g)
-    S = torch.tensor(g.S, dtype=torch.int32, device="cuda")
-    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+def sweep_shapes(bcpp, inputs, torch, log):
+    singles = []
+    for name in ("sbm_10k", "planted_1k"):
+        g = getattr(inputs, name)()
+        G = bcpp.Graph(g)
+        S = torch.tensor(g.S, dtype=torch.int32, device="cuda")
+        out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        singles.append((name + " plain", lambda G=G, S=S, out=out: bcpp.brandes_plain_dev(G, S, out)))
+        singles.append((name + " pp", lambda G=G, g=g: bcpp.brandes_pp(G, bcpp.partition_sk(G, g.part, g.k, g.S))))
     gs = inputs.batch_256()
-    B = bcpp.Batch(gs)
+    names = [n for n, _ in singles] + ["batch_256 plain", "batch_256 pp"]
     rows = {}
-    for div in (256, 512, 1024, 2048, 4096):
-        os.environ["BCPP_TUNE_SPG_DIV"] = str(div)
-        a = _time(lambda: bcpp.brandes_plain_dev(G, S, out), torch.cuda.synchronize)
-        b = _time(lambda: B.run(pp=False), torch.cuda.synchronize, reps=2)
-        rows[div] = (a, b)
-        log.append(f"div={div:5d} sbm_10k plain {a*1e3:8.3f} ms  batch_256 plain {b*1e3:8.3f} ms")
-        print(log[-1], flush=True)
+    for small, mid in SHAPE_PAIRS:
+        for div in SHAPE_DIVS:
+            os.environ["BCPP_TUNE_SMALL"] = str(small)
+            os.environ["BCPP_TUNE_MID"] = str(mid)
+            os.environ["BCPP_TUNE_SPG_DIV"] = str(div)
+            t = [_time(f, torch.cuda.synchronize, reps=2) for _, f in singles]
+            B = bcpp.Batch(gs)
+            t.append(_time(lambda: B.run(pp=False), torch.cuda.synchronize, reps=2))
+            t.append(_time(lambda: B.run(pp=True), torch.cuda.synchronize, reps=2))
+            del B
+            rows[(small, mid, div)] = t
+            show = lambda v: "all" if v >= BIG else str(v)
+            log.append(f"256 to {show(small):>4s} 512 to {show(mid):>4s} div {div:4d}: " + "  ".join(
+                f"{nm} {x*1e3:7.2f}" for nm, x in zip(names, t)))
+            print(log[-1], flush=True)
     _clear()
-    ba = min(r[0] for r in rows.values())
-    bb = min(r[1] for r in rows.values())
-    return min(rows, key=lambda d: rows[d][0] / ba + rows[d][1] / bb)
+    best = [min(r[i] for r in rows.values()) for i in range(len(names))]
+    return min(rows, key=lambda k: sum(x / b for x, b in zip(rows[k], best)))
 
 
 def sweep_dense(bcpp, inputs, torch, log):
     """Bucket steps with more than range >> shift bits scan the range instead; the
     shift only moves time (both visits queue the same nodes in the same order)."""
     work = []
-    for name in ("sbm_10k", "smallcut_100k", "pareto_100k"):
+    for name in ("smallcut_100k", "pareto_100k"):
         g = getattr(inputs, name)()
         G = bcpp.Graph(g)
         S = torch.tensor(g.S, dtype=torch.int32, device="cuda")
         out = torch.empty(g.n, dtype=torch.float64, device="cuda")
         work.append((name + " plain", lambda G=G, S=S, out=out: bcpp.brandes_plain_dev(G, S, out)))
-    gs = inputs.batch_256()
-    work.append(("batch_256 pp", lambda: bcpp.Batch(gs).run(pp=True)))
+        work.append((name + " pp", lambda G=G, g=g: bcpp.brandes_pp(G, bcpp.partition_sk(G, g.part, g.k, g.S))))
     rows = {}
     for shift in (1, 2, 3, 4, 6, 63):
         os.environ["BCPP_TUNE_DENSE_SHIFT"] = str(shift)
@@ -157,7 +123,7 @@ def write_header(path, small, mid, div, dense, log):
         "// ceil(|S| / tuned_spg_div) sources (1..64). A bucket step of a range of n nodes",
         "// with more than n >> tuned_dense_shift bits scans the range instead.",
         "//",
-        "// Timings of the sweep (best of 3, plain target-set Brandes on the device):",
+        "// Timings of the sweep (ms, best of 2 after a warm-up run):",
     ]
     lines += [f"//   {ln}" for ln in log]
     lines += [
@@ -187,9 +153,9 @@ def main():
     bcpp.lib()
     _clear()
     log = []
-    small, mid, choice = sweep_threads(bcpp, inputs, torch, log)
-    log.append("best threads per size: " + ", ".join(f"{n}: {t}" for n, t in choice.items()))
-    div = sweep_spg(bcpp, inputs, torch, log)
+    small, mid, div = sweep_shapes(bcpp, inputs, torch, log)
+    os.environ["BCPP_TUNE_SMALL"] = str(small)
+    os.environ["BCPP_TUNE_MID"] = str(mid)
     os.environ["BCPP_TUNE_SPG_DIV"] = str(div)
     dense = sweep_dense(bcpp, inputs, torch, log)
     log.append(f"chosen: small range {small}, mid range {mid}, sources-per-group divisor {div}, "
