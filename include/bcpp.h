@@ -165,7 +165,12 @@ int bc_brandes_pp_dev(const bc_graph* g, const bc_skeleton* sk, uint32_t flags,
 
 /* Many independent graphs in one device run: each graph g_i with its own partition
  * and targets. All graphs' groups of sources (and, for Brandes++, all parts) run in
- * the same launches; plain Brandes over the batch replays one captured HIP graph. */
+ * the same launches. Both passes replay one captured HIP graph each, built on the
+ * pass's first run (for Brandes++ the whole pipeline: Build_SK phases 1 and 2,
+ * Dijkstra_SK, the skeleton assembly, Brandes_SK + Centrality and the reduction, all
+ * recomputed by every replay); BC_NO_GRAPH, BC_ENGINE_ONLY, or a group too large for
+ * the resident kernel, runs the pass eagerly instead. Results are bitwise the same
+ * either way. */
 int bc_batch_create(int32_t ngraphs, const bc_csr* graphs, const int32_t* const* parts,
                     const int32_t* ks, const int32_t* const* S, const int32_t* nS,
                     void* hip_stream, bc_batch** out);

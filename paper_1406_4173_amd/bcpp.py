@@ -289,7 +289,7 @@ class Batch:
         self.h = h
 
     def run(self, pp: bool = True, engine_only: bool = False, graph: bool = True):
-        """graph=False runs plain Brandes eagerly instead of replaying the captured graph."""
+        """graph=False runs the pass eagerly instead of replaying its captured graph."""
         outs = [np.empty(n, np.float64) for n in self.ns]
         ptrs = (ctypes.c_void_p * len(outs))(*[o.ctypes.data for o in outs])
         fl = ((BC_BATCH_PP if pp else BC_BATCH_PLAIN) | (BC_ENGINE_ONLY if engine_only else 0) |

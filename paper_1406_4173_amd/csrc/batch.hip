@@ -6,13 +6,15 @@
 // label range), so the union's skeleton is the disjoint union of the graphs'
 // skeletons and each graph's skeleton nodes and table rows are contiguous id ranges;
 // Dijkstra_SK then covers every part of every graph, and Brandes_SK + Centrality every
-// graph's groups, each in a single engine run. Scores of a disjoint union restricted
-// to one graph are that graph's own scores (no shortest path joins two graphs).
+// graph's groups, each in a single run of launches. Scores of a disjoint union
+// restricted to one graph are that graph's own scores (no shortest path joins two
+// graphs). Each pass is captured as a HIP graph on its first run and replayed after.
 #include <algorithm>
 #include <memory>
 
 #include "engine.h"
 #include "graph.h"
+#include "skbuild.h"
 
 namespace bcpp {
 // A batch's plain Brandes as a captured HIP graph. The batch never changes, so its
@@ -42,6 +44,45 @@ struct PlainPlan {
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
+// Brandes++ over the batch as one captured HIP graph. The first run builds the skeleton
+// of the union graph on the device in arenas the plan owns (the graph's own arenas are
+// swapped out meanwhile), keeps the build and every launch record, and captures the
+// device work of a whole run: phase 1 and 2 of Build_SK, the Dijkstra_SK launch, the
+// clique and table counts, the skeleton fill, the Brandes_SK + Centrality launch, the
+// reduction and the copies out. A replay recomputes all of it; only host bookkeeping
+// (sizes, offsets, group lists and launch records, fixed by the batch's graphs,
+// partitions and targets) is taken from the first run. Needs every group on the
+// resident kernel; otherwise the batch runs eagerly.
+struct PpPlan {
+    Arena pre, work, run;
+    std::unique_ptr<bc_skeleton> sk;
+    PartitionKeep part;
+    ResidentLaunch L;
+    ReducePtrs R;
+    uint32_t* d_err = nullptr;
+    double* d_out = nullptr;
+    hipStream_t stream = nullptr;
+    double* h_out = nullptr;    // pinned
+    uint32_t* h_err = nullptr;  // pinned
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    PpPlan() = default;
+    PpPlan(const PpPlan&) = delete;
+    PpPlan& operator=(const PpPlan&) = delete;
+    ~PpPlan() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (h_out) (void)hipHostFree(h_out);
+        if (h_err) (void)hipHostFree(h_err);
+        sk.reset();
+        run.release();
+        work.release();
+        pre.release();
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
 }  // namespace bcpp
 
 struct bc_batch {
@@ -54,8 +95,11 @@ struct bc_batch {
     int32_t nlab = 0;
     bc_graph* G = nullptr;       // the union graph
     std::unique_ptr<bcpp::PlainPlan> plan;  // plain Brandes, captured on first use
+    std::unique_ptr<bcpp::PpPlan> pp_plan;  // Brandes++, captured on first use
+    bool pp_eager = false;                  // Brandes++ cannot be captured (runs eagerly)
     ~bc_batch() {
         plan.reset();
+        pp_plan.reset();
         delete G;
     }
 };
@@ -279,26 +323,28 @@ static int batch_plain_graph(bc_batch* b, double scale, double* const* bc_out) {
     return BC_OK;
 }
 
-static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
-    bc_graph* G = b->G;
-    hipStream_t s = G->stream;
-    const int32_t n = G->n;
-    PhaseTrace tr("batch Brandes++");
-    bc_skeleton* skp = nullptr;
-    BC_TRY(partition_impl(G, b->lab.data(), b->nlab, b->S_all.data(), (int32_t)b->S_all.size(), &skp,
-                          true));
-    tr.mark("partition");
-    std::unique_ptr<bc_skeleton> sk(skp);
-    const auto& oi = sk->h_out_idx;
-    const auto& ow = sk->h_out_which;
+// Brandes_SK + Centrality groups of every graph of the batch over the union skeleton,
+// and the reduction maps (node -> its graph's groups, its row in them).
+struct PpGroups {
     std::vector<GroupDesc> groups;
     std::vector<uint8_t> resident;
-    groups.reserve(b->S_all.size() + (size_t)b->ng);
-    resident.reserve(b->S_all.size() + (size_t)b->ng);
-    std::vector<int32_t> g0(n, 0), g1(n, 0), idx(n, -1);
-    std::vector<uint8_t> which(n, 0);
+    std::vector<int32_t> g0, g1, idx;
+    std::vector<uint8_t> which;
     int64_t steps = 1;
-    const bool allow_res = !(flags & BC_ENGINE_ONLY);
+};
+
+static void pp_groups(const bc_batch* b, const bc_skeleton* sk, bool allow_res, PpGroups* out) {
+    const bc_graph* G = b->G;
+    const int32_t n = G->n;
+    const auto& oi = sk->h_out_idx;
+    const auto& ow = sk->h_out_which;
+    PpGroups& Q = *out;
+    Q.groups.reserve(b->S_all.size() + (size_t)b->ng);
+    Q.resident.reserve(b->S_all.size() + (size_t)b->ng);
+    Q.g0.assign(n, 0);
+    Q.g1.assign(n, 0);
+    Q.idx.assign(n, -1);
+    Q.which.assign(n, 0);
     for (int32_t gi = 0; gi < b->ng; ++gi) {
         const int32_t lo = b->n_off[gi], hi = b->n_off[gi + 1];
         int32_t sk_lo = INT32_MAX, sk_hi = -1, t_lo = INT32_MAX, t_hi = -1;
@@ -317,19 +363,19 @@ static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
             const int32_t v = b->S_all[j];
             if (oi[v] >= 0 && ow[v] == 0) src.push_back(oi[v]);
         }
-        const int32_t first_group = (int32_t)groups.size();
+        const int32_t first_group = (int32_t)Q.groups.size();
         if (src.size() >= 2 && sk_hi > sk_lo) {
             const int32_t N = sk_hi - sk_lo;
             const int32_t tn = t_hi > t_lo ? t_hi - t_lo : 0;
             const bool res = allow_res && resident_takes(N);
             const size_t per = res ? (size_t)resident_sources_per_group((int64_t)src.size()) : LANES;
-            if (!res) steps = std::max(steps, max_steps_bound(N, LANES, (int64_t)(hi - lo) * G->maxw));
+            if (!res) Q.steps = std::max(Q.steps, max_steps_bound(N, LANES, (int64_t)(hi - lo) * G->maxw));
             for (size_t c = 0; c < src.size(); c += per) {
                 GroupDesc D;
                 D.g.row_ptr = sk->d_row_ptr;
                 D.g.col = sk->d_col;
                 D.g.len = sk->d_len;
-                D.g.mult = sk_mult(sk.get());
+                D.g.mult = sk_mult(sk);
                 D.g.nflag = sk->d_nflag;
                 D.g.twin = sk->d_twin;
                 D.lo = sk_lo;
@@ -346,37 +392,174 @@ static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
                 D.tn = tn;
                 D.nsrc = (int32_t)std::min<size_t>(per, src.size() - c);
                 for (int l = 0; l < LANES; ++l) D.src[l] = l < D.nsrc ? src[c + l] : -1;
-                groups.push_back(D);
-                resident.push_back(res ? 1 : 0);
+                Q.groups.push_back(D);
+                Q.resident.push_back(res ? 1 : 0);
             }
         }
         for (int32_t v = lo; v < hi; ++v) {
-            g0[v] = first_group;
-            g1[v] = (int32_t)groups.size();
-            if (oi[v] >= 0 && g1[v] > g0[v]) {
-                idx[v] = ow[v] == 0 ? oi[v] - sk_lo : oi[v] - t_lo;
-                which[v] = ow[v];
+            Q.g0[v] = first_group;
+            Q.g1[v] = (int32_t)Q.groups.size();
+            if (oi[v] >= 0 && Q.g1[v] > Q.g0[v]) {
+                Q.idx[v] = ow[v] == 0 ? oi[v] - sk_lo : oi[v] - t_lo;
+                Q.which[v] = ow[v];
             }
         }
     }
+}
+
+static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
+    bc_graph* G = b->G;
+    hipStream_t s = G->stream;
+    const int32_t n = G->n;
+    PhaseTrace tr("batch Brandes++");
+    bc_skeleton* skp = nullptr;
+    BC_TRY(partition_impl(G, b->lab.data(), b->nlab, b->S_all.data(), (int32_t)b->S_all.size(), &skp,
+                          true));
+    tr.mark("partition");
+    std::unique_ptr<bc_skeleton> sk(skp);
+    PpGroups Q;
+    pp_groups(b, sk.get(), !(flags & BC_ENGINE_ONLY), &Q);
     Arena& W = G->work;
-    const size_t need = mixed_bytes(groups, resident, steps) + (size_t)n * 13 +
-                        (size_t)groups.size() * 16 + (1 << 20);
+    const size_t need = mixed_bytes(Q.groups, Q.resident, Q.steps) + (size_t)n * 13 +
+                        (size_t)Q.groups.size() * 16 + (1 << 20);
     BC_TRY(W.reserve(need));
     int32_t* d_g0 = W.take<int32_t>(n);
     int32_t* d_g1 = W.take<int32_t>(n);
     int32_t* d_idx = W.take<int32_t>(n);
     uint8_t* d_which = W.take<uint8_t>(n);
     if (!d_g0 || !d_g1 || !d_idx || !d_which) return fail(BC_E_NOMEM, "batch: workspace too small");
-    BC_HIP(hipMemcpyAsync(d_g0, g0.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
-    BC_HIP(hipMemcpyAsync(d_g1, g1.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
-    BC_HIP(hipMemcpyAsync(d_idx, idx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
-    BC_HIP(hipMemcpyAsync(d_which, which.data(), n, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(d_g0, Q.g0.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(d_g1, Q.g1.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(d_idx, Q.idx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    BC_HIP(hipMemcpyAsync(d_which, Q.which.data(), n, hipMemcpyHostToDevice, s));
     tr.mark("groups");
-    BC_TRY(run_mixed(W, s, groups, resident, steps));
+    BC_TRY(run_mixed(W, s, Q.groups, Q.resident, Q.steps));
     tr.mark("Brandes_SK");
-    BC_TRY(reduce_scores(s, W, groups, n, d_g0, d_g1, d_idx, d_which, 0.5, d_out, false));
+    BC_TRY(reduce_scores(s, W, Q.groups, n, d_g0, d_g1, d_idx, d_which, 0.5, d_out, false));
     tr.mark("reduce");
+    return BC_OK;
+}
+
+__global__ void k_or_words(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, uint32_t* __restrict__ out) {
+    if (threadIdx.x == 0) out[0] = a[0] | b[0];
+}
+
+// Builds b->pp_plan, or leaves it empty (and returns BC_OK) when some group would not
+// run on the resident kernel.
+static int build_pp_plan(bc_batch* b) {
+    bc_graph* G = b->G;
+    hipStream_t s0 = G->stream;
+    const int32_t n = G->n;
+    auto P = std::make_unique<PpPlan>();
+    std::swap(G->pre, P->pre);
+    std::swap(G->work, P->work);
+    bc_skeleton* skp = nullptr;
+    const int rc0 = partition_impl(G, b->lab.data(), b->nlab, b->S_all.data(), (int32_t)b->S_all.size(), &skp,
+                                   true, &P->part);
+    std::swap(G->pre, P->pre);
+    std::swap(G->work, P->work);
+    P->sk.reset(skp);
+    BC_TRY(rc0);
+    if (!P->part.resident && !P->part.b.groups.empty()) return BC_OK;
+    PpGroups Q;
+    pp_groups(b, P->sk.get(), true, &Q);
+    for (uint8_t r : Q.resident)
+        if (!r) return BC_OK;
+    size_t need = resident_launch_bytes(Q.groups.size()) + 2 * (Q.groups.size() * 8 + 256) + (size_t)n * 21 +
+                  (1 << 20);
+    for (const GroupDesc& D : Q.groups) need += resident_group_bytes(D);
+    BC_TRY(P->run.reserve(need));
+    int32_t* d_g0 = P->run.take<int32_t>(std::max(n, 1));
+    int32_t* d_g1 = P->run.take<int32_t>(std::max(n, 1));
+    int32_t* d_idx = P->run.take<int32_t>(std::max(n, 1));
+    uint8_t* d_which = P->run.take<uint8_t>(std::max(n, 1));
+    P->d_out = P->run.take<double>(std::max(n, 1));
+    P->d_err = P->run.take<uint32_t>(1);
+    if (!d_g0 || !d_g1 || !d_idx || !d_which || !P->d_out || !P->d_err)
+        return fail(BC_E_NOMEM, "batch: workspace too small");
+    BC_HIP(hipMemcpyAsync(d_g0, Q.g0.data(), (size_t)n * 4, hipMemcpyHostToDevice, s0));
+    BC_HIP(hipMemcpyAsync(d_g1, Q.g1.data(), (size_t)n * 4, hipMemcpyHostToDevice, s0));
+    BC_HIP(hipMemcpyAsync(d_idx, Q.idx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s0));
+    BC_HIP(hipMemcpyAsync(d_which, Q.which.data(), n, hipMemcpyHostToDevice, s0));
+    for (GroupDesc& D : Q.groups)
+        if (!resident_alloc(P->run, D)) return fail(BC_E_NOMEM, "batch: workspace too small");
+    BC_TRY(resident_upload(s0, P->run, Q.groups, &P->L));
+    BC_TRY(reduce_upload(s0, P->run, Q.groups, &P->R));
+    BC_HIP(hipHostMalloc((void**)&P->h_out, (size_t)std::max(n, 1) * 8));
+    BC_HIP(hipHostMalloc((void**)&P->h_err, sizeof(uint32_t)));
+    BC_HIP(hipStreamSynchronize(s0));
+    BC_HIP(hipStreamCreate(&P->stream));
+    hipStream_t s = P->stream;
+    const SkBuild& B = P->part.b;
+    const bool prof_on = profiler().on;
+    profiler().on = false;
+    BC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, s, P->d_err);
+    int rc = B.issue_phase1(s);
+    if (rc == BC_OK) rc = B.issue_phase2(s);
+    if (rc == BC_OK && P->part.resident) {
+        hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, s, P->part.L.d_err);
+        rc = resident_launch(s, P->part.L);
+    }
+    if (rc == BC_OK) rc = B.issue_count(s);
+    if (rc == BC_OK) rc = B.issue_fill(s, P->sk.get());
+    if (rc == BC_OK && !Q.groups.empty()) {
+        hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, s, P->L.d_err);
+        rc = resident_launch(s, P->L);
+    }
+    if (rc == BC_OK) rc = reduce_launch(s, P->R, n, d_g0, d_g1, d_idx, d_which, 0.5, P->d_out, false);
+    if (rc == BC_OK) {
+        // the error words of the two launches (a missing launch reads the cleared word)
+        uint32_t* e1 = P->part.resident ? P->part.L.d_err : P->d_err;
+        uint32_t* e2 = Q.groups.empty() ? P->d_err : P->L.d_err;
+        hipLaunchKernelGGL(k_or_words, dim3(1), dim3(64), 0, s, e1, e2, P->d_err);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(P->h_out, P->d_out, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(P->h_err, P->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+            rc = fail(BC_E_DEVICE, "batch: capture of the copies failed");
+    }
+    const hipError_t ec = hipStreamEndCapture(s, &P->graph);
+    profiler().on = prof_on;
+    BC_TRY(rc);
+    if (ec != hipSuccess) return fail(BC_E_DEVICE, std::string("batch: capture failed: ") + hipGetErrorString(ec));
+    // a memset node would be replayed wrongly on this platform: the build clears with
+    // fill kernels, and a library that recorded one makes the plan unusable
+    size_t nn = 0;
+    BC_HIP(hipGraphGetNodes(P->graph, nullptr, &nn));
+    std::vector<hipGraphNode_t> nodes(nn);
+    BC_HIP(hipGraphGetNodes(P->graph, nodes.data(), &nn));
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType t;
+        BC_HIP(hipGraphNodeGetType(nd, &t));
+        if (t == hipGraphNodeTypeMemset) return fail(BC_E_DEVICE, "batch: captured Brandes++ holds a memset");
+    }
+    BC_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+    b->pp_plan = std::move(P);
+    return BC_OK;
+}
+
+// Brandes++ over the batch by replaying its captured graph (built on first use).
+// Returns BC_E_NOTFOUND when the batch cannot be captured (the caller runs it eagerly).
+static int batch_pp_graph(bc_batch* b, double scale, double* const* bc_out) {
+    if (!b->pp_plan) {
+        if (b->pp_eager) return BC_E_NOTFOUND;
+        BC_TRY(build_pp_plan(b));
+        if (!b->pp_plan) {
+            b->pp_eager = true;
+            return BC_E_NOTFOUND;
+        }
+    }
+    PpPlan& P = *b->pp_plan;
+    PhaseTrace tr("batch Brandes++ (graph)");
+    BC_HIP(hipGraphLaunch(P.exec, P.stream));
+    BC_HIP(hipStreamSynchronize(P.stream));
+    tr.mark("replay");
+    if (*P.h_err & ERR_OVERFLOW) return fail(BC_E_OVERFLOW, "a shortest-path count reached 2^64");
+    for (int32_t i = 0; i < b->ng; ++i) {
+        if (!bc_out[i]) continue;
+        for (int32_t v = b->n_off[i]; v < b->n_off[i + 1]; ++v)
+            bc_out[i][v - b->n_off[i]] = P.h_out[v] * scale;
+    }
     return BC_OK;
 }
 
@@ -459,6 +642,10 @@ int bc_batch_run(bc_batch* b, uint32_t flags, double* const* bc_out) {
         bool res = true;
         for (int32_t i = 0; i < b->ng; ++i) res = res && resident_takes(b->n_off[i + 1] - b->n_off[i]);
         if (res) return batch_plain_graph(b, (flags & BC_ORDERED) ? 2.0 : 1.0, bc_out);
+    }
+    if ((flags & BC_BATCH_PP) && !(flags & (BC_ENGINE_ONLY | BC_NO_GRAPH))) {
+        const int rc = batch_pp_graph(b, (flags & BC_ORDERED) ? 2.0 : 1.0, bc_out);
+        if (rc != BC_E_NOTFOUND) return rc;
     }
     BC_TRY(G->out.reserve((size_t)n * 8 + 256));
     double* d_out = G->out.take<double>(n);

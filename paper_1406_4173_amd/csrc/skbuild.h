@@ -11,6 +11,13 @@
 //            fill), blocked flags, interior rows, output maps, group states. After it
 //            nothing refers to the scratch arena, so the next prepare may reuse it.
 //   assemble after the Dijkstra_SK groups: skeleton rows, clique arcs, tables.
+//
+// The device work of each stage is also available on its own (issue_*): the same
+// kernels and copies on the same buffers, with no host synchronisation. Given the same
+// graph, partition and targets, the host values that the stages read back are the same
+// every time, so a caller that keeps the SkBuild, its arenas and the skeleton can
+// enqueue (or capture into a HIP graph) the whole build again without the host. Every
+// buffer that a kernel accumulates into is cleared by a fill kernel inside the stage.
 #pragma once
 
 #include <functional>
@@ -33,6 +40,8 @@ struct SkBuild {
     const bc_graph* g = nullptr;
     int32_t n = 0, nS = 0;
     int64_t nlab = 0;
+    int32_t k_in = 0;    // k of the given partition
+    bool given = false;  // targets already carry singleton labels
     bool weighted = false;
     std::vector<int32_t> S;  // targets (original ids)
     // per part of P' (host copies of phase 1, and their prefix sums)
@@ -45,13 +54,26 @@ struct SkBuild {
     std::vector<GroupDesc> groups;  // Dijkstra_SK groups
     std::vector<DskInfo> info;
     int64_t largest = 0, kprime = 0, clique_pairs = 0, table_pairs = 0;
-    size_t cub_bytes = 0;  // scratch of the device sort and scans
+    size_t cub_bytes = 0;  // scratch of the device scans
+    int32_t ntiles = 1;    // tiles of the renumbering sort
     // phase 1 (graph scratch arena)
+    int32_t* p_part = nullptr;
     int32_t* p_lab = nullptr;
     uint8_t* p_ist = nullptr;
     uint8_t* p_fr = nullptr;
     int32_t* p_S = nullptr;
+    int32_t* p_psize = nullptr;
+    int32_t* p_pnf = nullptr;
+    unsigned long long* p_parc = nullptr;
+    unsigned long long* p_cross = nullptr;
     // phase 2 (caller's arena)
+    uint32_t *d_keys = nullptr, *d_keys2 = nullptr;  // renumbering sort
+    int32_t* d_vals = nullptr;
+    int32_t *d_hist = nullptr, *d_hoff = nullptr;
+    int64_t *d_icnt = nullptr, *d_rcnt = nullptr;    // row counts before the scans
+    int64_t *d_poff = nullptr, *d_fbase = nullptr;   // per part (copies of the host values)
+    int32_t *d_ppnf = nullptr, *d_pg0 = nullptr, *d_png = nullptr, *d_ibase = nullptr;
+    void* d_cub = nullptr;
     int32_t* d_old = nullptr;  // renumbered position -> original node
     int32_t* d_nid = nullptr;  // original node -> renumbered position
     int64_t* d_irp = nullptr;  // intra-part CSR, renumbered
@@ -83,6 +105,21 @@ struct SkBuild {
     // get_store(bytes, arena) must hand back an arena with at least `bytes` free.
     int assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
                  const std::function<int(size_t, Arena*&)>& get_store);
+
+    // Device work only, on stream s: phase 1; phase 2 (sort, CSR, rows, maps); the
+    // clique and table counts; the skeleton fill into sk's arrays.
+    int issue_phase1(hipStream_t s) const;
+    int issue_phase2(hipStream_t s) const;
+    int issue_count(hipStream_t s) const;
+    int issue_fill(hipStream_t s, const bc_skeleton* sk) const;
+};
+
+// What partition_impl leaves behind for a caller that replays the build: the build
+// itself and, when the Dijkstra_SK groups ran on the resident kernel, their launch.
+struct PartitionKeep {
+    SkBuild b;
+    bool resident = false;
+    ResidentLaunch L;
 };
 
 // Brandes_SK groups (with the fused Centrality pass) over a skeleton, sources

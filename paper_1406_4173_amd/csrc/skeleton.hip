@@ -190,13 +190,88 @@ __global__ void k_p1_frontier(int32_t n, const int64_t* __restrict__ rp, const i
 }
 
 // Phase 2: renumbering key (part, then frontier before interior; ties keep node order
-// in the stable sort) and the inverse map.
+// in the stable sort) and the inverse map. Labels are below 2^31, so keys fit 32 bits.
 __global__ void k_p2_keys(int32_t n, const int32_t* __restrict__ lab, const uint8_t* __restrict__ fr,
-                          unsigned long long* __restrict__ key, int32_t* __restrict__ val) {
+                          uint32_t* __restrict__ key, int32_t* __restrict__ val) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    key[v] = (unsigned long long)lab[v] * 2ull + (fr[v] ? 0ull : 1ull);
+    key[v] = (uint32_t)lab[v] * 2u + (fr[v] ? 0u : 1u);
     val[v] = (int32_t)v;
+}
+
+// Stable LSD radix sort of (key, value) pairs, 8 key bits per pass, in tiles of
+// RS_TILE consecutive items (one workgroup of 256 threads, RS_TILE / 256 rounds of 256
+// consecutive items). k_rs_hist counts each tile's digits into hist[digit * ntiles +
+// tile]; an exclusive scan of hist gives every (digit, tile) its first output slot;
+// k_rs_scatter then places the tile's items in order. Within a round, lanes of one
+// wave with equal digits are found with one ballot per digit bit and ranked by lane;
+// per-wave counts in LDS order the waves, and a running count per digit orders the
+// rounds, so equal keys keep their input order. It uses no library scratch that must
+// be cleared beforehand, so a captured graph can replay it.
+constexpr int RS_TILE = 1024;
+
+__global__ void k_rs_hist(int32_t n, const uint32_t* __restrict__ key, int shift, int32_t ntiles,
+                          int32_t* __restrict__ hist) {
+    __shared__ int32_t c[256];
+    c[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_TILE / 256; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        if (i < n) atomicAdd(&c[(key[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = c[threadIdx.x];
+}
+
+__global__ void k_rs_scatter(int32_t n, const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                             uint32_t* __restrict__ kout, int32_t* __restrict__ vout, int shift,
+                             int32_t ntiles, const int32_t* __restrict__ off) {
+    __shared__ int32_t run[256];    // next output slot of each digit
+    __shared__ int32_t wc[4][256];  // this round: per wave, items of each digit, then slots
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    run[tid] = off[(int64_t)tid * ntiles + blockIdx.x];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_TILE / 256; ++r) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+        __syncthreads();
+        const int64_t i = base + r * 256 + tid;
+        const bool ok = i < n;
+        const uint32_t k = ok ? kin[i] : 0u;
+        const uint32_t d = (k >> shift) & 255u;
+        unsigned long long m = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const unsigned long long bb = __ballot((d >> b) & 1u);
+            m &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const int rank = __popcll(m & below);
+        if (ok && (m >> lane) == 1ull) wc[wave][d] = rank + 1;  // last lane of its digit
+        __syncthreads();
+        int32_t acc = run[tid];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int32_t c = wc[w][tid];
+            wc[w][tid] = acc;
+            acc += c;
+        }
+        run[tid] = acc;
+        __syncthreads();
+        if (ok) {
+            const int32_t pos = wc[wave][d] + rank;
+            kout[pos] = k;
+            vout[pos] = vin[i];
+        }
+        __syncthreads();
+    }
+}
+
+// Zero fill of nw 32-bit words (in place of a memset, which a replayed graph must not hold).
+__global__ void k_zero_words(uint32_t* __restrict__ p, int64_t nw) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 __global__ void k_p2_nid(int32_t n, const int32_t* __restrict__ old, int32_t* __restrict__ nid) {
@@ -335,8 +410,32 @@ static unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>((n + 
 
 static int key_bits(int64_t nlab) {
     int b = 1;
-    while (b < 63 && ((int64_t)1 << b) < 2 * nlab + 2) ++b;
+    while (b < 32 && ((int64_t)1 << b) < 2 * nlab + 2) ++b;
     return b;
+}
+
+static void zero_bytes(hipStream_t s, void* p, size_t bytes) {
+    const int64_t nw = (int64_t)(bytes / 4);
+    if (nw <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((nw + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_zero_words, dim3(grid), dim3(256), 0, s, (uint32_t*)p, nw);
+}
+
+int SkBuild::issue_phase1(hipStream_t s) const {
+    if (n <= 0) return BC_OK;
+    KTimer kt(BC_K_OTHER, s);
+    zero_bytes(s, p_psize, (size_t)nlab * 4);
+    zero_bytes(s, p_pnf, (size_t)nlab * 4);
+    zero_bytes(s, p_parc, (size_t)nlab * 8);
+    zero_bytes(s, p_cross, 8);
+    hipLaunchKernelGGL(k_p1_labels, dim3(blocks_for(n)), dim3(256), 0, s, n, p_part, p_lab, p_ist);
+    if (nS)
+        hipLaunchKernelGGL(k_p1_targets, dim3(blocks_for(nS)), dim3(256), 0, s, nS, p_S, k_in, given ? 1 : 0,
+                           p_lab, p_ist);
+    hipLaunchKernelGGL(k_p1_frontier, dim3(blocks_for(n)), dim3(256), 0, s, n, g->d_row_ptr, g->d_col, p_lab,
+                       p_fr, p_psize, p_pnf, p_parc, p_cross);
+    BC_HIP(hipGetLastError());
+    return BC_OK;
 }
 
 int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const int32_t* Sx, int32_t nSx,
@@ -352,6 +451,8 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
             return fail(BC_E_INVAL, "partition label out of range at node " + std::to_string(v));
     BC_TRY(validate_targets(n, Sx, nS));
     S.assign(Sx, Sx + nS);
+    k_in = k;
+    given = given_singletons;
     weighted = g->d_len != nullptr;
     nlab = (int64_t)k + (given_singletons ? 0 : nS);
     if (nlab >= INT32_MAX) return fail(BC_E_INVAL, "too many parts");
@@ -368,36 +469,23 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
         Arena& P = gm->pre;
         const size_t need = (size_t)n * 4 * 2 + (size_t)n * 2 + (size_t)nS * 4 + (size_t)nlab * 16 + 16 * 256;
         BC_TRY(P.reserve(need));
-        int32_t* d_part = P.take<int32_t>(n);
+        p_part = P.take<int32_t>(n);
         p_lab = P.take<int32_t>(n);
         p_ist = P.take<uint8_t>(n);
         p_fr = P.take<uint8_t>(n);
         p_S = P.take<int32_t>(std::max(nS, 1));
-        int32_t* d_psize = P.take<int32_t>(nlab);
-        int32_t* d_pnf = P.take<int32_t>(nlab);
-        unsigned long long* d_parc = P.take<unsigned long long>(nlab);
-        unsigned long long* d_cross = P.take<unsigned long long>(1);
-        if (!d_cross) return fail(BC_E_NOMEM, "partition: scratch too small");
-        BC_HIP(hipMemcpyAsync(d_part, part, (size_t)n * 4, hipMemcpyHostToDevice, s));
+        p_psize = P.take<int32_t>(nlab);
+        p_pnf = P.take<int32_t>(nlab);
+        p_parc = P.take<unsigned long long>(nlab);
+        p_cross = P.take<unsigned long long>(1);
+        if (!p_cross) return fail(BC_E_NOMEM, "partition: scratch too small");
+        BC_HIP(hipMemcpyAsync(p_part, part, (size_t)n * 4, hipMemcpyHostToDevice, s));
         if (nS) BC_HIP(hipMemcpyAsync(p_S, S.data(), (size_t)nS * 4, hipMemcpyHostToDevice, s));
-        BC_HIP(hipMemsetAsync(d_psize, 0, (size_t)nlab * 4, s));
-        BC_HIP(hipMemsetAsync(d_pnf, 0, (size_t)nlab * 4, s));
-        BC_HIP(hipMemsetAsync(d_parc, 0, (size_t)nlab * 8, s));
-        BC_HIP(hipMemsetAsync(d_cross, 0, 8, s));
-        {
-            KTimer kt(BC_K_OTHER, s);
-            hipLaunchKernelGGL(k_p1_labels, dim3(blocks_for(n)), dim3(256), 0, s, n, d_part, p_lab, p_ist);
-            if (nS)
-                hipLaunchKernelGGL(k_p1_targets, dim3(blocks_for(nS)), dim3(256), 0, s, nS, p_S, k,
-                                   given_singletons ? 1 : 0, p_lab, p_ist);
-            hipLaunchKernelGGL(k_p1_frontier, dim3(blocks_for(n)), dim3(256), 0, s, n, g->d_row_ptr, g->d_col,
-                               p_lab, p_fr, d_psize, d_pnf, d_parc, d_cross);
-        }
-        BC_HIP(hipGetLastError());
-        BC_HIP(hipMemcpyAsync(psize.data(), d_psize, (size_t)nlab * 4, hipMemcpyDeviceToHost, s));
-        BC_HIP(hipMemcpyAsync(pnf.data(), d_pnf, (size_t)nlab * 4, hipMemcpyDeviceToHost, s));
-        BC_HIP(hipMemcpyAsync(parc.data(), d_parc, (size_t)nlab * 8, hipMemcpyDeviceToHost, s));
-        BC_HIP(hipMemcpyAsync(&cross, d_cross, 8, hipMemcpyDeviceToHost, s));
+        BC_TRY(issue_phase1(s));
+        BC_HIP(hipMemcpyAsync(psize.data(), p_psize, (size_t)nlab * 4, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(pnf.data(), p_pnf, (size_t)nlab * 4, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(parc.data(), p_parc, (size_t)nlab * 8, hipMemcpyDeviceToHost, s));
+        BC_HIP(hipMemcpyAsync(&cross, p_cross, 8, hipMemcpyDeviceToHost, s));
         BC_HIP(hipStreamSynchronize(s));
     }
     tr.mark("phase 1 (device)");
@@ -447,13 +535,13 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
     }
     if (rows >= INT32_MAX) return fail(BC_E_INVAL, "too many interior nodes");
     nint = (int32_t)rows;
-    // scratch of the device sort and scans
+    // scratch of the device scans (CSR offsets, and the radix sort's digit offsets)
     cub_bytes = 0;
+    ntiles = (int32_t)std::max<int64_t>((n + RS_TILE - 1) / RS_TILE, 1);
     if (n > 0) {
         size_t b = 0;
-        BC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, (unsigned long long*)nullptr,
-                                                  (unsigned long long*)nullptr, (int32_t*)nullptr,
-                                                  (int32_t*)nullptr, n, 0, key_bits(nlab), s));
+        BC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int32_t*)nullptr, (int32_t*)nullptr,
+                                                (int64_t)ntiles * 256, s));
         cub_bytes = std::max(cub_bytes, b);
         BC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, n + 1, s));
         cub_bytes = std::max(cub_bytes, b);
@@ -472,25 +560,68 @@ size_t SkBuild::temp_bytes() const {
     need += N * (8 + 8 + 4 + 4 + 4 + 8 + 8 + 1 + 4 + 1) + 16 +  // keys, vals, old, nid, counts, irp, blk, out
             (size_t)n_intra * (weighted ? 8 : 4) + (size_t)nR * 8 + K * (8 + 4 + 8 + 4 + 4 + 1) + 16 +
             ng * (sizeof(DskInfo) + sizeof(GroupDesc)) + I * 20 + (size_t)std::max(nS, 1) * 4 +
-            (size_t)(nlab + 1) * (8 * 2 + 4 * 4) + cub_bytes + 48 * 256;
+            (size_t)(nlab + 1) * (8 * 2 + 4 * 4) + (size_t)ntiles * 256 * 4 * 2 + cub_bytes + 52 * 256;
     return need;
+}
+
+int SkBuild::issue_phase2(hipStream_t s) const {
+    KTimer kt(BC_K_OTHER, s);
+    if (nsk) zero_bytes(s, d_cdeg, (size_t)nsk * 4);
+    zero_bytes(s, d_maxlen, 4);
+    zero_bytes(s, d_rmax, 4);
+    zero_bytes(s, d_icnt + n, 8);
+    zero_bytes(s, d_rcnt + nsk, 8);
+    if (n > 0) {
+        // renumbering: sort (key, node) pairs; the pass count decides which value
+        // buffer the first pass reads so that the last one writes d_old
+        const int bits = key_bits(nlab), passes = (bits + 7) / 8;
+        uint32_t* kb[2] = {d_keys, d_keys2};
+        int32_t* vb[2] = {passes % 2 ? d_vals : d_old, passes % 2 ? d_old : d_vals};
+        hipLaunchKernelGGL(k_p2_keys, dim3(blocks_for(n)), dim3(256), 0, s, n, p_lab, p_fr, kb[0], vb[0]);
+        for (int ps = 0; ps < passes; ++ps) {
+            const int i = ps & 1;
+            hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(256), 0, s, n, kb[i], 8 * ps, ntiles, d_hist);
+            size_t cb = cub_bytes;
+            BC_HIP(hipcub::DeviceScan::ExclusiveSum(d_cub, cb, d_hist, d_hoff, (int64_t)ntiles * 256, s));
+            hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(256), 0, s, n, kb[i], vb[i], kb[i ^ 1], vb[i ^ 1],
+                               8 * ps, ntiles, d_hoff);
+        }
+        hipLaunchKernelGGL(k_p2_nid, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, d_nid);
+        hipLaunchKernelGGL(k_p2_count, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, g->d_row_ptr, g->d_col,
+                           p_lab, p_fr, d_poff, d_fbase, d_icnt, d_rcnt, d_rdeg);
+        size_t cb = cub_bytes;
+        BC_HIP(hipcub::DeviceScan::ExclusiveSum(d_cub, cb, d_icnt, d_irp, n + 1, s));
+        cb = cub_bytes;
+        BC_HIP(hipcub::DeviceScan::ExclusiveSum(d_cub, cb, d_rcnt, d_rptr, nsk + 1, s));
+        hipLaunchKernelGGL(k_p2_fill, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, d_nid, g->d_row_ptr,
+                           g->d_col, g->d_len, p_lab, p_fr, d_poff, d_fbase, d_irp, d_rptr, d_icol, d_iw,
+                           d_rcol, d_rw, d_rmax);
+        hipLaunchKernelGGL(k_p2_rows, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, p_lab, p_fr, p_ist, d_poff,
+                           d_fbase, d_ppnf, d_pg0, d_png, d_ibase, d_blk, d_il, d_ig0, d_ing, d_inode, d_out_idx,
+                           d_out_which, d_nodes, d_sflag);
+        if (nS)
+            hipLaunchKernelGGL(k_p2_src, dim3(blocks_for(nS)), dim3(256), 0, s, nS, p_S, p_fr, p_lab, d_nid,
+                               d_poff, d_fbase, d_srcsk);
+    }
+    BC_HIP(hipGetLastError());
+    return BC_OK;
 }
 
 int SkBuild::upload(Arena& W, hipStream_t s) {
     PhaseTrace tr("upload");
     const int32_t ng = (int32_t)groups.size();
     const int64_t NL = std::max<int64_t>(nlab, 1);
-    unsigned long long* keys = W.take<unsigned long long>(std::max(n, 1));
-    unsigned long long* keys2 = W.take<unsigned long long>(std::max(n, 1));
-    int32_t* vals = W.take<int32_t>(std::max(n, 1));
+    d_keys = W.take<uint32_t>(std::max(n, 1));
+    d_keys2 = W.take<uint32_t>(std::max(n, 1));
+    d_vals = W.take<int32_t>(std::max(n, 1));
     d_old = W.take<int32_t>(std::max(n, 1));
     d_nid = W.take<int32_t>(std::max(n, 1));
-    int64_t* icnt = W.take<int64_t>(n + 1);
+    d_icnt = W.take<int64_t>(n + 1);
     d_irp = W.take<int64_t>(n + 1);
     d_icol = W.take<int32_t>(std::max<int64_t>(n_intra, 1));
     d_iw = weighted ? W.take<uint32_t>(std::max<int64_t>(n_intra, 1)) : nullptr;
     d_blk = W.take<uint8_t>(std::max(n, 1));
-    int64_t* rcnt = W.take<int64_t>(nsk + 1);
+    d_rcnt = W.take<int64_t>(nsk + 1);
     d_rdeg = W.take<int32_t>(std::max(nsk, 1));
     d_rptr = W.take<int64_t>(nsk + 1);
     d_rcol = W.take<int32_t>(std::max<int64_t>(nR, 1));
@@ -507,21 +638,23 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
     d_nodes = W.take<int32_t>(std::max(nsk, 1));
     d_sflag = W.take<uint8_t>(std::max(nsk, 1));
     d_srcsk = W.take<int32_t>(std::max(nS, 1));
-    int64_t* d_poff = W.take<int64_t>(NL + 1);
-    int64_t* d_fbase = W.take<int64_t>(NL + 1);
-    int32_t* d_pnf = W.take<int32_t>(NL);
-    int32_t* d_pg0 = W.take<int32_t>(NL);
-    int32_t* d_png = W.take<int32_t>(NL);
-    int32_t* d_ibase = W.take<int32_t>(NL);
+    d_poff = W.take<int64_t>(NL + 1);
+    d_fbase = W.take<int64_t>(NL + 1);
+    d_ppnf = W.take<int32_t>(NL);
+    d_pg0 = W.take<int32_t>(NL);
+    d_png = W.take<int32_t>(NL);
+    d_ibase = W.take<int32_t>(NL);
     d_maxlen = W.take<uint32_t>(1);
     d_rmax = W.take<uint32_t>(1);
-    void* cub = W.take<unsigned char>(std::max<size_t>(cub_bytes, 1));
+    d_hist = W.take<int32_t>((size_t)ntiles * 256);
+    d_hoff = W.take<int32_t>((size_t)ntiles * 256);
+    d_cub = W.take<unsigned char>(std::max<size_t>(cub_bytes, 1));
     d_desc = W.take<GroupDesc>(std::max(ng, 1));
-    if (!keys || !keys2 || !vals || !d_old || !d_nid || !icnt || !d_irp || !d_icol || (weighted && !d_iw) ||
-        !d_blk || !rcnt || !d_rdeg || !d_rptr || !d_rcol || !d_rw || !d_cdeg || !d_info || !d_il || !d_ig0 ||
+    if (!d_keys || !d_keys2 || !d_vals || !d_old || !d_nid || !d_icnt || !d_irp || !d_icol || (weighted && !d_iw) ||
+        !d_blk || !d_rcnt || !d_rdeg || !d_rptr || !d_rcol || !d_rw || !d_cdeg || !d_info || !d_il || !d_ig0 ||
         !d_ing || !d_tdeg || !d_inode || !d_out_idx || !d_out_which || !d_nodes || !d_sflag || !d_srcsk ||
-        !d_poff || !d_fbase || !d_pnf || !d_pg0 || !d_png || !d_ibase || !d_maxlen || !d_rmax || !cub ||
-        !d_desc)
+        !d_poff || !d_fbase || !d_ppnf || !d_pg0 || !d_png || !d_ibase || !d_maxlen || !d_rmax || !d_hist ||
+        !d_hoff || !d_cub || !d_desc)
         return fail(BC_E_NOMEM, "partition: workspace too small");
     auto h2d = [&](void* d, const void* h, size_t b) -> int {
         if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s));
@@ -529,39 +662,12 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
     };
     BC_TRY(h2d(d_poff, poff.data(), (size_t)(nlab + 1) * 8));
     BC_TRY(h2d(d_fbase, fbase.data(), (size_t)(nlab + 1) * 8));
-    BC_TRY(h2d(d_pnf, pnf.data(), (size_t)nlab * 4));
+    BC_TRY(h2d(d_ppnf, pnf.data(), (size_t)nlab * 4));
     BC_TRY(h2d(d_pg0, p_g0.data(), (size_t)nlab * 4));
     BC_TRY(h2d(d_png, p_ng.data(), (size_t)nlab * 4));
     BC_TRY(h2d(d_ibase, ibase.data(), (size_t)nlab * 4));
     BC_TRY(h2d(d_info, info.data(), (size_t)ng * sizeof(DskInfo)));
-    if (nsk) BC_HIP(hipMemsetAsync(d_cdeg, 0, (size_t)nsk * 4, s));
-    BC_HIP(hipMemsetAsync(d_maxlen, 0, 4, s));
-    BC_HIP(hipMemsetAsync(d_rmax, 0, 4, s));
-    BC_HIP(hipMemsetAsync(icnt + n, 0, 8, s));
-    BC_HIP(hipMemsetAsync(rcnt + nsk, 0, 8, s));
-    if (n > 0) {
-        KTimer kt(BC_K_OTHER, s);
-        size_t cb = cub_bytes;
-        hipLaunchKernelGGL(k_p2_keys, dim3(blocks_for(n)), dim3(256), 0, s, n, p_lab, p_fr, keys, vals);
-        BC_HIP(hipcub::DeviceRadixSort::SortPairs(cub, cb, keys, keys2, vals, d_old, n, 0, key_bits(nlab), s));
-        hipLaunchKernelGGL(k_p2_nid, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, d_nid);
-        hipLaunchKernelGGL(k_p2_count, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, g->d_row_ptr, g->d_col,
-                           p_lab, p_fr, d_poff, d_fbase, icnt, rcnt, d_rdeg);
-        cb = cub_bytes;
-        BC_HIP(hipcub::DeviceScan::ExclusiveSum(cub, cb, icnt, d_irp, n + 1, s));
-        cb = cub_bytes;
-        BC_HIP(hipcub::DeviceScan::ExclusiveSum(cub, cb, rcnt, d_rptr, nsk + 1, s));
-        hipLaunchKernelGGL(k_p2_fill, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, d_nid, g->d_row_ptr,
-                           g->d_col, g->d_len, p_lab, p_fr, d_poff, d_fbase, d_irp, d_rptr, d_icol, d_iw,
-                           d_rcol, d_rw, d_rmax);
-        hipLaunchKernelGGL(k_p2_rows, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, p_lab, p_fr, p_ist, d_poff,
-                           d_fbase, d_pnf, d_pg0, d_png, d_ibase, d_blk, d_il, d_ig0, d_ing, d_inode, d_out_idx,
-                           d_out_which, d_nodes, d_sflag);
-        if (nS)
-            hipLaunchKernelGGL(k_p2_src, dim3(blocks_for(nS)), dim3(256), 0, s, nS, p_S, p_fr, p_lab, d_nid,
-                               d_poff, d_fbase, d_srcsk);
-    }
-    BC_HIP(hipGetLastError());
+    BC_TRY(issue_phase2(s));
     for (auto& G : groups) {
         G.g.row_ptr = d_irp;
         G.g.col = d_icol;
@@ -570,16 +676,14 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
         if (!group_alloc(W, G, 0)) return fail(BC_E_NOMEM, "partition: group state does not fit");
     }
     BC_TRY(h2d(d_desc, groups.data(), (size_t)ng * sizeof(GroupDesc)));
-    // host arrays above are staged by the runtime; after this the scratch arena of the
-    // graph is no longer read
+    // host arrays above are staged by the runtime; after this only a replay of the
+    // device work reads the graph's scratch arena again
     BC_HIP(hipStreamSynchronize(s));
     tr.mark("phase 2 (device)");
     return BC_OK;
 }
 
-int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
-                      const std::function<int(size_t, Arena*&)>& get_store) {
-    (void)W;
+int SkBuild::issue_count(hipStream_t s) const {
     const int32_t ng = (int32_t)groups.size();
     if (ng > 0) {
         KTimer kt(BC_K_OTHER, s);
@@ -589,6 +693,45 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
                                d_ig0, d_ing, d_tdeg, nullptr, nullptr, nullptr, nullptr);
     }
     BC_HIP(hipGetLastError());
+    return BC_OK;
+}
+
+int SkBuild::issue_fill(hipStream_t s, const bc_skeleton* sk) const {
+    const int32_t ng = (int32_t)groups.size();
+    auto d2d = [&](void* d, const void* h, size_t b) -> int {
+        if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyDeviceToDevice, s));
+        return BC_OK;
+    };
+    BC_TRY(d2d(sk->d_nflag, d_sflag, nsk));
+    BC_TRY(d2d(sk->d_nodes, d_nodes, (size_t)nsk * 4));
+    BC_TRY(d2d(sk->d_tnode, d_inode, (size_t)nint * 4));
+    BC_TRY(d2d(sk->d_out_idx, d_out_idx, (size_t)n * 4));
+    BC_TRY(d2d(sk->d_out_which, d_out_which, n));
+    {
+        KTimer kt(BC_K_OTHER, s);
+        if (nsk)
+            hipLaunchKernelGGL(k_fill_r, dim3((nsk + 255) / 256), dim3(256), 0, s, nsk, d_rptr, d_rcol, d_rw,
+                               sk->d_row_ptr, sk->d_col, sk->d_len, sk->d_mult);
+        if (ng) {
+            hipLaunchKernelGGL(k_clique_fill, dim3((ng + 3) / 4), dim3(256), 0, s, d_desc, d_info, ng,
+                               sk->d_row_ptr, d_rdeg, sk->d_col, sk->d_len, sk->d_mult, d_maxlen);
+            if (nint)
+                hipLaunchKernelGGL(k_table, dim3((nint + 3) / 4), dim3(256), 0, s, d_desc, d_info, nint, d_il,
+                                   d_ig0, d_ing, nullptr, sk->d_trow, sk->d_tcol, sk->d_tlen, sk->d_tsig);
+        }
+        if (nsk)
+            hipLaunchKernelGGL(k_sk_twin, dim3((nsk + 3) / 4), dim3(256), 0, s, nsk, sk->d_row_ptr, d_rdeg,
+                               sk->d_col, sk->d_twin);
+    }
+    BC_HIP(hipGetLastError());
+    return BC_OK;
+}
+
+int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
+                      const std::function<int(size_t, Arena*&)>& get_store) {
+    (void)W;
+    const int32_t ng = (int32_t)groups.size();
+    BC_TRY(issue_count(s));
     std::vector<int32_t> cdeg(nsk, 0), rdeg(nsk, 0), tdeg(nint, 0);
     if (nsk) {
         BC_HIP(hipMemcpyAsync(cdeg.data(), d_cdeg, (size_t)nsk * 4, hipMemcpyDeviceToHost, s));
@@ -631,34 +774,9 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
         if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s));
         return BC_OK;
     };
-    auto d2d = [&](void* d, const void* h, size_t b) -> int {
-        if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyDeviceToDevice, s));
-        return BC_OK;
-    };
     BC_TRY(h2d(sk->d_row_ptr, srow.data(), (size_t)(nsk + 1) * 8));
     BC_TRY(h2d(sk->d_trow, trow.data(), (size_t)(nint + 1) * 8));
-    BC_TRY(d2d(sk->d_nflag, d_sflag, nsk));
-    BC_TRY(d2d(sk->d_nodes, d_nodes, (size_t)nsk * 4));
-    BC_TRY(d2d(sk->d_tnode, d_inode, (size_t)nint * 4));
-    BC_TRY(d2d(sk->d_out_idx, d_out_idx, (size_t)n * 4));
-    BC_TRY(d2d(sk->d_out_which, d_out_which, n));
-    {
-        KTimer kt(BC_K_OTHER, s);
-        if (nsk)
-            hipLaunchKernelGGL(k_fill_r, dim3((nsk + 255) / 256), dim3(256), 0, s, nsk, d_rptr, d_rcol, d_rw,
-                               sk->d_row_ptr, sk->d_col, sk->d_len, sk->d_mult);
-        if (ng) {
-            hipLaunchKernelGGL(k_clique_fill, dim3((ng + 3) / 4), dim3(256), 0, s, d_desc, d_info, ng,
-                               sk->d_row_ptr, d_rdeg, sk->d_col, sk->d_len, sk->d_mult, d_maxlen);
-            if (nint)
-                hipLaunchKernelGGL(k_table, dim3((nint + 3) / 4), dim3(256), 0, s, d_desc, d_info, nint, d_il,
-                                   d_ig0, d_ing, nullptr, sk->d_trow, sk->d_tcol, sk->d_tlen, sk->d_tsig);
-        }
-        if (nsk)
-            hipLaunchKernelGGL(k_sk_twin, dim3((nsk + 3) / 4), dim3(256), 0, s, nsk, sk->d_row_ptr, d_rdeg,
-                               sk->d_col, sk->d_twin);
-    }
-    BC_HIP(hipGetLastError());
+    BC_TRY(issue_fill(s, sk));
     uint32_t clique_max = 0, rmax = 0;
     std::vector<int32_t> srcsk(nS);
     sk->h_out_idx.resize(n);
@@ -703,9 +821,10 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
 }
 
 int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
-                   bc_skeleton** out, bool given_singletons) {
+                   bc_skeleton** out, bool given_singletons, PartitionKeep* keep) {
     PhaseTrace tr("partition");
-    SkBuild b;
+    SkBuild local;
+    SkBuild& b = keep ? keep->b : local;
     BC_TRY(b.prepare(g, part, k, S, nS, given_singletons));
     tr.mark("prepare (host)");
     bc_graph* gm = const_cast<bc_graph*>(g);
@@ -733,7 +852,17 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
             G.gsig = W.take<uint64_t>((size_t)(G.hi - G.lo));
             if (!G.gdist || !G.gsig) return fail(BC_E_NOMEM, "partition: workspace too small");
         }
-        BC_TRY(run_resident(s, W, b.groups));
+        if (keep) {
+            keep->resident = true;
+            BC_TRY(resident_upload(s, W, b.groups, &keep->L));
+            BC_TRY(resident_launch(s, keep->L));
+            uint32_t herr = 0;
+            BC_HIP(hipMemcpyAsync(&herr, keep->L.d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            BC_HIP(hipStreamSynchronize(s));
+            if (herr & ERR_OVERFLOW) return fail(BC_E_OVERFLOW, "a shortest-path count reached 2^64");
+        } else {
+            BC_TRY(run_resident(s, W, b.groups));
+        }
     } else if (!b.groups.empty()) {
         BC_TRY(run_groups_prealloc(W, s, b.groups));
     }

@@ -99,3 +99,29 @@ def test_batch_plain_graph_replays_match_eager(bcpp):
             assert np.array_equal(a, b), f"replay {rep} differs from the eager run"
         bcpp.brandes_plain(Go, other.S[: 40 + rep])
         bcpp.Batch(gs[:3]).run(pp=True)
+
+
+def test_batch_pp_graph_replays_match_eager(bcpp):
+    # Brandes++ over a batch replays one captured HIP graph holding the whole pipeline
+    # (Build_SK, Dijkstra_SK, assembly, Brandes_SK + Centrality, reduction); every
+    # replay must equal the eager run bit for bit, with eager runs of the same batch
+    # (which use the union graph's own workspaces) and other work in between
+    big = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 96, 0), inputs.equal_sizes(20000, 40),
+                     4.0 / 499, 15000, 3, "big20k")
+    big.S = inputs.random_targets(33, big.n, 25)
+    gs = inputs.batch_256(20) + [big] + mixed_graphs()
+    B = bcpp.Batch(gs)
+    eager = B.run(pp=True, graph=False)
+    for g, got in zip(gs, eager):
+        assert_scores(got, oracle.bc(g, g.S))
+    other = inputs.planted_1k()
+    Go = bcpp.Graph(other)
+    for rep in range(4):
+        res = B.run(pp=True)
+        for a, b in zip(res, eager):
+            assert np.array_equal(a, b), f"replay {rep} differs from the eager run"
+        again = B.run(pp=True, graph=False)
+        for a, b in zip(again, eager):
+            assert np.array_equal(a, b)
+        bcpp.brandes_pp(Go, bcpp.partition_sk(Go, other.part, other.k, other.S[: 40 + rep]))
+        B.run(pp=False)
