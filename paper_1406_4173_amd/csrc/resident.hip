@@ -48,8 +48,9 @@ __device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
     return v;
 }
 
-// Visit the nodes v of [0, n) for which sel(v) holds. Each wave scans 64 consecutive
-// nodes per pass (its share: passes T apart), appends the selected ones to its own LDS
+// Visit the nodes v of [0, n) for which sel(v) holds. Wave w owns the BLK-node blocks b
+// with b % (T / 64) == w and scans 64 of its nodes per pass (64 / BLK blocks), in
+// increasing order; it appends the selected ones to its own LDS
 // queue wq (128 entries) and hands every full queue of 64, and the last partial one,
 // to body(v, valid) with all lanes converged. A step that settles few nodes thus costs
 // one round of neighbour loads per wave instead of one per scan pass. sel is
@@ -57,16 +58,20 @@ __device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
 // on what body does to other nodes in the same step. The queue is private to the
 // wave, whose LDS accesses complete in order.
 constexpr int WQ = 128;
-template <int T, int SCAN, class Sel, class Body>
+template <int T, int SCAN, int BLK, class Sel, class Body>
 __device__ __forceinline__ void for_selected(int32_t n, int32_t* __restrict__ wq, Sel&& sel, Body&& body) {
+    constexpr int NW = T / 64;
     const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    // pass q of wave w reads blocks w + NW * (q * 64 / BLK + j), j = lane / BLK
+    const int32_t off = NW * BLK * (lane / BLK) + lane % BLK;
     int cnt = 0;
-    for (int32_t base0 = (int32_t)(threadIdx.x & ~63u); base0 < n; base0 += SCAN * T) {
+    for (int32_t base0 = wave * BLK; base0 < n; base0 += SCAN * T) {
         unsigned long long ms[SCAN];
         bool hit[SCAN];
 #pragma unroll
         for (int p = 0; p < SCAN; ++p) {
-            const int32_t v = base0 + p * T + lane;
+            const int32_t v = base0 + p * T + off;
             hit[p] = v < n && sel(v);
             ms[p] = __ballot(hit[p]);
         }
@@ -76,7 +81,7 @@ __device__ __forceinline__ void for_selected(int32_t n, int32_t* __restrict__ wq
             if (m == 0ull) continue;
             const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            if (hit[p]) wq[cnt + rank] = base0 + p * T + lane;
+            if (hit[p]) wq[cnt + rank] = base0 + p * T + off;
             cnt += __popcll(m);
             if (cnt >= 64) {
                 body(wq[lane], true);
@@ -286,6 +291,11 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     // Dijkstra_SK groups (no GF_BACKWARD): forward only, restricted path counts, and
     // d and sigma of every node written out per source lane
     const bool bwd = (R.flags & GF_BACKWARD) != 0;
+    // Node ownership blocks of the scan: a step's nodes cluster (communities are runs of
+    // ids), and the step lasts as long as its busiest wave, so LDS-state groups deal
+    // 16-node blocks round the waves. Device-memory state keeps 64-node blocks, those of
+    // the bucket visit.
+    constexpr int OWN_BLK = GLOBAL ? 64 : 16;
     const bool restrict_ = (R.flags & GF_RESTRICT) != 0;
     // Bucket bitmaps (state in device memory and R.lg >= 0), in LDS: bucket d mod 2^lg
     // holds one bit per node offered distance d (the pending distances D+1 .. D+longest
@@ -304,7 +314,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     uint32_t* __restrict__ bc = bm + (size_t)(RM + 1) * W;         // [RM+1][2]
     auto cidx = [&](uint32_t d) { return ((d & RM) << 1) | ((d >> lg) & 1u); };
     // this wave's record region (backward groups): nodes, then step numbers, then ends;
-    // a wave queues only nodes of its own 64-node blocks (b % (T / 64) == wave)
+    // a wave queues only nodes of its own blocks (at most 64 * ceil(n / T) of them)
     const int32_t wcap = 64 * ((n + T - 1) / T);
     int32_t* __restrict__ rnodes = bwd ? R.rlist + (int64_t)(tid >> 6) * 3 * wcap : nullptr;
     int32_t* __restrict__ rsegk = bwd ? rnodes + wcap : nullptr;
@@ -399,13 +409,13 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                 // on a count that stale bits inflate by a racy amount) changes no result
                 uint32_t* row = bm + (size_t)(D & RM) * W;
                 if (bc[cidx(D)] > (uint32_t)R.dense) {
-                    for_selected<T, GLOBAL ? 8 : 4>(n, wq, [&](int32_t v) { return D_(v) == D; }, fbody);
+                    for_selected<T, GLOBAL ? 8 : 4, OWN_BLK>(n, wq, [&](int32_t v) { return D_(v) == D; }, fbody);
                     for (int32_t i = tid; i < W; i += T) row[i] = 0u;
                 } else {
                     for_bucket<T>(row, W, wq, [&](int32_t v) { return D_(v) == D; }, fbody);
                 }
             } else {
-                for_selected<T, GLOBAL ? 8 : 4>(
+                for_selected<T, GLOBAL ? 8 : 4, OWN_BLK>(
                     n, wq,
                     [&](int32_t v) {
                         const uint32_t dv = D_(v);
@@ -633,12 +643,12 @@ int64_t tune_value(const char* name, int64_t dflt) {
     const char* e = getenv(name);
     if (!e || !*e) return dflt;
     const long long v = atoll(e);
-    return v > 0 ? (int64_t)v : dflt;
+    return v >= 0 ? (int64_t)v : dflt;
 }
 struct SizeClasses {
     int64_t small = tune_value("BCPP_TUNE_SMALL", tuned_small_range);
     int64_t mid = tune_value("BCPP_TUNE_MID", tuned_mid_range);
-    int64_t dense_shift = tune_value("BCPP_TUNE_DENSE_SHIFT", tuned_dense_shift);
+    int64_t dense_shift = std::min<int64_t>(63, tune_value("BCPP_TUNE_DENSE_SHIFT", tuned_dense_shift));
     int of(int64_t range) const { return range <= small ? 0 : range <= mid ? 1 : 2; }
 };
 
@@ -656,7 +666,7 @@ int64_t resident_max_range() {
 }
 
 int32_t resident_sources_per_group(int64_t nsrc) {
-    const int64_t div = tune_value("BCPP_TUNE_SPG_DIV", tuned_spg_div);
+    const int64_t div = std::max<int64_t>(1, tune_value("BCPP_TUNE_SPG_DIV", tuned_spg_div));
     return (int32_t)std::min<int64_t>(LANES, std::max<int64_t>(1, (nsrc + div - 1) / div));
 }
 

@@ -172,15 +172,16 @@ def test_plain_dev_entry_point(bcpp):
     assert_scores(out.cpu().numpy(), oracle.bc(g, S))
 
 
-@pytest.mark.parametrize("wmax,intra", [(None, 0.9), (4, 0.99), (12, 0.95), (100, 0.95)],
+@pytest.mark.parametrize("n,wmax,intra", [(20000, None, 0.9), (20000, 4, 0.99), (20000, 12, 0.95),
+                                           (20000, 100, 0.95)],
                          ids=["unit", "w4-chain", "w12", "w100-no-buckets"])
-def test_plain_bucket_and_scan_steps_agree(bcpp, monkeypatch, wmax, intra):
+def test_plain_bucket_and_scan_steps_agree(bcpp, monkeypatch, n, wmax, intra):
     """A range too large for LDS keeps bucket bitmaps of the pending distances (arcs up
     to 63 long): a step with few bits reads its bucket, a dense one scans the range.
     Both queue the same nodes in the same order, so every threshold (0: always the
     bucket, 63: always the scan) gives the same bits, and those match the oracle."""
-    rng = inputs.rng_for(inputs.SEED_BASE + 91, 0 if wmax is None else wmax)
-    g = inputs._community_graph(rng, 20000, 400, 8.0, intra, wmax, "bucket20k")
+    rng = inputs.rng_for(inputs.SEED_BASE + 91, 0 if wmax is None else wmax, n)
+    g = inputs._community_graph(rng, n, n // 50, 8.0, intra, wmax, "bucket")
     S = np.sort(rng.choice(g.n, 160, replace=False)).astype(np.int32)
     G = bcpp.Graph(g)
     got = {}
