@@ -173,9 +173,8 @@ __device__ __forceinline__ void for_bucket(uint32_t* __restrict__ row, int32_t W
 // e = the arc, ok = false past the last arc; incl/excl are the calling lane's own
 // inclusive/exclusive arc offsets (its slot's range [excl, incl)). All lanes stay
 // converged, so f may use cross-lane operations before it branches on ok.
-template <class F>
-__device__ __forceinline__ void for_queue_arcs(const int64_t* __restrict__ rp, int32_t lo, int32_t q,
-                                               bool valid, F&& f) {
+template <class P, class F>
+__device__ __forceinline__ void for_queue_arcs(P rp, int32_t lo, int32_t q, bool valid, F&& f) {
     const int lane = threadIdx.x & 63;
     int64_t e0 = 0;
     int deg = 0;
@@ -236,6 +235,16 @@ struct RGroup {
 
 namespace {
 
+// Device-memory arrays are used through global-address-space pointers. The launch
+// records hold generic pointers, whose accesses compile to flat instructions, and a
+// wait for a flat load's data also waits for every LDS operation in flight (and the
+// reverse), which serialises the arc rounds' L2 loads with their LDS atomics.
+#define GAS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GAS T* gas(T* p) {
+    return (GAS T*)p;
+}
+
 // State accessors. With the state in device memory (GLOBAL) the distances and counts
 // change through L2 atomics, so every read goes past the CU's L1 (agent-scope atomic
 // load) and never sees a stale line.
@@ -277,16 +286,23 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         GLOBAL ? R.gsig : reinterpret_cast<uint64_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15));
     auto D_ = [&](int32_t i) { return ld_d<GLOBAL>(&dist[i]); };
     auto S_ = [&](int32_t i) { return ld_s<GLOBAL>(&sig[i]); };
-    const int64_t* __restrict__ rp = C.g.row_ptr;
-    const int32_t* __restrict__ col = C.g.col;
-    const uint32_t* __restrict__ len = C.g.len;
-    const uint64_t* __restrict__ mult = C.g.mult;
-    const uint8_t* __restrict__ nflag = C.g.nflag;
+    // device-memory arrays, read and written as global memory (see gas)
+    const GAS int64_t* __restrict__ rp = gas(C.g.row_ptr);
+    const GAS int32_t* __restrict__ col = gas(C.g.col);
+    const GAS uint32_t* __restrict__ len = gas(C.g.len);
+    const GAS uint64_t* __restrict__ mult = gas(C.g.mult);
+    const GAS uint8_t* __restrict__ nflag = gas(C.g.nflag);
+    const GAS int64_t* __restrict__ trow = gas(C.trow);
+    const GAS int32_t* __restrict__ tcol = gas(C.tcol);
+    const GAS uint32_t* __restrict__ tlen = gas(C.tlen);
+    const GAS uint64_t* __restrict__ tsig = gas(C.tsig);
     const bool cent = (R.flags & GF_CENT) != 0 && R.tn > 0;
-    double* __restrict__ cacc = R.cacc;
+    GAS double* __restrict__ cacc = gas(R.cacc);
+    GAS double* __restrict__ cint = gas(R.cint);
+    GAS uint32_t* __restrict__ steps = gas(R.steps);
     // interior scratch of the current source: d(s,v) and sigma(s,v) per table row
-    uint32_t* __restrict__ idist = R.idist;
-    uint64_t* __restrict__ isig = R.isig;
+    GAS uint32_t* __restrict__ idist = gas(R.idist);
+    GAS uint64_t* __restrict__ isig = gas(R.isig);
 
     // Dijkstra_SK groups (no GF_BACKWARD): forward only, restricted path counts, and
     // d and sigma of every node written out per source lane
@@ -316,13 +332,13 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     // this wave's record region (backward groups): nodes, then step numbers, then ends;
     // a wave queues only nodes of its own blocks (at most 64 * ceil(n / T) of them)
     const int32_t wcap = 64 * ((n + T - 1) / T);
-    int32_t* __restrict__ rnodes = bwd ? R.rlist + (int64_t)(tid >> 6) * 3 * wcap : nullptr;
-    int32_t* __restrict__ rsegk = bwd ? rnodes + wcap : nullptr;
-    int32_t* __restrict__ rsege = bwd ? rnodes + 2 * wcap : nullptr;
+    GAS int32_t* __restrict__ rnodes = bwd ? gas(R.rlist) + (int64_t)(tid >> 6) * 3 * wcap : nullptr;
+    GAS int32_t* __restrict__ rsegk = bwd ? rnodes + wcap : nullptr;
+    GAS int32_t* __restrict__ rsege = bwd ? rnodes + 2 * wcap : nullptr;
     if (bwd)
         for (int32_t v = tid; v < n; v += T) cacc[v] = 0.0;
     if (cent)
-        for (int32_t i = tid; i < R.tn; i += T) R.cint[i] = 0.0;
+        for (int32_t i = tid; i < R.tn; i += T) cint[i] = 0.0;
     unsigned long long bytes = 0;
     if (tid == 0) ovf_flag = 0u;  // ordered before any use by the barrier below
 
@@ -353,7 +369,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         int32_t wcur = 0, wseg = 0, wstep0 = 0, nsteps = 0;
         for (int it = 0, k = 0;; ++it) {
             uint32_t mn = INF32;
-            if (bwd && tid == 0) R.steps[k] = D;
+            if (bwd && tid == 0) steps[k] = D;
             auto fbody =
                 [&](int32_t q, bool valid) {
                     if (prof && valid) bytes += 12ull;
@@ -391,15 +407,20 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         // offers: all above D, so they never meet the parent test above
                         const uint32_t nv = D + L;
                         if (nv < D_(u)) {
-                            const uint32_t old = atomicMin(&dist[u], nv);
-                            if (nv < old) {
-                                if (bucket) {
+                            if (bucket) {
+                                // a bit per successful offer (a failed one leaves none)
+                                const uint32_t old = atomicMin(&dist[u], nv);
+                                if (nv < old) {
                                     const uint32_t bit = 1u << (u & 31);
                                     const uint32_t ow = atomicOr(&bm[(size_t)(nv & RM) * W + (u >> 5)], bit);
                                     if (!(ow & bit)) atomicAdd(&bc[cidx(nv)], 1u);
-                                } else {
-                                    mn = min(mn, nv);
                                 }
+                            } else {
+                                // the smallest offer to a node always lands, so the least
+                                // offer made is the least new tentative distance, and no
+                                // offer has to wait for the atomic's old value
+                                atomicMin(&dist[u], nv);
+                                mn = min(mn, nv);
                             }
                         }
                     });
@@ -474,20 +495,20 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         // ------------------------------------------- interior rows: d and sigma ----
         if (cent) {
             for (int32_t i = tid; i < R.tn; i += T) {
-                const int64_t e0 = C.trow[R.t_lo + i], e1 = C.trow[R.t_lo + i + 1];
+                const int64_t e0 = trow[R.t_lo + i], e1 = trow[R.t_lo + i + 1];
                 uint32_t dv = INF32;
                 for (int64_t e = e0; e < e1; ++e) {
-                    const uint32_t tf = D_(C.tcol[e] - lo);
-                    if (tf != INF32) dv = min(dv, tf + C.tlen[e]);
+                    const uint32_t tf = D_(tcol[e] - lo);
+                    if (tf != INF32) dv = min(dv, tf + tlen[e]);
                 }
                 uint64_t sv = 0;
                 bool o2 = false;
                 if (dv != INF32) {
                     for (int64_t e = e0; e < e1; ++e) {
-                        const int32_t f = C.tcol[e] - lo;
+                        const int32_t f = tcol[e] - lo;
                         const uint32_t tf = D_(f);
-                        if (tf == INF32 || tf + C.tlen[e] != dv) continue;
-                        const uint64_t a = S_(f), m = C.tsig[e];
+                        if (tf == INF32 || tf + tlen[e] != dv) continue;
+                        const uint64_t a = S_(f), m = tsig[e];
                         if (__umul64hi(a, m) != 0) o2 = true;
                         const uint64_t r = sv + a * m;
                         if (r < sv) o2 = true;
@@ -507,7 +528,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         // recorded for the step, so a node meets the same lanes as in the forward sweep
         int32_t seg = wseg - 1;
         for (int k = nsteps - 1; k >= 1; --k) {
-            D = R.steps[k];
+            D = steps[k];
             auto body = [&](int32_t q, bool valid) {
                     double prev = 0.0, ind = 0.0, acc = 0.0;
                     if (prof && valid) bytes += 8ull;
@@ -564,15 +585,15 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             for (int32_t i = tid; i < R.tn; i += T) {
                 const uint32_t dv = idist[i];
                 if (dv == INF32) continue;
-                const int64_t e0 = C.trow[R.t_lo + i], e1 = C.trow[R.t_lo + i + 1];
+                const int64_t e0 = trow[R.t_lo + i], e1 = trow[R.t_lo + i + 1];
                 double acc = 0.0;
                 for (int64_t e = e0; e < e1; ++e) {
-                    const int32_t f = C.tcol[e] - lo;
+                    const int32_t f = tcol[e] - lo;
                     const uint32_t tf = D_(f);
-                    if (tf == INF32 || tf != dv + C.tlen[e]) continue;
-                    acc += (double)C.tsig[e] * __longlong_as_double((long long)S_(f));
+                    if (tf == INF32 || tf != dv + tlen[e]) continue;
+                    acc += (double)tsig[e] * __longlong_as_double((long long)S_(f));
                 }
-                R.cint[i] += (double)isig[i] * acc;
+                cint[i] += (double)isig[i] * acc;
             }
         }
         __syncthreads();
