@@ -42,6 +42,75 @@ __device__ __forceinline__ uint32_t wmin_u32(uint32_t v) {
     return v;
 }
 
+// Inclusive wave scans with DPP (GFX9 family: row shifts inside 16-lane rows and row
+// broadcasts; VALU only, no LDS round trip): shifts by 1, 2, 4 and 8 inside each row,
+// then lane 15's value into row 1 and lane 47's into row 3, then lane 31's into rows 2
+// and 3. A lane whose source lies outside its row, or whose row is masked off, takes
+// the identity.
+constexpr int DPP_ROW_SHR = 0x110, DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+
+__device__ __forceinline__ int wscan_add(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR | 1, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR | 2, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR | 4, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR | 8, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_BCAST15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_BCAST31, 0xc, 0xf, false);
+    return x;
+}
+
+// The same for max over values >= -1 (identity -1).
+__device__ __forceinline__ int wscan_max(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, DPP_ROW_SHR | 1, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, DPP_ROW_SHR | 2, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, DPP_ROW_SHR | 4, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, DPP_ROW_SHR | 8, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, DPP_BCAST15, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, DPP_BCAST31, 0xc, 0xf, false));
+    return x;
+}
+
+// fp64 value of the lane O places lower in the same 16-lane row (0 where there is none).
+template <int O>
+__device__ __forceinline__ double dpp_row_shr(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, DPP_ROW_SHR | O, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), DPP_ROW_SHR | O, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
+}
+
+// Segmented inclusive sum over the wave: lane l adds the values of lanes seg .. l (its
+// segment starts at lane seg <= l; segments are contiguous). Inside each 16-lane row
+// by DPP shifts of 1, 2, 4 and 8; then, row by row, a lane whose segment began in an
+// earlier row adds the final value of the previous row's last lane. The order of the
+// additions depends only on the segments, so the sums are reproducible.
+__device__ __forceinline__ double wseg_sum(double c, int seg) {
+    const int lane = threadIdx.x & 63;
+    const int lim = max(seg, lane & ~15);
+    double t;
+    t = dpp_row_shr<1>(c);
+    if (lane - 1 >= lim) c += t;
+    t = dpp_row_shr<2>(c);
+    if (lane - 2 >= lim) c += t;
+    t = dpp_row_shr<4>(c);
+    if (lane - 4 >= lim) c += t;
+    t = dpp_row_shr<8>(c);
+    if (lane - 8 >= lim) c += t;
+#pragma unroll
+    for (int rr = 1; rr < 4; ++rr) {
+        const double carry = readlane_f64(c, 16 * rr - 1);
+        if ((lane >> 4) == rr && seg < 16 * rr) c += carry;
+    }
+    return c;
+}
+
 __device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o, 64);
@@ -59,7 +128,7 @@ __device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
 // wave, whose LDS accesses complete in order.
 constexpr int WQ = 128;
 template <int T, int SCAN, int BLK, class Sel, class Body>
-__device__ __forceinline__ void for_selected(int32_t n, int32_t* __restrict__ wq, Sel&& sel, Body&& body) {
+__device__ __forceinline__ void for_selected(int32_t n, int32_t* wq, Sel&& sel, Body&& body) {
     constexpr int NW = T / 64;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -105,7 +174,7 @@ __device__ __forceinline__ void for_selected(int32_t n, int32_t* __restrict__ wq
 // over the lanes and its bit by a search over the word's bit counts, so no lane loops
 // over the bits of a dense word while the others wait.
 template <int T, class Keep, class Body>
-__device__ __forceinline__ void for_bucket(uint32_t* __restrict__ row, int32_t W, int32_t* __restrict__ wq,
+__device__ __forceinline__ void for_bucket(uint32_t* __restrict__ row, int32_t W, int32_t* wq,
                                            Keep&& keep, Body&& body) {
     constexpr int NW = T / 64;
     const int lane = threadIdx.x & 63;
@@ -173,8 +242,14 @@ __device__ __forceinline__ void for_bucket(uint32_t* __restrict__ row, int32_t W
 // e = the arc, ok = false past the last arc; incl/excl are the calling lane's own
 // inclusive/exclusive arc offsets (its slot's range [excl, incl)). All lanes stay
 // converged, so f may use cross-lane operations before it branches on ok.
+// The owner of arc p is the last slot with arcs whose range starts at or before p:
+// each slot with arcs starting in the round writes its index at that position of the
+// 64-entry LDS scratch own (position 0 holds the previous round's last owner), and a
+// max-scan over the lanes fills the gaps. own is free while f runs. It is the first
+// half of the wave's queue, which the caller has read into q already: own must not be
+// declared restrict, or that read may be moved past the writes here.
 template <class P, class F>
-__device__ __forceinline__ void for_queue_arcs(P rp, int32_t lo, int32_t q, bool valid, F&& f) {
+__device__ __forceinline__ void for_queue_arcs(P rp, int32_t lo, int32_t q, bool valid, int32_t* own, F&& f) {
     const int lane = threadIdx.x & 63;
     int64_t e0 = 0;
     int deg = 0;
@@ -182,22 +257,20 @@ __device__ __forceinline__ void for_queue_arcs(P rp, int32_t lo, int32_t q, bool
         e0 = rp[lo + q];
         deg = (int)(rp[lo + q + 1] - e0);
     }
-    int incl = deg;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += t;
-    }
-    const int total = __shfl(incl, 63, 64);
+    const int incl = wscan_add(deg);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
     const int excl = incl - deg;
     const int e0lo = (int)(uint32_t)(uint64_t)e0, e0hi = (int)(uint32_t)((uint64_t)e0 >> 32);
+    int carry = -1;
     for (int r = 0; r < total; r += 64) {
+        own[lane] = -1;
+        if (deg > 0 && excl >= r && excl < r + 64) own[excl - r] = lane;
+        __builtin_amdgcn_wave_barrier();  // other lanes' writes before the read
+        int o = own[lane];
+        if (lane == 0) o = max(o, carry);
+        const int i = wscan_max(o);
+        carry = __builtin_amdgcn_readlane(i, 63);
         const int p = r + lane;
-        // owner = number of slots whose arcs end at or before p (at most 63)
-        int i = 0;
-#pragma unroll
-        for (int st = 32; st > 0; st >>= 1)
-            if (__shfl(incl, i + st - 1, 64) <= p) i += st;
         const int ex = __shfl(excl, i, 64);
         const uint64_t base = ((uint64_t)(uint32_t)__shfl(e0hi, i, 64) << 32) | (uint32_t)__shfl(e0lo, i, 64);
         f(i, (int64_t)base + (p - ex), p < total, incl, excl, r);
@@ -278,7 +351,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     const RCtx& C = ctxs[R.ctx];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    int32_t* __restrict__ wq = wqueue[tid >> 6];
+    int32_t* wq = wqueue[tid >> 6];  // also the arc rounds' owner scratch: not restrict
     const int32_t lo = R.lo;
     const int32_t n = R.hi - R.lo;
     uint32_t* __restrict__ dist = GLOBAL ? R.gdist : reinterpret_cast<uint32_t*>(lds);
@@ -377,7 +450,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         if (valid) rnodes[wcur + lane] = q;
                         wcur += (int32_t)__popcll(__ballot(valid));
                     }
-                    for_queue_arcs(rp, lo, q, valid, [&](int owner, int64_t e, bool ok, int, int, int) {
+                    for_queue_arcs(rp, lo, q, valid, wq, [&](int owner, int64_t e, bool ok, int, int, int) {
                         const int32_t v = __shfl(q, owner, 64);
                         if (!ok) return;
                         if (prof) bytes += 12ull;
@@ -536,7 +609,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         prev = cacc[q];
                         ind = (nflag && (nflag[lo + q] & NF_TARGET)) ? 1.0 : 0.0;
                     }
-                    for_queue_arcs(rp, lo, q, valid, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
+                    for_queue_arcs(rp, lo, q, valid, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
                         // segment of this lane's arc: lanes from its node's first arc in
                         // this round
                         const int seg = max(__shfl(excl, owner, 64) - r, 0);
@@ -552,11 +625,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                             }
                         }
                         // per-node sums of the round: segmented inclusive scan
-#pragma unroll
-                        for (int o = 1; o < 64; o <<= 1) {
-                            const double t = __shfl_up(c, o, 64);
-                            if (lane - o >= seg) c += t;
-                        }
+                        c = wseg_sum(c, seg);
                         // each slot takes the sum at the last lane of its arcs in the round
                         const int a = max(excl - r, 0), b = min(incl - r, 64);
                         const double part = __shfl(c, max(b - 1, 0), 64);
