@@ -23,48 +23,85 @@ namespace bcpp {
 
 // Clique arcs out of each source f: one per frontier q != f of its part with
 // sigma(f,q) > 0 (zero-multiplicity pairs carry no shortest path and are dropped).
-// Thread = (group, lane); the lanes of a wave read one state row together.
-__global__ void k_clique_count(const GroupDesc* __restrict__ desc, const DskInfo* __restrict__ info,
-                               int32_t ngroups, int32_t* __restrict__ cdeg) {
-    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (g >= ngroups) return;
+// One workgroup of 256 threads per Dijkstra_SK group, whose states are rows
+// [frontier j][64 source lanes]: the four waves split the rows, each lane counting for
+// its source, and the per-wave counts are summed in LDS.
+__global__ void __launch_bounds__(256) k_clique_count(const GroupDesc* __restrict__ desc,
+                                                      const DskInfo* __restrict__ info, int32_t ngroups,
+                                                      int32_t* __restrict__ cdeg) {
+    __shared__ int32_t part[4][64];
+    const int g = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const DskInfo I = info[g];
-    if (lane >= I.nsrc) return;
-    const uint64_t* sig = desc[g].sigma;
+    const uint64_t* __restrict__ sig = desc[g].sigma;
     const int32_t own = I.fl0 + lane;
     int32_t cnt = 0;
-    for (int32_t j = 0; j < I.nf; ++j)
-        cnt += (j != own && sig[(int64_t)j * 64 + lane] != 0) ? 1 : 0;
-    cdeg[I.sk_base + own] = cnt;
+    if (lane < I.nsrc)
+        for (int32_t j = wave; j < I.nf; j += 4) cnt += (j != own && sig[(int64_t)j * 64 + lane] != 0) ? 1 : 0;
+    part[wave][lane] = cnt;
+    __syncthreads();
+    if (wave == 0 && lane < I.nsrc) cdeg[I.sk_base + own] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
 }
 
-__global__ void k_clique_fill(const GroupDesc* __restrict__ desc, const DskInfo* __restrict__ info,
-                              int32_t ngroups, const int64_t* __restrict__ row_ptr,
-                              const int32_t* __restrict__ rdeg, int32_t* __restrict__ col,
-                              uint32_t* __restrict__ len, uint64_t* __restrict__ mult,
-                              uint32_t* __restrict__ maxlen) {
-    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (g >= ngroups) return;
+// The arcs themselves, in increasing frontier order after the row's cut arcs. The
+// workgroup stages 64 rows of sigma and d at a time in LDS (rows padded to 65 entries
+// so that reading one source's column is free of bank conflicts); then each wave takes
+// one source's column at a time, keeps the non-zero entries with a ballot and writes
+// them to that source's row with consecutive lanes at consecutive positions.
+__global__ void __launch_bounds__(256) k_clique_fill(const GroupDesc* __restrict__ desc,
+                                                     const DskInfo* __restrict__ info, int32_t ngroups,
+                                                     const int64_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ rdeg, int32_t* __restrict__ col,
+                                                     uint32_t* __restrict__ len, uint64_t* __restrict__ mult,
+                                                     uint32_t* __restrict__ maxlen) {
+    __shared__ uint64_t ts[64][65];
+    __shared__ uint32_t td[64][65];
+    __shared__ int64_t pos[64];
+    __shared__ uint32_t bmax;
+    const int g = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const DskInfo I = info[g];
-    if (lane >= I.nsrc) return;
     const GroupDesc& G = desc[g];
-    const int32_t own = I.fl0 + lane;
-    const int32_t f = I.sk_base + own;
-    int64_t pos = row_ptr[f] + rdeg[f];
-    uint32_t mx = 0;
-    for (int32_t j = 0; j < I.nf; ++j) {
-        const uint64_t s = G.sigma[(int64_t)j * 64 + lane];
-        if (j == own || s == 0) continue;
-        const uint32_t d = G.dist[(int64_t)j * 64 + lane];
-        col[pos] = I.sk_base + j;
-        len[pos] = d;
-        mult[pos] = s;
-        mx = max(mx, d);
-        ++pos;
+    if (wave == 0 && lane < I.nsrc) {
+        const int32_t f = I.sk_base + I.fl0 + lane;
+        pos[lane] = row_ptr[f] + rdeg[f];
     }
-    if (mx) atomicMax(maxlen, mx);
+    if (threadIdx.x == 0) bmax = 0u;
+    uint32_t mx = 0;
+    for (int32_t j0 = 0; j0 < I.nf; j0 += 64) {
+        __syncthreads();  // pos and bmax set; the previous tile fully read
+        for (int r = wave; r < 64; r += 4) {
+            const int32_t j = j0 + r;
+            uint64_t sv = 0;
+            uint32_t dv = 0;
+            if (j < I.nf && lane < I.nsrc) {
+                sv = G.sigma[(int64_t)j * 64 + lane];
+                dv = G.dist[(int64_t)j * 64 + lane];
+            }
+            ts[r][lane] = sv;
+            td[r][lane] = dv;
+        }
+        __syncthreads();
+        for (int32_t src = wave; src < I.nsrc; src += 4) {
+            const int32_t j = j0 + lane;
+            const uint64_t sv = ts[lane][src];
+            const bool keep = j < I.nf && j != I.fl0 + src && sv != 0;
+            const unsigned long long m = __ballot(keep);
+            if (keep) {
+                const int64_t at = pos[src] + __popcll(m & ((1ull << lane) - 1ull));
+                const uint32_t d = td[lane][src];
+                col[at] = I.sk_base + j;
+                len[at] = d;
+                mult[at] = sv;
+                mx = max(mx, d);
+            }
+            if (lane == 0) pos[src] += __popcll(m);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    if (lane == 0 && mx) atomicMax(&bmax, mx);
+    __syncthreads();
+    if (threadIdx.x == 0 && bmax) atomicMax(maxlen, bmax);
 }
 
 // Cut arcs R with tuple <w(e), 1>, placed first in each skeleton row.
@@ -687,7 +724,7 @@ int SkBuild::issue_count(hipStream_t s) const {
     const int32_t ng = (int32_t)groups.size();
     if (ng > 0) {
         KTimer kt(BC_K_OTHER, s);
-        hipLaunchKernelGGL(k_clique_count, dim3((ng + 3) / 4), dim3(256), 0, s, d_desc, d_info, ng, d_cdeg);
+        hipLaunchKernelGGL(k_clique_count, dim3(ng), dim3(256), 0, s, d_desc, d_info, ng, d_cdeg);
         if (nint)
             hipLaunchKernelGGL(k_table, dim3((nint + 3) / 4), dim3(256), 0, s, d_desc, d_info, nint, d_il,
                                d_ig0, d_ing, d_tdeg, nullptr, nullptr, nullptr, nullptr);
@@ -713,7 +750,7 @@ int SkBuild::issue_fill(hipStream_t s, const bc_skeleton* sk) const {
             hipLaunchKernelGGL(k_fill_r, dim3((nsk + 255) / 256), dim3(256), 0, s, nsk, d_rptr, d_rcol, d_rw,
                                sk->d_row_ptr, sk->d_col, sk->d_len, sk->d_mult);
         if (ng) {
-            hipLaunchKernelGGL(k_clique_fill, dim3((ng + 3) / 4), dim3(256), 0, s, d_desc, d_info, ng,
+            hipLaunchKernelGGL(k_clique_fill, dim3(ng), dim3(256), 0, s, d_desc, d_info, ng,
                                sk->d_row_ptr, d_rdeg, sk->d_col, sk->d_len, sk->d_mult, d_maxlen);
             if (nint)
                 hipLaunchKernelGGL(k_table, dim3((nint + 3) / 4), dim3(256), 0, s, d_desc, d_info, nint, d_il,
