@@ -318,23 +318,6 @@ __device__ __forceinline__ GAS T* gas(T* p) {
     return (GAS T*)p;
 }
 
-// State accessors. With the state in device memory (GLOBAL) the distances and counts
-// change through L2 atomics, so every read goes past the CU's L1 (agent-scope atomic
-// load) and never sees a stale line.
-template <bool GLOBAL>
-__device__ __forceinline__ uint32_t ld_d(uint32_t* p) {
-    if constexpr (GLOBAL)
-        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-        return *p;
-}
-template <bool GLOBAL>
-__device__ __forceinline__ uint64_t ld_s(uint64_t* p) {
-    if constexpr (GLOBAL)
-        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-        return *p;
-}
 
 template <int T, bool GLOBAL>
 __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
@@ -354,11 +337,49 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     int32_t* wq = wqueue[tid >> 6];  // also the arc rounds' owner scratch: not restrict
     const int32_t lo = R.lo;
     const int32_t n = R.hi - R.lo;
-    uint32_t* __restrict__ dist = GLOBAL ? R.gdist : reinterpret_cast<uint32_t*>(lds);
-    uint64_t* __restrict__ sig =
-        GLOBAL ? R.gsig : reinterpret_cast<uint64_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15));
-    auto D_ = [&](int32_t i) { return ld_d<GLOBAL>(&dist[i]); };
-    auto S_ = [&](int32_t i) { return ld_s<GLOBAL>(&sig[i]); };
+    // One source's state: in LDS, or (GLOBAL) in device memory, changed through L2
+    // atomics and read past the CU's L1 (agent-scope atomic loads), always through
+    // global-address-space pointers
+    uint32_t* __restrict__ dist = reinterpret_cast<uint32_t*>(lds);
+    uint64_t* __restrict__ sig = reinterpret_cast<uint64_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15));
+    GAS uint32_t* __restrict__ gdist = gas(R.gdist);
+    GAS uint64_t* __restrict__ gsig = gas(R.gsig);
+    auto D_ = [&](int32_t i) -> uint32_t {
+        if constexpr (GLOBAL)
+            return __hip_atomic_load(gdist + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return dist[i];
+    };
+    auto S_ = [&](int32_t i) -> uint64_t {
+        if constexpr (GLOBAL)
+            return __hip_atomic_load(gsig + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return sig[i];
+    };
+    auto setD = [&](int32_t i, uint32_t v) {
+        if constexpr (GLOBAL)
+            gdist[i] = v;
+        else
+            dist[i] = v;
+    };
+    auto setS = [&](int32_t i, uint64_t v) {
+        if constexpr (GLOBAL)
+            gsig[i] = v;
+        else
+            sig[i] = v;
+    };
+    auto minD = [&](int32_t i, uint32_t v) -> uint32_t {
+        if constexpr (GLOBAL)
+            return __hip_atomic_fetch_min(gdist + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return atomicMin(&dist[i], v);
+    };
+    auto addS = [&](int32_t i, uint64_t v) -> uint64_t {
+        if constexpr (GLOBAL)
+            return __hip_atomic_fetch_add(gsig + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return atomicAdd((unsigned long long*)&sig[i], (unsigned long long)v);
+    };
     // device-memory arrays, read and written as global memory (see gas)
     const GAS int64_t* __restrict__ rp = gas(C.g.row_ptr);
     const GAS int32_t* __restrict__ col = gas(C.g.col);
@@ -418,8 +439,8 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     for (int b = 0; b < R.nsrc; ++b) {
         const int32_t s = srcs[R.src_off + b] - lo;
         for (int32_t v = tid; v < n; v += T) {
-            dist[v] = (v == s) ? 0u : INF32;
-            sig[v] = (v == s) ? 1ull : 0ull;
+            setD(v, (v == s) ? 0u : INF32);
+            setS(v, (v == s) ? 1ull : 0ull);
         }
         if (tid == 0) fwd_next[0] = fwd_next[1] = fwd_next[2] = INF32;
         if (bucket) {
@@ -472,7 +493,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                     x *= m;
                                 }
                                 if (x) {
-                                    const uint64_t old = atomicAdd((unsigned long long*)&sig[v], (unsigned long long)x);
+                                    const uint64_t old = addS(v, x);
                                     if (old + x < old) ovf = true;
                                 }
                             }
@@ -482,7 +503,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         if (nv < D_(u)) {
                             if (bucket) {
                                 // a bit per successful offer (a failed one leaves none)
-                                const uint32_t old = atomicMin(&dist[u], nv);
+                                const uint32_t old = minD(u, nv);
                                 if (nv < old) {
                                     const uint32_t bit = 1u << (u & 31);
                                     const uint32_t ow = atomicOr(&bm[(size_t)(nv & RM) * W + (u >> 5)], bit);
@@ -492,7 +513,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                 // the smallest offer to a node always lands, so the least
                                 // offer made is the least new tentative distance, and no
                                 // offer has to wait for the atomic's old value
-                                atomicMin(&dist[u], nv);
+                                minD(u, nv);
                                 mn = min(mn, nv);
                             }
                         }
@@ -635,7 +656,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         const double sv = (double)S_(q);
                         const double dl = sv * acc;
                         cacc[q] = prev + dl;
-                        sig[q] = (uint64_t)__double_as_longlong((ind + dl) / sv);
+                        setS(q, (uint64_t)__double_as_longlong((ind + dl) / sv));
                     }
                 };
             if (seg >= 0 && rsegk[seg] == k) {
