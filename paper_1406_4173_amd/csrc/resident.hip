@@ -127,6 +127,11 @@ __device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
 // on what body does to other nodes in the same step. The queue is private to the
 // wave, whose LDS accesses complete in order.
 constexpr int WQ = 128;
+// Arrays of a wave's forward record: queued nodes, step numbers, step ends, and, with
+// the state in device memory, each queued node's first arc (two halves) and degree, so
+// that the backward reads a node's arcs without an L2 trip through the row pointers.
+// (For LDS-state groups, mostly small, the extra stores cost more than they save.)
+__host__ __device__ constexpr int rec_arrays(bool global_state) { return global_state ? 6 : 3; }
 template <int T, int SCAN, int BLK, class Sel, class Body>
 __device__ __forceinline__ void for_selected(int32_t n, int32_t* wq, Sel&& sel, Body&& body) {
     constexpr int NW = T / 64;
@@ -248,15 +253,10 @@ __device__ __forceinline__ void for_bucket(uint32_t* __restrict__ row, int32_t W
 // max-scan over the lanes fills the gaps. own is free while f runs. It is the first
 // half of the wave's queue, which the caller has read into q already: own must not be
 // declared restrict, or that read may be moved past the writes here.
-template <class P, class F>
-__device__ __forceinline__ void for_queue_arcs(P rp, int32_t lo, int32_t q, bool valid, int32_t* own, F&& f) {
+// The calling lane's slot holds the arcs [e0, e0 + deg) (deg = 0 for an empty slot).
+template <class F>
+__device__ __forceinline__ void for_queue_arcs(int64_t e0, int deg, int32_t* own, F&& f) {
     const int lane = threadIdx.x & 63;
-    int64_t e0 = 0;
-    int deg = 0;
-    if (valid) {
-        e0 = rp[lo + q];
-        deg = (int)(rp[lo + q + 1] - e0);
-    }
     const int incl = wscan_add(deg);
     const int total = __builtin_amdgcn_readlane(incl, 63);
     const int excl = incl - deg;
@@ -426,9 +426,14 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     // this wave's record region (backward groups): nodes, then step numbers, then ends;
     // a wave queues only nodes of its own blocks (at most 64 * ceil(n / T) of them)
     const int32_t wcap = 64 * ((n + T - 1) / T);
-    GAS int32_t* __restrict__ rnodes = bwd ? gas(R.rlist) + (int64_t)(tid >> 6) * 3 * wcap : nullptr;
+    // (and with GLOBAL each queued node's first arc, split in halves, and its degree)
+    constexpr bool REC_ARCS = GLOBAL;
+    GAS int32_t* __restrict__ rnodes = bwd ? gas(R.rlist) + (int64_t)(tid >> 6) * rec_arrays(GLOBAL) * wcap : nullptr;
     GAS int32_t* __restrict__ rsegk = bwd ? rnodes + wcap : nullptr;
     GAS int32_t* __restrict__ rsege = bwd ? rnodes + 2 * wcap : nullptr;
+    GAS int32_t* __restrict__ re0lo = bwd && REC_ARCS ? rnodes + 3 * wcap : nullptr;
+    GAS int32_t* __restrict__ re0hi = bwd && REC_ARCS ? rnodes + 4 * wcap : nullptr;
+    GAS int32_t* __restrict__ rdeg = bwd && REC_ARCS ? rnodes + 5 * wcap : nullptr;
     if (bwd)
         for (int32_t v = tid; v < n; v += T) cacc[v] = 0.0;
     if (cent)
@@ -467,21 +472,37 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             auto fbody =
                 [&](int32_t q, bool valid) {
                     if (prof && valid) bytes += 12ull;
+                    int64_t e0 = 0;
+                    int deg = 0;
+                    if (valid) {
+                        e0 = rp[lo + q];
+                        deg = (int)(rp[lo + q + 1] - e0);
+                    }
                     if (bwd) {
-                        if (valid) rnodes[wcur + lane] = q;
+                        if (valid) {
+                            rnodes[wcur + lane] = q;
+                            if constexpr (REC_ARCS) {
+                                re0lo[wcur + lane] = (int32_t)(uint32_t)(uint64_t)e0;
+                                re0hi[wcur + lane] = (int32_t)(uint32_t)((uint64_t)e0 >> 32);
+                                rdeg[wcur + lane] = deg;
+                            }
+                        }
                         wcur += (int32_t)__popcll(__ballot(valid));
                     }
-                    for_queue_arcs(rp, lo, q, valid, wq, [&](int owner, int64_t e, bool ok, int, int, int) {
+                    for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int, int, int) {
                         const int32_t v = __shfl(q, owner, 64);
                         if (!ok) return;
                         if (prof) bytes += 12ull;
                         const int32_t u = col[e] - lo;
                         const uint32_t L = len ? len[e] : 1u;
+                        // one read of u's distance serves both tests below: if another
+                        // lane lowers it meanwhile, the offer test passes at worst for an
+                        // offer that then changes nothing
+                        const uint32_t du = D_(u);
                         // u is a parent of v if it settled at D - L in an earlier step (eq.
                         // parentsall / eq. multiparents); the count adds in with an atomic,
                         // exact for integers, and a wrap of any addition is an overflow
                         if (v != s && L <= D) {
-                            const uint32_t du = D_(u);
                             // Dijkstra_SK (eq. frontierparents): a frontier parent other
                             // than the source is tight but adds no paths
                             if (du != INF32 && du + L == D &&
@@ -500,7 +521,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         }
                         // offers: all above D, so they never meet the parent test above
                         const uint32_t nv = D + L;
-                        if (nv < D_(u)) {
+                        if (nv < du) {
                             if (bucket) {
                                 // a bit per successful offer (a failed one leaves none)
                                 const uint32_t old = minD(u, nv);
@@ -623,14 +644,14 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         int32_t seg = wseg - 1;
         for (int k = nsteps - 1; k >= 1; --k) {
             D = steps[k];
-            auto body = [&](int32_t q, bool valid) {
+            auto body = [&](int32_t q, int64_t e0, int deg, bool valid) {
                     double prev = 0.0, ind = 0.0, acc = 0.0;
                     if (prof && valid) bytes += 8ull;
                     if (valid) {
                         prev = cacc[q];
                         ind = (nflag && (nflag[lo + q] & NF_TARGET)) ? 1.0 : 0.0;
                     }
-                    for_queue_arcs(rp, lo, q, valid, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
+                    for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
                         // segment of this lane's arc: lanes from its node's first arc in
                         // this round
                         const int seg = max(__shfl(excl, owner, 64) - r, 0);
@@ -663,7 +684,19 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                 const int32_t beg = seg > 0 ? rsege[seg - 1] : 0, end = rsege[seg];
                 for (int32_t c = beg; c < end; c += 64) {
                     const bool valid = c + lane < end;
-                    body(valid ? rnodes[c + lane] : 0, valid);
+                    int32_t q = 0, d = 0;
+                    int64_t e0 = 0;
+                    if (valid) {
+                        q = rnodes[c + lane];
+                        if constexpr (REC_ARCS) {
+                            e0 = (int64_t)(((uint64_t)(uint32_t)re0hi[c + lane] << 32) | (uint32_t)re0lo[c + lane]);
+                            d = rdeg[c + lane];
+                        } else {
+                            e0 = rp[lo + q];
+                            d = (int)(rp[lo + q + 1] - e0);
+                        }
+                    }
+                    body(q, e0, d, valid);
                 }
                 --seg;
             }
@@ -781,8 +814,11 @@ int32_t resident_sources_per_group(int64_t nsrc) {
     return (int32_t)std::min<int64_t>(LANES, std::max<int64_t>(1, (nsrc + div - 1) / div));
 }
 
-// Ints of a backward group's forward record: 3 * T * ceil(range / T) for any T <= 1024.
-size_t record_ints(int64_t range) { return 3 * ((size_t)range + 1024) + 64; }
+// Ints of a backward group's forward record: rec_arrays * T * ceil(range / T) for any
+// T <= 1024 (the state is in device memory exactly when the range exceeds LDS).
+size_t record_ints(int64_t range) {
+    return (size_t)rec_arrays(range > resident_max_range()) * ((size_t)range + 1024) + 64;
+}
 
 bool resident_takes(int64_t range) {
     const char* e = getenv("BCPP_RESIDENT");
