@@ -545,13 +545,13 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                 // on a count that stale bits inflate by a racy amount) changes no result
                 uint32_t* row = bm + (size_t)(D & RM) * W;
                 if (bc[cidx(D)] > (uint32_t)R.dense) {
-                    for_selected<T, GLOBAL ? 8 : 4, OWN_BLK>(n, wq, [&](int32_t v) { return D_(v) == D; }, fbody);
+                    for_selected<T, GLOBAL ? 8 : 2, OWN_BLK>(n, wq, [&](int32_t v) { return D_(v) == D; }, fbody);
                     for (int32_t i = tid; i < W; i += T) row[i] = 0u;
                 } else {
                     for_bucket<T>(row, W, wq, [&](int32_t v) { return D_(v) == D; }, fbody);
                 }
             } else {
-                for_selected<T, GLOBAL ? 8 : 4, OWN_BLK>(
+                for_selected<T, GLOBAL ? 8 : 2, OWN_BLK>(
                     n, wq,
                     [&](int32_t v) {
                         const uint32_t dv = D_(v);
