@@ -288,11 +288,12 @@ class Batch:
                                      ctypes.byref(h)))
         self.h = h
 
-    def run(self, pp: bool = True, engine_only: bool = False, graph: bool = True):
-        """graph=False runs the pass eagerly instead of replaying its captured graph."""
+    def run(self, pp: bool = True, engine_only: bool = False, graph: bool = True, ordered: bool = False):
+        """graph=False runs the pass eagerly instead of replaying its captured graph;
+        ordered=True returns the ordered-pair sums (twice the default)."""
         outs = [np.empty(n, np.float64) for n in self.ns]
         ptrs = (ctypes.c_void_p * len(outs))(*[o.ctypes.data for o in outs])
-        fl = ((BC_BATCH_PP if pp else BC_BATCH_PLAIN) | (BC_ENGINE_ONLY if engine_only else 0) |
+        fl = ((BC_BATCH_PP if pp else BC_BATCH_PLAIN) | _flags(ordered, engine_only) |
               (0 if graph else BC_NO_GRAPH))
         _check(lib().bc_batch_run(self.h, fl, ctypes.cast(ptrs, _P)))
         return outs

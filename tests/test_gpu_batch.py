@@ -125,3 +125,17 @@ def test_batch_pp_graph_replays_match_eager(bcpp):
             assert np.array_equal(a, b)
         bcpp.brandes_pp(Go, bcpp.partition_sk(Go, other.part, other.k, other.S[: 40 + rep]))
         B.run(pp=False)
+
+
+@pytest.mark.parametrize("graph", [True, False], ids=["replay", "eager"])
+def test_batch_ordered_is_twice_unordered(bcpp, graph):
+    # BC_ORDERED gives the ordered-pair sums, exactly twice the unordered scores, for
+    # both passes (scaling by 2 is exact in fp64)
+    gs = inputs.batch_256(10)
+    B = bcpp.Batch(gs)
+    for pp in (False, True):
+        a = B.run(pp=pp, graph=graph)
+        b = B.run(pp=pp, graph=graph, ordered=True)
+        for x, y, g in zip(a, b, gs):
+            assert np.array_equal(y, 2.0 * x)
+            assert_scores(y, oracle.bc(g, g.S, True))
