@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sbm_10k",
-                    choices=["planted_1k", "sbm_10k", "pareto_100k", "smallcut_100k", "batch_256",
+                    choices=["planted_1k", "sbm_10k", "pareto_100k", "smallcut_100k", "batch_256", "p1_sweep",
                              "serve_64"])
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="measured window of the serving workload (after a 2 s warm-up)")
@@ -89,8 +89,12 @@ def timed(fn, steps, warmup, sync):
 
 
 def cpu_baseline(g, budget_s):
-    """The oracle as it stands (single-threaded target-set Brandes) on the first sources
-    of S, sized to roughly `budget_s` seconds; returns TEPS over the sample."""
+    """The oracle as it stands, on the first sources of S, timed on the host: half the
+    budget single-threaded, half on all host threads (up to 16), each thread one oracle
+    call on a contiguous chunk of the sample (the C oracle keeps no global state and
+    releases the GIL). TEPS over each sample; value is the all-threads rate."""
+    import concurrent.futures as cf
+
     import numpy as np
 
     import oracle
@@ -101,17 +105,27 @@ def cpu_baseline(g, budget_s):
     t0 = time.perf_counter()
     oracle.bc(g, probe, L=L)
     per_src = max((time.perf_counter() - t0) / probe.size, 1e-6)
-    ns = int(max(2, min(S.size, budget_s / per_src)))
-    sample = S[:ns]
+    ns1 = int(max(2, min(S.size, 0.5 * budget_s / per_src)))
     t0 = time.perf_counter()
-    oracle.bc(g, sample, L=L)
-    dt = time.perf_counter() - t0
+    oracle.bc(g, S[:ns1], L=L)
+    dt1 = time.perf_counter() - t0
+    v1 = ns1 * g.m / dt1
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(16, avail, S.size // 2))
+    nsp = int(max(2 * cores, min(S.size, 0.5 * budget_s / per_src * cores)))
+    chunks = np.array_split(S[:nsp], cores)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        list(ex.map(lambda c: oracle.bc(g, c, L=L), chunks))
+    dtp = time.perf_counter() - t0
     return {
-        "value": ns * g.m / dt,
+        "value": nsp * g.m / dtp,
         "unit": "TEPS",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"first {ns} of {S.size} targets of the same graph ({dt:.1f} s, single thread)",
+        "value_1core": v1,
+        "sample": (f"{cores} host threads on the first {nsp} of {S.size} targets of the same graph, "
+                   f"a contiguous chunk each ({dtp:.1f} s); one thread on the first {ns1} ({dt1:.1f} s)"),
     }
 
 
@@ -174,6 +188,57 @@ def bench_batch(args):
         "eager_ms_per_step": t_eager * 1e3,
         "plain": {"value": units / t_plain, "unit": "TEPS", "ms_per_step": t_plain * 1e3},
         "pp_over_plain": t_plain / t_pp,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def bench_p1_sweep(args):
+    """Small-cut sweep (100,000 nodes in 5,000 communities of 20, mean degree 8, weights
+    1..4, |S| = 200) over the fraction of intra-community edges: per fraction, Brandes++
+    (partition included) and plain Brandes timed the same way as the single-graph
+    workloads, and the skeleton's size. The smaller the cut, the smaller the skeleton
+    and the larger Brandes++'s lead. value = Brandes++ TEPS at the smallest cut."""
+    import numpy as np
+    import torch
+
+    from paper_1406_4173_amd import bcpp, inputs
+
+    dev = torch.device("cuda:0")
+    sync = torch.cuda.synchronize
+    rows = []
+    for f in inputs.P1_INTRA:
+        g = inputs.p1_graph(f)
+        G = bcpp.Graph(g, stream=torch.cuda.current_stream(dev))
+        S_dev = torch.tensor(g.S, dtype=torch.int32, device=dev)
+        out = torch.empty(g.n, dtype=torch.float64, device=dev)
+        part = np.ascontiguousarray(g.part, np.int32)
+        S_host = np.ascontiguousarray(g.S, np.int32)
+        state = {}
+
+        def pp_step():
+            sk = bcpp.partition_sk(G, part, g.k, S_host)
+            bcpp.brandes_pp_dev(G, sk, out)
+            state["sk"] = sk
+
+        t_pp = timed(pp_step, args.steps, args.warmup, sync)
+        t_plain = timed(lambda: bcpp.brandes_plain_dev(G, S_dev, out), args.steps, args.warmup, sync)
+        st = state["sk"].stats()
+        units = float(len(g.S) * g.m)
+        rows.append({"intra": f, "m": int(g.m), "pp_ms": t_pp * 1e3, "plain_ms": t_plain * 1e3,
+                     "pp_teps": units / t_pp, "plain_teps": units / t_plain, "pp_over_plain": t_plain / t_pp,
+                     "skeleton_nodes": st["n_sk"], "skeleton_arcs": st["r_arcs"] + st["clique_arcs"],
+                     "table_nnz": st["table_nnz"]})
+        print(f"p1 intra {f}: Brandes++ {t_pp*1e3:.2f} ms, plain {t_plain*1e3:.2f} ms", file=sys.stderr,
+              flush=True)
+    last = rows[-1]
+    res = {
+        "metric": "exact-BC TEPS (|S|*m/s), Brandes++ vs plain Brandes over a small-cut sweep, 1 GPU",
+        "value": last["pp_teps"], "unit": "TEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": last["pp_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32/u64/f64", "data": "synthetic",
+        "config": {"workload": "p1_sweep", "n": 100000, "communities": 5000, "targets": 200,
+                   "intra": list(inputs.P1_INTRA)},
+        "sweep": rows,
     }
     print(json.dumps(res), flush=True)
 
@@ -251,15 +316,17 @@ def bench_serve(args):
 
 def main():
     args = parse()
-    if args.workload == "batch_256":
-        return bench_batch(args)
-    if args.workload == "serve_64":
-        return bench_serve(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards "
               "by source batches across GPUs by design but only the one-GPU kernel is built",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch_256":
+        return bench_batch(args)
+    if args.workload == "serve_64":
+        return bench_serve(args)
+    if args.workload == "p1_sweep":
+        return bench_p1_sweep(args)
     import numpy as np
     import torch
 

@@ -267,6 +267,19 @@ def smallcut_100k() -> Graph:
     return g
 
 
+P1_INTRA = (0.9, 0.97, 0.99, 0.995, 0.998)
+
+
+def p1_graph(intra: float) -> Graph:
+    """Small-cut sweep: 100,000 nodes in 5,000 communities of 20, mean degree 8 with a
+    fraction `intra` of the edges inside a community, weights uniform in {1..4},
+    |S| = 200. The fraction sets the cut size, and with it how small the skeleton is."""
+    rng = rng_for(SEED_BASE + 6, int(round(intra * 1000)))
+    g = _community_graph(rng, 100000, 5000, 8.0, intra, 4, f"p1_{intra}")
+    g.S = np.sort(rng.choice(g.n, 200, replace=False)).astype(np.int32)
+    return g
+
+
 def serving_pool(count: int = 64) -> list:
     """64 resident graphs: n log-uniform in [1e3, 5e4], max(4, n/200) equal
     communities, mean degree 8 with 85% of edges inside a community; unit weights for

@@ -211,3 +211,15 @@ def test_pp_bucket_and_scan_steps_agree(bcpp, monkeypatch):
         got[shift] = bcpp.brandes_pp(G, sk)
     assert np.array_equal(got["0"], got["63"])
     assert_scores(got["0"], oracle.bc(g, g.S))
+
+
+@pytest.mark.parametrize("intra", [0.9, 0.998])
+def test_pp_small_cut_sweep_graphs(bcpp, intra):
+    # the two ends of the small-cut sweep (100,000 nodes, communities of 20): a large
+    # skeleton with small tables, and a small skeleton with large tables
+    g = inputs.p1_graph(intra)
+    G = bcpp.Graph(g)
+    sk = bcpp.partition_sk(G, g.part, g.k, g.S)
+    want = oracle.bc(g, g.S)
+    assert_scores(bcpp.brandes_pp(G, sk), want)
+    assert_scores(bcpp.brandes_plain(G, g.S), want)
