@@ -417,11 +417,13 @@ static int admit(bc_server* sv, Query* q) {
 static int admit_prepared(bc_server* sv, Query* q) {
     SkBuild& b = *q->build;
     q->groups = b.groups;
-    bool res = !(q->flags & BC_ENGINE_ONLY) && !q->groups.empty();
+    bool res = !(q->flags & BC_ENGINE_ONLY);
     for (auto& G : q->groups) res = res && resident_takes((int64_t)G.hi - G.lo);
     if (res) {
         // Dijkstra_SK as one resident launch on a side stream; parts larger than LDS
-        // keep their one-source state in the query's block
+        // keep their one-source state in the query's block. A query without
+        // Dijkstra_SK groups launches nothing and goes on to Brandes_SK when polled
+        // (on the engine it would make the loop step the engine for nothing).
         size_t need = b.temp_bytes() + resident_launch_bytes(q->groups.size()) + 8192;
         for (auto& G : q->groups)
             if ((int64_t)G.hi - G.lo > resident_max_range()) need += (size_t)(G.hi - G.lo) * 12 + 512;
