@@ -333,11 +333,17 @@ struct PpGroups {
     int64_t steps = 1;
 };
 
-static void pp_groups(const bc_batch* b, const bc_skeleton* sk, bool allow_res, PpGroups* out) {
+static int pp_groups(const bc_batch* b, const bc_skeleton* sk, bool allow_res, PpGroups* out) {
     const bc_graph* G = b->G;
     const int32_t n = G->n;
-    const auto& oi = sk->h_out_idx;
-    const auto& ow = sk->h_out_which;
+    // per node: skeleton id or table row (the skeleton was assembled on the graph's stream)
+    std::vector<int32_t> oi(n);
+    std::vector<uint8_t> ow(n);
+    if (n) {
+        BC_HIP(hipMemcpyAsync(oi.data(), sk->d_out_idx, (size_t)n * 4, hipMemcpyDeviceToHost, G->stream));
+        BC_HIP(hipMemcpyAsync(ow.data(), sk->d_out_which, n, hipMemcpyDeviceToHost, G->stream));
+        BC_HIP(hipStreamSynchronize(G->stream));
+    }
     PpGroups& Q = *out;
     Q.groups.reserve(b->S_all.size() + (size_t)b->ng);
     Q.resident.reserve(b->S_all.size() + (size_t)b->ng);
@@ -405,6 +411,7 @@ static void pp_groups(const bc_batch* b, const bc_skeleton* sk, bool allow_res, 
             }
         }
     }
+    return BC_OK;
 }
 
 static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
@@ -418,7 +425,7 @@ static int batch_pp(bc_batch* b, uint32_t flags, double* d_out) {
     tr.mark("partition");
     std::unique_ptr<bc_skeleton> sk(skp);
     PpGroups Q;
-    pp_groups(b, sk.get(), !(flags & BC_ENGINE_ONLY), &Q);
+    BC_TRY(pp_groups(b, sk.get(), !(flags & BC_ENGINE_ONLY), &Q));
     Arena& W = G->work;
     const size_t need = mixed_bytes(Q.groups, Q.resident, Q.steps) + (size_t)n * 13 +
                         (size_t)Q.groups.size() * 16 + (1 << 20);
@@ -462,7 +469,7 @@ static int build_pp_plan(bc_batch* b) {
     BC_TRY(rc0);
     if (!P->part.resident && !P->part.b.groups.empty()) return BC_OK;
     PpGroups Q;
-    pp_groups(b, P->sk.get(), true, &Q);
+    BC_TRY(pp_groups(b, P->sk.get(), true, &Q));
     for (uint8_t r : Q.resident)
         if (!r) return BC_OK;
     size_t need = resident_launch_bytes(Q.groups.size()) + 2 * (Q.groups.size() * 8 + 256) + (size_t)n * 21 +

@@ -38,9 +38,6 @@ struct bc_skeleton {
     bc_sk_stats stats{};
     // skeleton targets in skeleton ids (the sources of Brandes_SK), in target order
     std::vector<int32_t> h_src;
-    // per original node: skeleton id (which 0), interior table row (which 1), or -1
-    std::vector<int32_t> h_out_idx;
-    std::vector<uint8_t> h_out_which;
     // device arrays (all in `store`)
     int64_t* d_row_ptr = nullptr;  // [n_sk+1]
     int32_t* d_col = nullptr;      // [m_arcs]

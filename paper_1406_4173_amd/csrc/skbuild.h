@@ -95,6 +95,9 @@ struct SkBuild {
     uint32_t* d_maxlen = nullptr;
     uint32_t* d_rmax = nullptr;
     GroupDesc* d_desc = nullptr;
+    // row lengths (with a trailing zero) and their exclusive scans: the skeleton's
+    // and the interior table's row offsets, copied into the skeleton by the fill
+    int64_t *d_slen = nullptr, *d_srow = nullptr, *d_tlen = nullptr, *d_trow = nullptr;
 
     int prepare(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
                 bool given_singletons);
@@ -107,7 +110,8 @@ struct SkBuild {
                  const std::function<int(size_t, Arena*&)>& get_store);
 
     // Device work only, on stream s: phase 1; phase 2 (sort, CSR, rows, maps); the
-    // clique and table counts; the skeleton fill into sk's arrays.
+    // clique and table counts with the row offsets they give; the skeleton fill
+    // into sk's arrays.
     int issue_phase1(hipStream_t s) const;
     int issue_phase2(hipStream_t s) const;
     int issue_count(hipStream_t s) const;

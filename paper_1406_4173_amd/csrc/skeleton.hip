@@ -104,6 +104,16 @@ __global__ void __launch_bounds__(256) k_clique_fill(const GroupDesc* __restrict
     if (threadIdx.x == 0 && bmax) atomicMax(maxlen, bmax);
 }
 
+// Row lengths of the skeleton (cut arcs, then clique arcs) and of the interior
+// table, each with a trailing zero so that an exclusive scan ends on the total.
+__global__ void k_row_lengths(int32_t nsk, int32_t nint, const int32_t* __restrict__ rdeg,
+                              const int32_t* __restrict__ cdeg, const int32_t* __restrict__ tdeg,
+                              int64_t* __restrict__ slen, int64_t* __restrict__ tlen) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= nsk) slen[i] = i < nsk ? (int64_t)rdeg[i] + cdeg[i] : 0;
+    if (i <= nint) tlen[i] = (i < nint && tdeg) ? (int64_t)tdeg[i] : 0;
+}
+
 // Cut arcs R with tuple <w(e), 1>, placed first in each skeleton row.
 __global__ void k_fill_r(int32_t nsk, const int64_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
                          const uint32_t* __restrict__ rw, const int64_t* __restrict__ row_ptr,
@@ -584,6 +594,8 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
         cub_bytes = std::max(cub_bytes, b);
         BC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, nsk + 1, s));
         cub_bytes = std::max(cub_bytes, b);
+        BC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, nint + 1, s));
+        cub_bytes = std::max(cub_bytes, b);
     }
     tr.mark("groups, interior rows");
     return BC_OK;
@@ -597,7 +609,8 @@ size_t SkBuild::temp_bytes() const {
     need += N * (8 + 8 + 4 + 4 + 4 + 8 + 8 + 1 + 4 + 1) + 16 +  // keys, vals, old, nid, counts, irp, blk, out
             (size_t)n_intra * (weighted ? 8 : 4) + (size_t)nR * 8 + K * (8 + 4 + 8 + 4 + 4 + 1) + 16 +
             ng * (sizeof(DskInfo) + sizeof(GroupDesc)) + I * 20 + (size_t)std::max(nS, 1) * 4 +
-            (size_t)(nlab + 1) * (8 * 2 + 4 * 4) + (size_t)ntiles * 256 * 4 * 2 + cub_bytes + 52 * 256;
+            (size_t)(nlab + 1) * (8 * 2 + 4 * 4) + (size_t)ntiles * 256 * 4 * 2 + cub_bytes +
+            (K + 1) * 16 + (I + 1) * 16 + 56 * 256;
     return need;
 }
 
@@ -687,6 +700,11 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
     d_hoff = W.take<int32_t>((size_t)ntiles * 256);
     d_cub = W.take<unsigned char>(std::max<size_t>(cub_bytes, 1));
     d_desc = W.take<GroupDesc>(std::max(ng, 1));
+    d_slen = W.take<int64_t>(nsk + 1);
+    d_srow = W.take<int64_t>(nsk + 1);
+    d_tlen = W.take<int64_t>(nint + 1);
+    d_trow = W.take<int64_t>(nint + 1);
+    if (!d_slen || !d_srow || !d_tlen || !d_trow) return fail(BC_E_NOMEM, "partition: workspace too small");
     if (!d_keys || !d_keys2 || !d_vals || !d_old || !d_nid || !d_icnt || !d_irp || !d_icol || (weighted && !d_iw) ||
         !d_blk || !d_rcnt || !d_rdeg || !d_rptr || !d_rcol || !d_rw || !d_cdeg || !d_info || !d_il || !d_ig0 ||
         !d_ing || !d_tdeg || !d_inode || !d_out_idx || !d_out_which || !d_nodes || !d_sflag || !d_srcsk ||
@@ -722,12 +740,25 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
 
 int SkBuild::issue_count(hipStream_t s) const {
     const int32_t ng = (int32_t)groups.size();
+    KTimer kt(BC_K_OTHER, s);
     if (ng > 0) {
-        KTimer kt(BC_K_OTHER, s);
         hipLaunchKernelGGL(k_clique_count, dim3(ng), dim3(256), 0, s, d_desc, d_info, ng, d_cdeg);
         if (nint)
             hipLaunchKernelGGL(k_table, dim3((nint + 3) / 4), dim3(256), 0, s, d_desc, d_info, nint, d_il,
                                d_ig0, d_ing, d_tdeg, nullptr, nullptr, nullptr, nullptr);
+    }
+    // without Dijkstra_SK groups no table row has an entry
+    hipLaunchKernelGGL(k_row_lengths, dim3(std::max(nsk, nint) / 256 + 1), dim3(256), 0, s, nsk, nint, d_rdeg,
+                       d_cdeg, ng > 0 ? d_tdeg : nullptr, d_slen, d_tlen);
+    BC_HIP(hipGetLastError());
+    if (n > 0) {
+        size_t cb = cub_bytes;
+        BC_HIP(hipcub::DeviceScan::ExclusiveSum(d_cub, cb, d_slen, d_srow, nsk + 1, s));
+        cb = cub_bytes;
+        BC_HIP(hipcub::DeviceScan::ExclusiveSum(d_cub, cb, d_tlen, d_trow, nint + 1, s));
+    } else {
+        zero_bytes(s, d_srow, 8);
+        zero_bytes(s, d_trow, 8);
     }
     BC_HIP(hipGetLastError());
     return BC_OK;
@@ -739,6 +770,8 @@ int SkBuild::issue_fill(hipStream_t s, const bc_skeleton* sk) const {
         if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyDeviceToDevice, s));
         return BC_OK;
     };
+    BC_TRY(d2d(sk->d_row_ptr, d_srow, (size_t)(nsk + 1) * 8));
+    BC_TRY(d2d(sk->d_trow, d_trow, (size_t)(nint + 1) * 8));
     BC_TRY(d2d(sk->d_nflag, d_sflag, nsk));
     BC_TRY(d2d(sk->d_nodes, d_nodes, (size_t)nsk * 4));
     BC_TRY(d2d(sk->d_tnode, d_inode, (size_t)nint * 4));
@@ -767,23 +800,17 @@ int SkBuild::issue_fill(hipStream_t s, const bc_skeleton* sk) const {
 int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
                       const std::function<int(size_t, Arena*&)>& get_store) {
     (void)W;
-    const int32_t ng = (int32_t)groups.size();
     BC_TRY(issue_count(s));
-    std::vector<int32_t> cdeg(nsk, 0), rdeg(nsk, 0), tdeg(nint, 0);
-    if (nsk) {
-        BC_HIP(hipMemcpyAsync(cdeg.data(), d_cdeg, (size_t)nsk * 4, hipMemcpyDeviceToHost, s));
-        BC_HIP(hipMemcpyAsync(rdeg.data(), d_rdeg, (size_t)nsk * 4, hipMemcpyDeviceToHost, s));
-    }
-    if (nint && ng) BC_HIP(hipMemcpyAsync(tdeg.data(), d_tdeg, (size_t)nint * 4, hipMemcpyDeviceToHost, s));
+    // read back the skeleton's row offsets (the host keeps them for group ranges)
+    // and the table's total; both were scanned on the device
+    sk->h_row_ptr.assign(nsk + 1, 0);
+    int64_t T = 0;
+    BC_HIP(hipMemcpyAsync(sk->h_row_ptr.data(), d_srow, (size_t)(nsk + 1) * 8, hipMemcpyDeviceToHost, s));
+    BC_HIP(hipMemcpyAsync(&T, d_trow + nint, 8, hipMemcpyDeviceToHost, s));
     BC_HIP(hipStreamSynchronize(s));
-    std::vector<int64_t> srow(nsk + 1, 0), trow(nint + 1, 0);
-    int64_t ncl = 0;
-    for (int32_t f = 0; f < nsk; ++f) {
-        srow[f + 1] = srow[f] + rdeg[f] + cdeg[f];
-        ncl += cdeg[f];
-    }
-    for (int32_t i = 0; i < nint; ++i) trow[i + 1] = trow[i] + tdeg[i];
-    const int64_t M = srow[nsk], T = trow[nint];
+    const int64_t M = sk->h_row_ptr[nsk];
+    // every skeleton row holds its cut arcs (nR in all) and then its clique arcs
+    const int64_t ncl = M - nR;
 
     // ---- the skeleton's own store
     const size_t sbytes = (size_t)(nsk + 1) * 8 + (size_t)M * (4 + 4 + 8 + 8) + (size_t)nsk +
@@ -807,24 +834,12 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
     sk->d_out_idx = A.take<int32_t>(std::max(n, 1));
     sk->d_out_which = A.take<uint8_t>(std::max(n, 1));
     if (!sk->d_out_which) return fail(BC_E_NOMEM, "skeleton store too small");
-    auto h2d = [&](void* d, const void* h, size_t b) -> int {
-        if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s));
-        return BC_OK;
-    };
-    BC_TRY(h2d(sk->d_row_ptr, srow.data(), (size_t)(nsk + 1) * 8));
-    BC_TRY(h2d(sk->d_trow, trow.data(), (size_t)(nint + 1) * 8));
     BC_TRY(issue_fill(s, sk));
     uint32_t clique_max = 0, rmax = 0;
     std::vector<int32_t> srcsk(nS);
-    sk->h_out_idx.resize(n);
-    sk->h_out_which.resize(n);
     BC_HIP(hipMemcpyAsync(&clique_max, d_maxlen, 4, hipMemcpyDeviceToHost, s));
     BC_HIP(hipMemcpyAsync(&rmax, d_rmax, 4, hipMemcpyDeviceToHost, s));
     if (nS) BC_HIP(hipMemcpyAsync(srcsk.data(), d_srcsk, (size_t)nS * 4, hipMemcpyDeviceToHost, s));
-    if (n) {
-        BC_HIP(hipMemcpyAsync(sk->h_out_idx.data(), d_out_idx, (size_t)n * 4, hipMemcpyDeviceToHost, s));
-        BC_HIP(hipMemcpyAsync(sk->h_out_which.data(), d_out_which, n, hipMemcpyDeviceToHost, s));
-    }
     BC_HIP(hipStreamSynchronize(s));
 
     sk->graph = g;
@@ -834,7 +849,6 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
     sk->h_src.clear();
     for (int32_t f : srcsk)
         if (f >= 0) sk->h_src.push_back(f);
-    sk->h_row_ptr = srow;
     sk->n_sk = nsk;
     sk->n_int = nint;
     sk->m_arcs = M;
