@@ -239,6 +239,8 @@ static int build_plain_plan(bc_batch* b) {
                 GroupDesc D;
                 D.lo = lo;
                 D.hi = hi;
+                D.arc_lo = G->h_row_ptr[lo];
+                D.arcs = G->h_row_ptr[hi] - G->h_row_ptr[lo];
                 D.flags = GF_BACKWARD;
                 D.ring_len = b->maxw[gi] + 1;
                 D.nsrc = std::min(per, ns - c);
@@ -273,6 +275,7 @@ static int build_plain_plan(bc_batch* b) {
         D.g.col = G->d_col;
         D.g.len = G->d_len;
         D.g.nflag = d_flag;
+        D.g.twin = G->d_twin;
         if (!resident_alloc(P->mem, D)) return fail(BC_E_NOMEM, "batch: workspace too small");
     }
     ResidentLaunch L;

@@ -242,6 +242,8 @@ int plain_resident(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_d
         GroupDesc& G = groups[j];
         G.lo = 0;
         G.hi = n;
+        G.arc_lo = 0;
+        G.arcs = g->nnz;
         G.flags = GF_BACKWARD;
         G.ring_len = g->maxw + 1;
         const int32_t first = j * spg;
@@ -265,6 +267,7 @@ int plain_resident(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_d
         G.g.col = g->d_col;
         G.g.len = g->d_len;
         G.g.nflag = d_flag;
+        G.g.twin = g->d_twin;
         if (!resident_alloc(g->work, G)) return fail(BC_E_NOMEM, "plain: workspace too small");
     }
     BC_TRY(run_resident(s, g->work, groups));

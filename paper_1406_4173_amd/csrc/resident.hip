@@ -117,6 +117,41 @@ __device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
     return v;
 }
 
+// Set bits of the bitmap tb in positions [a, a + n).
+__device__ __forceinline__ int bits_in(const uint32_t* tb, int a, int n) {
+    if (n <= 0) return 0;
+    const int w0 = a >> 5, w1 = (a + n - 1) >> 5;
+    const uint32_t m0 = ~0u << (a & 31), m1 = ~0u >> (31 - ((a + n - 1) & 31));
+    if (w0 == w1) return __popc(tb[w0] & m0 & m1);
+    int c = __popc(tb[w0] & m0) + __popc(tb[w1] & m1);
+    for (int w = w0 + 1; w < w1; ++w) c += __popc(tb[w]);
+    return c;
+}
+
+// Position of the j-th (from 0) set bit of tb at or after position a; the caller
+// knows that many bits are set there.
+__device__ __forceinline__ int select_bit(const uint32_t* tb, int a, int j) {
+    int w = a >> 5;
+    uint32_t x = tb[w] & (~0u << (a & 31));
+    int c = __popc(x);
+    while (j >= c) {
+        j -= c;
+        x = tb[++w];
+        c = __popc(x);
+    }
+    int pos = 0;
+#pragma unroll
+    for (int h = 16; h > 0; h >>= 1) {
+        const int cl = __popc(x & ((1u << h) - 1u));
+        if (j >= cl) {
+            j -= cl;
+            x >>= h;
+            pos += h;
+        }
+    }
+    return (w << 5) + pos;
+}
+
 // Visit the nodes v of [0, n) for which sel(v) holds. Wave w owns the BLK-node blocks b
 // with b % (T / 64) == w and scans 64 of its nodes per pass (64 / BLK blocks), in
 // increasing order; it appends the selected ones to its own LDS
@@ -294,7 +329,7 @@ struct RGroup {
     uint32_t flags;
     int32_t lg;     // bucket bitmaps: log2 of the bucket count (>= longest arc + 1); -1 = scan
     int32_t dense;  // a bucket step with more bits than this scans the range instead
-    int32_t pad_;
+    int32_t tw;     // words of the tight-arc bitmap in LDS after the state (0 = none)
     int64_t src_off;
     double* cacc;
     double* cint;
@@ -423,6 +458,24 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     uint32_t* __restrict__ bm = reinterpret_cast<uint32_t*>(lds);  // [RM+1][W]
     uint32_t* __restrict__ bc = bm + (size_t)(RM + 1) * W;         // [RM+1][2]
     auto cidx = [&](uint32_t d) { return ((d & RM) << 1) | ((d >> lg) & 1u); };
+    // Tight-arc bitmap (LDS state, backward groups whose graph has reverse-arc indices):
+    // one bit per arc of the range, after the state. For every tight parent arc x -> v
+    // that the forward finds, it sets the bit of the reverse arc v -> x (same length and
+    // multiplicity), so the backward expands only v's arcs to its children, in arc order:
+    // exactly the arcs whose test dx == dv + len would pass, without reading the others.
+    const GAS int64_t* __restrict__ twin = gas(C.g.twin);
+    uint32_t* __restrict__ tb = reinterpret_cast<uint32_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15) + (size_t)n * 8);
+    int64_t abase = 0;
+    uint32_t tbits = 0;  // arcs of the range
+    bool tight = false;
+    if constexpr (!GLOBAL) {
+        if (bwd && R.tw > 0 && twin) {
+            abase = rp[lo];
+            const int64_t na = rp[R.hi] - abase;
+            tight = na > 0 && ((na + 31) >> 5) <= (int64_t)R.tw;
+            tbits = tight ? (uint32_t)na : 0u;
+        }
+    }
     // this wave's record region (backward groups): nodes, then step numbers, then ends;
     // a wave queues only nodes of its own blocks (at most 64 * ceil(n / T) of them)
     const int32_t wcap = 64 * ((n + T - 1) / T);
@@ -447,6 +500,8 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             setD(v, (v == s) ? 0u : INF32);
             setS(v, (v == s) ? 1ull : 0ull);
         }
+        if (tight)
+            for (int32_t i = tid; i < R.tw; i += T) tb[i] = 0u;
         if (tid == 0) fwd_next[0] = fwd_next[1] = fwd_next[2] = INF32;
         if (bucket) {
             const int32_t tot = (int32_t)(RM + 1) * W;
@@ -495,6 +550,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         if (prof) bytes += 12ull;
                         const int32_t u = col[e] - lo;
                         const uint32_t L = len ? len[e] : 1u;
+                        const int64_t te = tight ? twin[e] : 0;
                         // one read of u's distance serves both tests below: if another
                         // lane lowers it meanwhile, the offer test passes at worst for an
                         // offer that then changes nothing
@@ -507,6 +563,10 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                             // than the source is tight but adds no paths
                             if (du != INF32 && du + L == D &&
                                 !(restrict_ && u != s && nflag && (nflag[lo + u] & NF_BLOCKED))) {
+                                if (tight) {
+                                    const uint64_t t = (uint64_t)(te - abase);
+                                    if (t < tbits) atomicOr(&tb[t >> 5], 1u << (t & 31));
+                                }
                                 uint64_t x = S_(u);
                                 if (mult) {
                                     const uint64_t m = mult[e];
@@ -651,6 +711,26 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         prev = cacc[q];
                         ind = (nflag && (nflag[lo + q] & NF_TARGET)) ? 1.0 : 0.0;
                     }
+                    if (tight) {
+                        // only the arcs to v's children: their bits, in arc order
+                        const int a = valid ? (int)(e0 - abase) : 0;
+                        const int td = valid ? bits_in(tb, a, deg) : 0;
+                        if (prof && valid) bytes += 20ull * (unsigned long long)deg;
+                        for_queue_arcs(0, td, wq, [&](int owner, int64_t j, bool ok, int incl, int excl, int r) {
+                            const int seg = max(__shfl(excl, owner, 64) - r, 0);
+                            const int ao = __shfl(a, owner, 64);
+                            double c = 0.0;
+                            if (ok) {
+                                const int64_t e = abase + select_bit(tb, ao, (int)j);
+                                c = __longlong_as_double((long long)S_(col[e] - lo));
+                                if (mult) c *= (double)mult[e];
+                            }
+                            c = wseg_sum(c, seg);
+                            const int ab = max(excl - r, 0), b = min(incl - r, 64);
+                            const double part = __shfl(c, max(b - 1, 0), 64);
+                            if (b > ab) acc += part;
+                        });
+                    } else
                     for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
                         // segment of this lane's arc: lanes from its node's first arc in
                         // this round
@@ -789,6 +869,14 @@ int64_t tune_value(const char* name, int64_t dflt) {
     const long long v = atoll(e);
     return v >= 0 ? (int64_t)v : dflt;
 }
+// The backward's tight-arc bitmap; BCPP_TIGHT=0 switches it off (every arc is tested).
+bool tight_arcs_on() {
+    static const bool on = [] {
+        const char* e = getenv("BCPP_TIGHT");
+        return !(e && strcmp(e, "0") == 0);
+    }();
+    return on;
+}
 struct SizeClasses {
     int64_t small = tune_value("BCPP_TUNE_SMALL", tuned_small_range);
     int64_t mid = tune_value("BCPP_TUNE_MID", tuned_mid_range);
@@ -883,6 +971,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         const int lg0 = bucket_lg(G.ring_len);
         const size_t bb = lg0 >= 0 ? bucket_bytes(range, lg0) : 0;
         int c, lg = -1;
+        int32_t tw = 0;
         size_t need;
         if (state > limits().lds) {
             if (!G.gdist || !G.gsig) return fail(BC_E_INVAL, "resident: no state buffers for a large range");
@@ -892,6 +981,14 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         } else {
             c = sc.of(range);
             need = state;
+            // the tight-arc bitmap, where it fits beside the state
+            if (tight_arcs_on() && (G.flags & GF_BACKWARD) && G.g.twin && G.arcs > 0) {
+                const int64_t words = (G.arcs + 31) / 32;
+                if (state + (size_t)words * 4 <= limits().lds) {
+                    tw = (int32_t)words;
+                    need = state + (size_t)words * 4;
+                }
+            }
         }
         L->lds[c] = std::max(L->lds[c], need);
         const auto key = std::make_pair((const void*)G.g.row_ptr, (const void*)G.trow);
@@ -903,6 +1000,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         RGroup r{};
         r.lg = lg;
         r.dense = (int32_t)(range >> sc.dense_shift);
+        r.tw = tw;
         r.ctx = it->second;
         r.lo = G.lo;
         r.hi = G.hi;

@@ -973,8 +973,11 @@ std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk) {
         G.g.len = sk->d_len;
         G.g.mult = sk_mult(sk);
         G.g.nflag = sk->d_nflag;
+        G.g.twin = sk->d_twin;
         G.lo = 0;
         G.hi = sk->n_sk;
+        G.arc_lo = 0;
+        G.arcs = sk->m_arcs;
         G.ring_len = sk->max_len + 1;
         G.flags = GF_BACKWARD | (sk->n_int ? GF_CENT : 0u);
         G.trow = sk->d_trow;
