@@ -59,8 +59,10 @@ def measured_traffic(workload, kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    # a process's first calls include a one-off stall of several ms (once, somewhere in
+    # the first dozen calls, whatever the call pattern): warm up past it
+    ap.add_argument("--warmup", type=int, default=15)
     ap.add_argument("--workload", default="sbm_10k",
                     choices=["planted_1k", "sbm_10k", "pareto_100k", "smallcut_100k", "batch_256", "p1_sweep",
                              "serve_64"])

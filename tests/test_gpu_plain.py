@@ -194,3 +194,17 @@ def test_plain_bucket_and_scan_steps_agree(bcpp, monkeypatch, n, wmax, intra):
     assert np.array_equal(got["0"], got["63"])
     assert np.array_equal(got["0"], got[None])
     assert_scores(got[None], oracle.bc(g, S))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,deg", [(8000, 10.0), (12000, 30.0)])
+def test_plain_lds_state_with_and_without_tight_bitmap(bcpp, n, deg):
+    """With the state in LDS the backward expands only the arcs that the forward found
+    tight (a bitmap of the range's arcs beside the state). 8,000 nodes of degree 10
+    leave room for it; 12,000 nodes of degree 30 fill LDS with the state alone (144 KB
+    against 45 KB of bitmap), so every arc is tested there. Both match the oracle."""
+    rng = inputs.rng_for(inputs.SEED_BASE + 93, n, int(deg))
+    g = inputs._community_graph(rng, n, n // 50, deg, 0.9, 10, "tight")
+    S = np.sort(rng.choice(g.n, 40, replace=False)).astype(np.int32)
+    G = bcpp.Graph(g)
+    assert_scores(bcpp.brandes_plain(G, S), oracle.bc(g, S))

@@ -223,3 +223,35 @@ def test_pp_small_cut_sweep_graphs(bcpp, intra):
     want = oracle.bc(g, g.S)
     assert_scores(bcpp.brandes_pp(G, sk), want)
     assert_scores(bcpp.brandes_plain(G, g.S), want)
+
+
+def test_pp_skeletons_alive_together_and_freed_out_of_order(bcpp):
+    """Skeletons of three graphs of different sizes are built while others are alive
+    and freed out of order (device memory freed by one is often handed to the next);
+    every Brandes++ result equals that graph's first one bit for bit, and the first
+    ones equal the oracle."""
+    rng = inputs.rng_for(inputs.SEED_BASE + 95)
+    graphs = [inputs.planted_1k()]
+    for n, k in ((30000, 600), (8000, 160)):
+        g = inputs._community_graph(rng, n, k, 8.0, 0.97, 4, "recycle")
+        g.S = np.sort(rng.choice(n, 50, replace=False)).astype(np.int32)
+        graphs.append(g)
+    Gs = [bcpp.Graph(g) for g in graphs]
+    first = {}
+    alive = []
+    for step, i in enumerate([1, 0, 2, 1, 2, 0, 2, 1, 0]):
+        g = graphs[i]
+        sk = bcpp.partition_sk(Gs[i], g.part, g.k, g.S)
+        got = bcpp.brandes_pp(Gs[i], sk)
+        if i in first:
+            assert np.array_equal(got, first[i]), f"graph {i} at step {step}"
+        else:
+            assert_scores(got, oracle.bc(g, g.S))
+            first[i] = got
+        alive.append(sk)
+        if step % 3 != 0:
+            alive.pop(0).close()
+        if step % 4 == 3:
+            alive.pop().close()
+    for sk in alive:
+        sk.close()
