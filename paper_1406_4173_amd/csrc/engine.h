@@ -77,6 +77,7 @@ struct GroupDesc {
     // resident groups too large for LDS: the one-source state in device memory
     uint32_t* gdist = nullptr;  // [hi-lo]
     uint64_t* gsig = nullptr;   // [hi-lo]
+    uint32_t* gtb = nullptr;    // [ceil(arcs/32)] their backward's tight-arc bitmap
     // resident backward groups: the forward's per-wave queue record and step distances
     int32_t* rlist = nullptr;
     uint32_t* steps = nullptr;  // [hi-lo+1]

@@ -117,28 +117,8 @@ __device__ __forceinline__ unsigned long long wsum_u64(unsigned long long v) {
     return v;
 }
 
-// Set bits of the bitmap tb in positions [a, a + n).
-__device__ __forceinline__ int bits_in(const uint32_t* tb, int a, int n) {
-    if (n <= 0) return 0;
-    const int w0 = a >> 5, w1 = (a + n - 1) >> 5;
-    const uint32_t m0 = ~0u << (a & 31), m1 = ~0u >> (31 - ((a + n - 1) & 31));
-    if (w0 == w1) return __popc(tb[w0] & m0 & m1);
-    int c = __popc(tb[w0] & m0) + __popc(tb[w1] & m1);
-    for (int w = w0 + 1; w < w1; ++w) c += __popc(tb[w]);
-    return c;
-}
-
-// Position of the j-th (from 0) set bit of tb at or after position a; the caller
-// knows that many bits are set there.
-__device__ __forceinline__ int select_bit(const uint32_t* tb, int a, int j) {
-    int w = a >> 5;
-    uint32_t x = tb[w] & (~0u << (a & 31));
-    int c = __popc(x);
-    while (j >= c) {
-        j -= c;
-        x = tb[++w];
-        c = __popc(x);
-    }
+// Position (0..31) of the j-th (from 0) set bit of x; x has more than j set bits.
+__device__ __forceinline__ int nth_set_bit(uint32_t x, int j) {
     int pos = 0;
 #pragma unroll
     for (int h = 16; h > 0; h >>= 1) {
@@ -149,7 +129,34 @@ __device__ __forceinline__ int select_bit(const uint32_t* tb, int a, int j) {
             pos += h;
         }
     }
-    return (w << 5) + pos;
+    return pos;
+}
+
+// Set bits in positions [a, a + n) of a bitmap whose word w is ld(w).
+template <class LD>
+__device__ __forceinline__ int bits_in(LD&& ld, int a, int n) {
+    if (n <= 0) return 0;
+    const int w0 = a >> 5, w1 = (a + n - 1) >> 5;
+    const uint32_t m0 = ~0u << (a & 31), m1 = ~0u >> (31 - ((a + n - 1) & 31));
+    if (w0 == w1) return __popc(ld(w0) & m0 & m1);
+    int c = __popc(ld(w0) & m0) + __popc(ld(w1) & m1);
+    for (int w = w0 + 1; w < w1; ++w) c += __popc(ld(w));
+    return c;
+}
+
+// Position of the j-th (from 0) set bit at or after position a; the caller knows that
+// many bits are set there.
+template <class LD>
+__device__ __forceinline__ int select_bit(LD&& ld, int a, int j) {
+    int w = a >> 5;
+    uint32_t x = ld(w) & (~0u << (a & 31));
+    int c = __popc(x);
+    while (j >= c) {
+        j -= c;
+        x = ld(++w);
+        c = __popc(x);
+    }
+    return (w << 5) + nth_set_bit(x, j);
 }
 
 // Visit the nodes v of [0, n) for which sel(v) holds. Wave w owns the BLK-node blocks b
@@ -337,6 +344,7 @@ struct RGroup {
     uint64_t* isig;   // [tn] interior sigma(s,v) of the current source
     uint32_t* gdist;  // [hi-lo] one-source state in device memory (ranges beyond LDS)
     uint64_t* gsig;
+    uint32_t* gtb;    // [tw] their tight-arc bitmap
     int32_t* rlist;   // backward groups: per-wave record of the forward's queues
     uint32_t* steps;  // backward groups: distance of each forward step
 };
@@ -458,24 +466,30 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     uint32_t* __restrict__ bm = reinterpret_cast<uint32_t*>(lds);  // [RM+1][W]
     uint32_t* __restrict__ bc = bm + (size_t)(RM + 1) * W;         // [RM+1][2]
     auto cidx = [&](uint32_t d) { return ((d & RM) << 1) | ((d >> lg) & 1u); };
-    // Tight-arc bitmap (LDS state, backward groups whose graph has reverse-arc indices):
-    // one bit per arc of the range, after the state. For every tight parent arc x -> v
-    // that the forward finds, it sets the bit of the reverse arc v -> x (same length and
-    // multiplicity), so the backward expands only v's arcs to its children, in arc order:
-    // exactly the arcs whose test dx == dv + len would pass, without reading the others.
+    // Tight-arc bitmap (backward groups whose graph has reverse-arc indices): one bit per
+    // arc of the range, in LDS after the state, or in device memory (R.gtb) with the
+    // state. For every tight parent arc x -> v that the forward finds, it sets the bit of
+    // the reverse arc v -> x (same length and multiplicity), so the backward expands only
+    // v's arcs to its children, in arc order: exactly the arcs whose test
+    // dx == dv + len would pass, without reading the others.
     const GAS int64_t* __restrict__ twin = gas(C.g.twin);
     uint32_t* __restrict__ tb = reinterpret_cast<uint32_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15) + (size_t)n * 8);
+    GAS uint32_t* __restrict__ gtb = gas(R.gtb);
     int64_t abase = 0;
     uint32_t tbits = 0;  // arcs of the range
     bool tight = false;
-    if constexpr (!GLOBAL) {
-        if (bwd && R.tw > 0 && twin) {
-            abase = rp[lo];
-            const int64_t na = rp[R.hi] - abase;
-            tight = na > 0 && ((na + 31) >> 5) <= (int64_t)R.tw;
-            tbits = tight ? (uint32_t)na : 0u;
-        }
+    if (bwd && R.tw > 0 && twin && (!GLOBAL || R.gtb)) {
+        abase = rp[lo];
+        const int64_t na = rp[R.hi] - abase;
+        tight = na > 0 && na < ((int64_t)1 << 31) - 64 && ((na + 31) >> 5) <= (int64_t)R.tw;
+        tbits = tight ? (uint32_t)na : 0u;
     }
+    auto tb_ld = [&](int w) -> uint32_t {
+        if constexpr (GLOBAL)
+            return __hip_atomic_load(gtb + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return tb[w];
+    };
     // this wave's record region (backward groups): nodes, then step numbers, then ends;
     // a wave queues only nodes of its own blocks (at most 64 * ceil(n / T) of them)
     const int32_t wcap = 64 * ((n + T - 1) / T);
@@ -501,7 +515,12 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             setS(v, (v == s) ? 1ull : 0ull);
         }
         if (tight)
-            for (int32_t i = tid; i < R.tw; i += T) tb[i] = 0u;
+            for (int32_t i = tid; i < R.tw; i += T) {
+                if constexpr (GLOBAL)
+                    gtb[i] = 0u;
+                else
+                    tb[i] = 0u;
+            }
         if (tid == 0) fwd_next[0] = fwd_next[1] = fwd_next[2] = INF32;
         if (bucket) {
             const int32_t tot = (int32_t)(RM + 1) * W;
@@ -565,7 +584,13 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                 !(restrict_ && u != s && nflag && (nflag[lo + u] & NF_BLOCKED))) {
                                 if (tight) {
                                     const uint64_t t = (uint64_t)(te - abase);
-                                    if (t < tbits) atomicOr(&tb[t >> 5], 1u << (t & 31));
+                                    if (t < tbits) {
+                                        if constexpr (GLOBAL)
+                                            __hip_atomic_fetch_or(gtb + (t >> 5), 1u << (t & 31),
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                        else
+                                            atomicOr(&tb[t >> 5], 1u << (t & 31));
+                                    }
                                 }
                                 uint64_t x = S_(u);
                                 if (mult) {
@@ -712,16 +737,46 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         ind = (nflag && (nflag[lo + q] & NF_TARGET)) ? 1.0 : 0.0;
                     }
                     if (tight) {
-                        // only the arcs to v's children: their bits, in arc order
+                        // only the arcs to v's children: their bits, in arc order. A node
+                        // whose arcs span at most two bitmap words keeps those words (its
+                        // own bits only) in registers, and the lanes that take its arcs
+                        // read them with shuffles; a wider node's lanes read the bitmap.
                         const int a = valid ? (int)(e0 - abase) : 0;
-                        const int td = valid ? bits_in(tb, a, deg) : 0;
+                        const int dg = valid ? deg : 0;
+                        const int sh = a & 31;
+                        const bool narrow = sh + dg <= 64;
+                        uint32_t x0 = 0u, x1 = 0u;
+                        int td = 0;
+                        if (dg > 0) {
+                            if (narrow) {
+                                x0 = tb_ld(a >> 5) & (~0u << sh);
+                                if (sh + dg < 32)
+                                    x0 &= ~0u >> (32 - (sh + dg));
+                                else if (sh + dg > 32)
+                                    x1 = tb_ld((a >> 5) + 1) & (~0u >> (64 - (sh + dg)));
+                                td = __popc(x0) + __popc(x1);
+                            } else {
+                                td = bits_in(tb_ld, a, dg);
+                            }
+                        }
                         if (prof && valid) bytes += 20ull * (unsigned long long)deg;
+                        const int an = narrow ? a : ~a;  // start bit, negative for a wide node
                         for_queue_arcs(0, td, wq, [&](int owner, int64_t j, bool ok, int incl, int excl, int r) {
                             const int seg = max(__shfl(excl, owner, 64) - r, 0);
-                            const int ao = __shfl(a, owner, 64);
+                            const int ao = __shfl(an, owner, 64);
+                            const uint32_t y0 = (uint32_t)__shfl((int)x0, owner, 64);
+                            const uint32_t y1 = (uint32_t)__shfl((int)x1, owner, 64);
                             double c = 0.0;
                             if (ok) {
-                                const int64_t e = abase + select_bit(tb, ao, (int)j);
+                                int pos;
+                                if (ao >= 0) {
+                                    const int c0 = __popc(y0);
+                                    pos = (int)j < c0 ? ((ao >> 5) << 5) + nth_set_bit(y0, (int)j)
+                                                      : (((ao >> 5) + 1) << 5) + nth_set_bit(y1, (int)j - c0);
+                                } else {
+                                    pos = select_bit(tb_ld, ~ao, (int)j);
+                                }
+                                const int64_t e = abase + pos;
                                 c = __longlong_as_double((long long)S_(col[e] - lo));
                                 if (mult) c *= (double)mult[e];
                             }
@@ -915,11 +970,18 @@ bool resident_takes(int64_t range) {
     return query_limits() == BC_OK;
 }
 
+// A backward group whose state is in device memory keeps its tight-arc bitmap there.
+static bool device_tight_bitmap(const GroupDesc& G) {
+    return tight_arcs_on() && (G.flags & GF_BACKWARD) && G.arcs > 0 && G.arcs < ((int64_t)1 << 31) - 64;
+}
+
 size_t resident_group_bytes(const GroupDesc& G) {
     const int64_t range = (int64_t)G.hi - G.lo;
     size_t b = ((size_t)range * 8 + 255) & ~(size_t)255;
-    if (range > resident_max_range())
+    if (range > resident_max_range()) {
         b += (((size_t)range * 4 + 255) & ~(size_t)255) + (((size_t)range * 8 + 255) & ~(size_t)255);
+        if (device_tight_bitmap(G)) b += ((size_t)((G.arcs + 31) / 32) * 4 + 255) & ~(size_t)255;
+    }
     if ((G.flags & GF_CENT) && G.tn > 0)
         b += (((size_t)G.tn * 8 + 255) & ~(size_t)255) * 2 + (((size_t)G.tn * 4 + 255) & ~(size_t)255);
     if (G.flags & GF_BACKWARD)
@@ -935,6 +997,10 @@ bool resident_alloc(Arena& a, GroupDesc& G) {
         G.gdist = a.take<uint32_t>((size_t)range);
         G.gsig = a.take<uint64_t>((size_t)range);
         if (!G.gdist || !G.gsig) return false;
+        if (device_tight_bitmap(G)) {
+            G.gtb = a.take<uint32_t>((size_t)((G.arcs + 31) / 32));
+            if (!G.gtb) return false;
+        }
     }
     if (G.flags & GF_BACKWARD) {
         G.rlist = a.take<int32_t>(record_ints(range));
@@ -976,6 +1042,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         if (state > limits().lds) {
             if (!G.gdist || !G.gsig) return fail(BC_E_INVAL, "resident: no state buffers for a large range");
             c = 3;
+            if (G.gtb && G.g.twin && (G.flags & GF_BACKWARD) && G.arcs > 0) tw = (int32_t)((G.arcs + 31) / 32);
             lg = (lg0 >= 0 && bb <= limits().lds) ? lg0 : -1;
             need = lg >= 0 ? bb : 0;
         } else {
@@ -1016,6 +1083,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         r.isig = G.sigma;
         r.gdist = G.gdist;
         r.gsig = G.gsig;
+        r.gtb = tw > 0 && c == 3 ? G.gtb : nullptr;
         r.rlist = G.rlist;
         r.steps = G.steps;
         if ((G.flags & GF_BACKWARD) && (!G.rlist || !G.steps))
