@@ -1,7 +1,9 @@
 """Autotuner of the resident kernel's launch shapes; writes csrc/tuned.h.
 
 Usage (on a machine with the GPU): python -m paper_1406_4173_amd.autotune [--out PATH]
-then rebuild (python -m paper_1406_4173_amd.build_lib).
+[--pairs SMALL:MID,...] [--divs DIV,...] [--dense SHIFT,...], then rebuild (python -m
+paper_1406_4173_amd.build_lib). The options narrow the grids below ("all" = no limit);
+a single --dense value is kept without timing.
 
 Four values are tuned, all fixed per build so that a graph gets the same launch shape
 alone, inside a batch or in the server (results then agree bit for bit):
@@ -59,7 +61,7 @@ SHAPE_PAIRS = [(BIG, BIG), (6500, BIG), (4000, 6500), (2500, 6500), (2500, 4000)
 SHAPE_DIVS = (256, 1024)
 
 
-def sweep_shapes(bcpp, inputs, torch, log):
+def sweep_shapes(bcpp, inputs, torch, log, pairs=SHAPE_PAIRS, divs=SHAPE_DIVS):
     singles = []
     for name in ("sbm_10k", "planted_1k"):
         g = getattr(inputs, name)()
@@ -71,8 +73,8 @@ def sweep_shapes(bcpp, inputs, torch, log):
     gs = inputs.batch_256()
     names = [n for n, _ in singles] + ["batch_256 plain", "batch_256 pp"]
     rows = {}
-    for small, mid in SHAPE_PAIRS:
-        for div in SHAPE_DIVS:
+    for small, mid in pairs:
+        for div in divs:
             os.environ["BCPP_TUNE_SMALL"] = str(small)
             os.environ["BCPP_TUNE_MID"] = str(mid)
             os.environ["BCPP_TUNE_SPG_DIV"] = str(div)
@@ -90,7 +92,7 @@ def sweep_shapes(bcpp, inputs, torch, log):
     return min(rows, key=lambda k: sum(rows[k]))
 
 
-def sweep_dense(bcpp, inputs, torch, log):
+def sweep_dense(bcpp, inputs, torch, log, shifts=(1, 2, 3, 4, 6, 63)):
     """Bucket steps with more than range >> shift bits scan the range instead; the
     shift only moves time (both visits queue the same nodes in the same order)."""
     work = []
@@ -102,7 +104,7 @@ def sweep_dense(bcpp, inputs, torch, log):
         work.append((name + " plain", lambda G=G, S=S, out=out: bcpp.brandes_plain_dev(G, S, out)))
         work.append((name + " pp", lambda G=G, g=g: bcpp.brandes_pp(G, bcpp.partition_sk(G, g.part, g.k, g.S))))
     rows = {}
-    for shift in (1, 2, 3, 4, 6, 63):
+    for shift in shifts:
         os.environ["BCPP_TUNE_DENSE_SHIFT"] = str(shift)
         rows[shift] = [_time(f, torch.cuda.synchronize, reps=2) for _, f in work]
         log.append(f"dense shift {shift:2d}: " + "  ".join(
@@ -144,7 +146,15 @@ def write_header(path, small, mid, div, dense, log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(HERE, "csrc", "tuned.h"))
+    ap.add_argument("--pairs", default=None, help="SMALL:MID,... (\"all\" = no limit)")
+    ap.add_argument("--divs", default=None, help="DIV,...")
+    ap.add_argument("--dense", default=None, help="SHIFT,... (one value: kept untimed)")
     args = ap.parse_args()
+    lim = lambda v: BIG if v == "all" else int(v)
+    pairs = ([tuple(lim(x) for x in p.split(":")) for p in args.pairs.split(",")] if args.pairs
+             else SHAPE_PAIRS)
+    divs = tuple(int(x) for x in args.divs.split(",")) if args.divs else SHAPE_DIVS
+    shifts = tuple(int(x) for x in args.dense.split(",")) if args.dense else (1, 2, 3, 4, 6, 63)
     import torch
 
     from paper_1406_4173_amd import bcpp, inputs
@@ -152,11 +162,11 @@ def main():
     bcpp.lib()
     _clear()
     log = []
-    small, mid, div = sweep_shapes(bcpp, inputs, torch, log)
+    small, mid, div = sweep_shapes(bcpp, inputs, torch, log, pairs, divs)
     os.environ["BCPP_TUNE_SMALL"] = str(small)
     os.environ["BCPP_TUNE_MID"] = str(mid)
     os.environ["BCPP_TUNE_SPG_DIV"] = str(div)
-    dense = sweep_dense(bcpp, inputs, torch, log)
+    dense = shifts[0] if len(shifts) == 1 else sweep_dense(bcpp, inputs, torch, log, shifts)
     log.append(f"chosen: small range {small}, mid range {mid}, sources-per-group divisor {div}, "
                f"dense shift {dense}")
     print(log[-1], flush=True)
