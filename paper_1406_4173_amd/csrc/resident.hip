@@ -9,12 +9,14 @@
 //             and lowers its neighbours' tentative distances with LDS atomics. Arc
 //             lengths are at least 1, so a node whose tentative distance equals the
 //             current step's D is final, and its parents were settled (and their counts
-//             written) in earlier steps, behind a barrier.
+//             written) in earlier steps, behind a barrier. Each tight parent arc found
+//             marks its reverse arc in a bitmap: the arcs to each node's children.
 //   interior  (skeleton groups with tables, Sec. 5, Step 3) d(s,v) and sigma(s,v) of
 //             every interior row from the frontier state.
 //   backward  the same steps in decreasing distance: delta(s|v) = sigma(s,v) * sum over
 //             tight children x of m(v,x) * coef(s,x), coef(s,v) = (I[v in S] + delta(s|v))
 //             / sigma(s,v) (eq. brandes / eq. multibrandes). coef replaces sigma in LDS.
+//             Only the arcs marked in the bitmap are read.
 //   interior  delta(s|v) of the interior rows (eq. localcentrality).
 // A group's node scores (cacc) and interior scores (cint) are owned by its workgroup
 // and accumulated in source order, so results do not depend on what else runs.
@@ -336,7 +338,7 @@ struct RGroup {
     uint32_t flags;
     int32_t lg;     // bucket bitmaps: log2 of the bucket count (>= longest arc + 1); -1 = scan
     int32_t dense;  // a bucket step with more bits than this scans the range instead
-    int32_t tw;     // words of the tight-arc bitmap in LDS after the state (0 = none)
+    int32_t tw;     // words of the tight-arc bitmap (0 = none): in LDS after the state, or gtb
     int64_t src_off;
     double* cacc;
     double* cint;
@@ -344,7 +346,7 @@ struct RGroup {
     uint64_t* isig;   // [tn] interior sigma(s,v) of the current source
     uint32_t* gdist;  // [hi-lo] one-source state in device memory (ranges beyond LDS)
     uint64_t* gsig;
-    uint32_t* gtb;    // [tw] their tight-arc bitmap
+    uint32_t* gtb;    // [tw] their tight-arc bitmap (state in device memory only)
     int32_t* rlist;   // backward groups: per-wave record of the forward's queues
     uint32_t* steps;  // backward groups: distance of each forward step
 };
