@@ -413,6 +413,29 @@ def main():
     if not args.no_plain:
         t_plain = timed(plain_step, args.steps, args.warmup, sync)
         res["plain"] = {"value": units / t_plain, "unit": "TEPS", "ms_per_step": t_plain * 1e3}
+        # the plain pass's roofline: the same steps again with the kernels' HIP events and
+        # byte counters on (after the timed steps, which ran without them)
+        bcpp.profile_enable(True)
+        bcpp.profile_reset()
+        for _ in range(args.steps):
+            plain_step()
+        sync()
+        pk = bcpp.profile_read()["resident"]
+        bcpp.profile_enable(False)
+        if pk["ms"] > 0 and pk["launches"] > 0:
+            ach = pk["alg_bytes"] / (pk["ms"] * 1e-3) / 1e9
+            res["plain"]["roofline"] = {
+                "kernel": "resident",
+                "bound": "hbm",
+                "achieved": ach,
+                "peak": PEAK_HBM_GBS,
+                "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS,
+                "launches": pk["launches"],
+                "avg_launch_us": pk["ms"] * 1e3 / pk["launches"],
+                "alg_bytes_per_launch": pk["alg_bytes"] / pk["launches"],
+                "timing": "HIP events on a profiled pass of the same steps after the timed ones",
+            }
         res["pp_over_plain"] = t_plain / t_pp
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
