@@ -927,6 +927,10 @@ int64_t tune_value(const char* name, int64_t dflt) {
     return v >= 0 ? (int64_t)v : dflt;
 }
 // The backward's tight-arc bitmap; BCPP_TIGHT=0 switches it off (every arc is tested).
+// A range takes it with at least TIGHT_MIN_DEG arcs per node: on sparser ranges (the
+// skeletons of graphs with small communities, 3 to 5 arcs per node) few arcs are
+// skipped, and the forward's reverse-arc loads and marks cost more than that saves.
+constexpr int64_t TIGHT_MIN_DEG = 6;
 bool tight_arcs_on() {
     static const bool on = [] {
         const char* e = getenv("BCPP_TIGHT");
@@ -934,6 +938,7 @@ bool tight_arcs_on() {
     }();
     return on;
 }
+bool tight_pays(int64_t range, int64_t arcs) { return arcs > 0 && arcs >= TIGHT_MIN_DEG * range; }
 struct SizeClasses {
     int64_t small = tune_value("BCPP_TUNE_SMALL", tuned_small_range);
     int64_t mid = tune_value("BCPP_TUNE_MID", tuned_mid_range);
@@ -974,7 +979,8 @@ bool resident_takes(int64_t range) {
 
 // A backward group whose state is in device memory keeps its tight-arc bitmap there.
 static bool device_tight_bitmap(const GroupDesc& G) {
-    return tight_arcs_on() && (G.flags & GF_BACKWARD) && G.arcs > 0 && G.arcs < ((int64_t)1 << 31) - 64;
+    return tight_arcs_on() && (G.flags & GF_BACKWARD) && tight_pays((int64_t)G.hi - G.lo, G.arcs) &&
+           G.arcs < ((int64_t)1 << 31) - 64;
 }
 
 size_t resident_group_bytes(const GroupDesc& G) {
@@ -1051,7 +1057,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
             c = sc.of(range);
             need = state;
             // the tight-arc bitmap, where it fits beside the state
-            if (tight_arcs_on() && (G.flags & GF_BACKWARD) && G.g.twin && G.arcs > 0) {
+            if (tight_arcs_on() && (G.flags & GF_BACKWARD) && G.g.twin && tight_pays(range, G.arcs)) {
                 const int64_t words = (G.arcs + 31) / 32;
                 if (state + (size_t)words * 4 <= limits().lds) {
                     tw = (int32_t)words;
