@@ -208,3 +208,23 @@ def test_plain_lds_state_with_and_without_tight_bitmap(bcpp, n, deg):
     S = np.sort(rng.choice(g.n, 40, replace=False)).astype(np.int32)
     G = bcpp.Graph(g)
     assert_scores(bcpp.brandes_plain(G, S), oracle.bc(g, S))
+
+
+@pytest.mark.gpu
+def test_plain_lds_state_tight_bitmap_with_hubs(bcpp):
+    """Nodes whose arcs span more than two words of the tight-arc bitmap count and
+    select their bits in the bitmap itself rather than in registers: a 3,000-node
+    community graph (state in LDS) with 5 hubs of degree 400, weights 1..3."""
+    rng = inputs.rng_for(inputs.SEED_BASE + 97)
+    base = inputs._community_graph(rng, 3000, 60, 8.0, 0.9, 3, "hubs")
+    u, v, w = base.edges()
+    hubs = np.arange(5) * 600
+    hu = np.repeat(hubs, 400)
+    hv = rng.choice(3000, hu.size)
+    g = inputs.graph_from_edges(3000, np.concatenate([u, hu]), np.concatenate([v, hv]),
+                                np.concatenate([w, rng.integers(1, 4, hu.size)]), name="hubs")
+    deg = np.diff(g.row_ptr)
+    assert deg[hubs].min() > 300 and g.nnz >= 6 * g.n
+    S = np.union1d(hubs, rng.choice(3000, 60, replace=False)).astype(np.int32)
+    G = bcpp.Graph(g)
+    assert_scores(bcpp.brandes_plain(G, S), oracle.bc(g, S))
