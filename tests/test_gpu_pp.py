@@ -255,3 +255,18 @@ def test_pp_skeletons_alive_together_and_freed_out_of_order(bcpp):
             alive.pop().close()
     for sk in alive:
         sk.close()
+
+
+def test_pp_lds_skeleton_with_wide_cliques(bcpp):
+    """A skeleton held in LDS with the tight-arc bitmap, wide rows and path
+    multiplicities: 2,000 nodes in 4 parts, degree 12, 10% of edges cut, weights 1..2,
+    40 targets. Its 1,531 frontier nodes have about 50 arcs each (up to 153), and
+    clique arcs carry up to 4 shortest paths."""
+    rng = inputs.rng_for(inputs.SEED_BASE + 99, 2000, 4)
+    g = inputs._community_graph(rng, 2000, 4, 12.0, 0.9, 2, "cliques")
+    g.S = np.sort(rng.choice(g.n, 40, replace=False)).astype(np.int32)
+    G = bcpp.Graph(g)
+    sk = bcpp.partition_sk(G, g.part, g.k, g.S)
+    st = sk.stats()
+    assert st["n_sk"] == 1531 and st["r_arcs"] + st["clique_arcs"] >= 6 * st["n_sk"]
+    assert_scores(bcpp.brandes_pp(G, sk), oracle.bc(g, g.S))
