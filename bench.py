@@ -6,8 +6,12 @@ Centrality pass, scores written to a device tensor). The graph is resident on th
 device before timing starts. Plain GPU Brandes on the same graph and targets is timed
 the same way and reported beside it, with the CPU oracle on a bounded sample.
 
+The default workload is pareto_100k: 100,000 nodes in 500 planted communities of
+Pareto(2) sizes, mean degree 8, 85% intra-community edges, weights 1..4, 2,000 random
+targets (Sec. 7's workload shape: random targets, community-structured graphs).
+
 Prints one JSON line. Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                                             [--workload sbm_10k]
+                                             [--workload pareto_100k]
 """
 import argparse
 import json
@@ -56,6 +60,29 @@ def measured_traffic(workload, kernel):
     return float(ent["fetch_bytes_per_launch"]) + float(ent["write_bytes_per_launch"])
 
 
+def roofline_entry(workload, kernel, kp, timing=None):
+    """Roofline of one kernel kind from its profiler totals: algorithmic bytes per
+    launch over the launch's average HIP-event duration, against the HBM peak; beside it
+    the measured HBM traffic (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled) and its own
+    fraction of the peak. `bound` comes from those counters: "hbm" when the measured
+    traffic runs at half the peak or more, else "latency" (neither HBM nor ALU throughput
+    is near its peak: the kernel waits on L2 and LDS round trips), or null without
+    counters for the current source."""
+    launches = max(kp["launches"], 1)
+    avg_s = kp["ms"] * 1e-3 / launches
+    alg = kp["alg_bytes"] / launches
+    achieved = alg / avg_s / 1e9 if avg_s > 0 else 0.0
+    traffic = measured_traffic(workload, kernel)
+    mfrac = traffic / avg_s / 1e9 / PEAK_HBM_GBS if traffic and avg_s > 0 else None
+    bound = None if mfrac is None else ("hbm" if mfrac >= 0.5 else "latency")
+    r = {"kernel": kernel, "bound": bound, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+         "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "measured_frac": mfrac,
+         "launches": kp["launches"], "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": alg}
+    if timing:
+        r["timing"] = timing
+    return r
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,7 +90,7 @@ def parse():
     # a process's first calls include a one-off stall of several ms (once, somewhere in
     # the first dozen calls, whatever the call pattern): warm up past it
     ap.add_argument("--warmup", type=int, default=15)
-    ap.add_argument("--workload", default="sbm_10k",
+    ap.add_argument("--workload", default="pareto_100k",
                     choices=["planted_1k", "sbm_10k", "pareto_100k", "smallcut_100k", "batch_256", "p1_sweep",
                              "serve_64"])
     ap.add_argument("--serve-seconds", type=float, default=30.0,
@@ -171,7 +198,6 @@ def bench_batch(args):
     bcpp.profile_enable(False)
     kern = max((k for k in prof if k != "other"), key=lambda k: prof[k]["ms"])
     kp = prof[kern]
-    achieved = kp["alg_bytes"] / (kp["ms"] * 1e-3) / 1e9 if kp["ms"] > 0 else 0.0
     res = {
         "metric": "exact-BC TEPS (|S|*m/s), Brandes++ batched, 1 GPU",
         "value": units / t_pp, "unit": "TEPS", "n_gpus": 1, "steps": args.steps,
@@ -179,13 +205,7 @@ def bench_batch(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64/f64", "data": "synthetic",
         "config": {"workload": "batch_256", "graphs": len(gs), "n": int(sum(g.n for g in gs)),
                    "m": int(sum(g.m for g in gs)), "targets": int(sum(len(g.S) for g in gs))},
-        "roofline": {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": measured_traffic("batch_256", kern),
-                     "alg_bytes_per_launch": kp["alg_bytes"] / max(kp["launches"], 1),
-                     "launches": kp["launches"],
-                     "avg_launch_us": kp["ms"] * 1e3 / max(kp["launches"], 1),
-                     "timing": "HIP events on eager runs of the replayed launches"},
+        "roofline": roofline_entry("batch_256", kern, kp, "HIP events on eager runs of the replayed launches"),
         "kernels_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
         "eager_ms_per_step": t_eager * 1e3,
         "plain": {"value": units / t_plain, "unit": "TEPS", "ms_per_step": t_plain * 1e3},
@@ -260,6 +280,11 @@ def bench_serve(args):
                                    seconds=warm + args.serve_seconds)
     srv = bcpp.Server(96 << 30, max_inflight=64)
     gids = [srv.add_graph(g) for g in pool]
+    # a seeded 1% (at least 20) of the measured window's queries, kept for the oracle
+    measured = [i for i, q in enumerate(stream) if q[0] >= warm]
+    ns_check = min(len(measured), max(20, -(-len(measured) // 100)))
+    check = set(np.random.default_rng(1406).choice(measured, ns_check, replace=False).tolist())
+    kept = {}
     t0 = time.perf_counter()
     out = {}
     lat, units_done, last_done = [], 0.0, 0.0
@@ -274,10 +299,10 @@ def bench_serve(args):
             t = srv.submit(gids[gi], S)
             if t is None:  # queue full: retry on the next pass
                 break
-            out[t] = (ts, pool[gi].n, float(len(S)) * pool[gi].m)
+            out[t] = (ts, pool[gi].n, float(len(S)) * pool[gi].m, i)
             i += 1
         for t in list(out):
-            ts, n, units = out[t]
+            ts, n, units, qi = out[t]
             try:
                 r = srv.poll(t, n)
             except bcpp.BcError as e:
@@ -289,6 +314,8 @@ def bench_serve(args):
                 continue
             tdone = time.perf_counter() - t0
             del out[t]
+            if qi in check:
+                kept[qi] = r
             if ts >= warm:
                 lat.append((tdone - ts) * 1e3)
                 units_done += units
@@ -300,6 +327,28 @@ def bench_serve(args):
         time.sleep(0.0005)
     st = srv.stats()
     srv.close()
+    # outside the measured window: the sample against the oracle (within 1e-9)
+    import concurrent.futures as cf
+
+    import oracle
+
+    L = oracle.lib()
+    done_check = sorted(kept)
+
+    def rel_err(qi):
+        ts, gi, S = stream[qi]
+        want = oracle.bc(pool[gi], S, L=L)
+        got = kept[qi]
+        err = np.abs(got - want) / np.maximum(np.abs(want), 1e-300)
+        err[want == 0] = 0
+        return float(err.max(initial=0.0)) if np.array_equal(got == 0, want == 0) else float("inf")
+
+    with cf.ThreadPoolExecutor(16) as ex:
+        errs = list(ex.map(rel_err, done_check))
+    oracle_check = {"sample": len(check), "checked": len(done_check),
+                    "mismatches": int(sum(e > 1e-9 for e in errs)),
+                    "max_rel_err": max(errs, default=0.0), "tolerance": 1e-9,
+                    "how": "seeded 1% (at least 20) of the measured window's queries, CPU oracle"}
     lat = np.array(lat) if lat else np.zeros(1)
     window = max(last_done - warm, 1e-9)
     res = {
@@ -311,7 +360,7 @@ def bench_serve(args):
                    "measured_s": args.serve_seconds, "queries": int(len(lat)),
                    "failed": int(failed), "failures": reasons},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-        "server": st,
+        "server": st, "oracle_check": oracle_check,
     }
     print(json.dumps(res), flush=True)
 
@@ -393,23 +442,24 @@ def main():
             "dijkstra_sk_sources": sk_stats["dsk_sources"],
         },
     }
-    # roofline of the dominant kernel (most time over the timed steps)
+    # roofline of the dominant kernel (most time over the timed steps), and of every
+    # kernel kind that ran, each with its share of the step
     kern = max((k for k in prof if k not in ("other",)), key=lambda k: prof[k]["ms"])
-    kp = prof[kern]
-    achieved = kp["alg_bytes"] / (kp["ms"] * 1e-3) / 1e9 if kp["ms"] > 0 else 0.0
-    res["roofline"] = {
-        "kernel": kern,
-        "bound": "hbm",
-        "achieved": achieved,
-        "peak": PEAK_HBM_GBS,
-        "unit": "GB/s",
-        "frac": achieved / PEAK_HBM_GBS,
-        "traffic": measured_traffic(args.workload, kern),
-        "launches": kp["launches"],
-        "avg_launch_us": kp["ms"] * 1e3 / max(kp["launches"], 1),
-        "alg_bytes_per_launch": kp["alg_bytes"] / max(kp["launches"], 1),
-    }
+    res["roofline"] = roofline_entry(args.workload, kern, prof[kern])
+    res["kernels"] = {k: dict(roofline_entry(args.workload, k, v), ms_per_step=v["ms"] / args.steps)
+                      for k, v in prof.items() if v["launches"] > 0 and k in ("resident", "dijkstra_sk")}
     res["kernels_ms_per_step"] = {k: v["ms"] / args.steps for k, v in prof.items()}
+    # where a Brandes++ step goes: the partition call (P', frontiers, Dijkstra_SK,
+    # assembly; host work included) and the Brandes_SK + Centrality call, timed apart
+    sk_keep = state["sk"]
+    t_part = timed(lambda: bcpp.partition_sk(G, part, g.k, S_host), args.steps, 2, sync)
+    t_bsk = timed(lambda: bcpp.brandes_pp_dev(G, sk_keep, out), args.steps, 2, sync)
+    res["pp_breakdown_ms"] = {
+        "partition_sk": t_part * 1e3,
+        "brandes_sk_centrality": t_bsk * 1e3,
+        "dijkstra_sk_kernel": prof["dijkstra_sk"]["ms"] / args.steps,
+        "brandes_sk_kernel": prof["resident"]["ms"] / args.steps,
+    }
     if not args.no_plain:
         t_plain = timed(plain_step, args.steps, args.warmup, sync)
         res["plain"] = {"value": units / t_plain, "unit": "TEPS", "ms_per_step": t_plain * 1e3}
@@ -423,19 +473,9 @@ def main():
         pk = bcpp.profile_read()["resident"]
         bcpp.profile_enable(False)
         if pk["ms"] > 0 and pk["launches"] > 0:
-            ach = pk["alg_bytes"] / (pk["ms"] * 1e-3) / 1e9
-            res["plain"]["roofline"] = {
-                "kernel": "resident",
-                "bound": "hbm",
-                "achieved": ach,
-                "peak": PEAK_HBM_GBS,
-                "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS,
-                "launches": pk["launches"],
-                "avg_launch_us": pk["ms"] * 1e3 / pk["launches"],
-                "alg_bytes_per_launch": pk["alg_bytes"] / pk["launches"],
-                "timing": "HIP events on a profiled pass of the same steps after the timed ones",
-            }
+            res["plain"]["roofline"] = roofline_entry(
+                args.workload + ":plain", "resident", pk,
+                "HIP events on a profiled pass of the same steps after the timed ones")
         res["pp_over_plain"] = t_plain / t_pp
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)

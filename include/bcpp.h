@@ -92,9 +92,14 @@ void bc_graph_destroy(bc_graph* g);
 
 /* --------------------------------------------------- the Brandes subroutine ---- */
 
-/* Shortest-path distances and path counts from each source (Sec. 3, eq. parentsall).
- * d: [nsrc * n] row-major by source, -1 = unreachable. sigma: [nsrc * n], 0 =
- * unreachable. Either output may be NULL. BC_E_OVERFLOW if a count reaches 2^64. */
+/* Shortest-path distances and path counts from each source (Sec. 3, eq. parentsall),
+ * as the kernel that computes the scores finds them: the source groups of a plain
+ * Brandes pass over src (src flagged as targets) run their forward and backward
+ * sweeps and write each source's d and sigma out after its forward sweep. (With the
+ * environment variable BCPP_RESIDENT=0 the multi-group engine computes them.) src may
+ * repeat a node. d: [nsrc * n] row-major by source, -1 = unreachable. sigma:
+ * [nsrc * n], 0 = unreachable. Either output may be NULL. BC_E_OVERFLOW if a count
+ * reaches 2^64. */
 int bc_sssp_counts(const bc_graph* g, const int32_t* src, int32_t nsrc, int64_t* d,
                    uint64_t* sigma);
 
@@ -148,8 +153,11 @@ int bc_skeleton_export(const bc_skeleton* sk, int32_t* nodes, int64_t* row_ptr,
                        uint32_t* tab_d, uint64_t* tab_sigma);
 
 /* Distances and multiplicity-weighted path counts on G_SK (Sec. 5, eq. multiparents)
- * from skeleton nodes src (original ids, each a skeleton node) to every skeleton node.
- * d, sigma: [nsrc * n_sk] in skeleton order. */
+ * from skeleton nodes src (original ids, each a skeleton node) to every skeleton node,
+ * as Brandes_SK finds them: the source groups of a Brandes_SK + Centrality pass over
+ * src run their sweeps and write each source's d and sigma out after its forward
+ * sweep (BCPP_RESIDENT=0: the multi-group engine). d, sigma: [nsrc * n_sk] in
+ * skeleton order. */
 int bc_skeleton_sssp_counts(const bc_skeleton* sk, const int32_t* src, int32_t nsrc,
                             int64_t* d, uint64_t* sigma);
 
@@ -223,7 +231,10 @@ void bc_server_destroy(bc_server* s);
 #define BC_K_RESIDENT 7 /* the LDS-resident kernel: 32 bytes per (source, arc) and 20 per
                          * (source, node) reached, the per-source state a traversal from
                          * memory would move (Sec. 3 forward and backward sweeps) */
-#define BC_K_COUNT 8
+#define BC_K_DIJKSTRA_SK 8 /* the same kernel running Dijkstra_SK groups (forward sweep
+                            * only, restricted counts): 12 bytes per (source, arc) and 12
+                            * per (source, node) reached */
+#define BC_K_COUNT 9
 void bc_profile_enable(int on);
 /* Totals since the last reset: launches, summed milliseconds, and the algorithmic
  * bytes the kernel's work units account for (see the kernel's documentation). */

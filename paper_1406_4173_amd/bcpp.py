@@ -21,7 +21,7 @@ BC_ENGINE_ONLY = 0x2
 BC_NO_GRAPH = 0x4
 BC_BATCH_PLAIN = 0x0
 BC_BATCH_PP = 0x100
-KERNELS = ["select", "settle", "push", "backward", "centrality", "sched", "other", "resident"]
+KERNELS = ["select", "settle", "push", "backward", "centrality", "sched", "other", "resident", "dijkstra_sk"]
 
 _P = ctypes.c_void_p
 _i32 = ctypes.c_int32

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 
 #include "engine.h"
@@ -93,6 +94,28 @@ __global__ void k_mark_targets(const int32_t* __restrict__ S, int32_t nS,
                                uint8_t* __restrict__ flag) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nS) flag[S[i]] = (uint8_t)NF_TARGET;
+}
+
+// Zero bytes [p, p + bytes): 16-byte stores where the address is aligned, bytes at the
+// ends. (A fill kernel rather than a memset, so that a captured graph may hold it.)
+__global__ void k_zero_bytes(unsigned char* __restrict__ p, int64_t head, int64_t nvec, int64_t bytes) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride)
+        reinterpret_cast<uint4*>(p + head)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bytes; i += stride)
+        if (i < head || i >= head + nvec * 16) p[i] = 0;
+}
+
+int zero_device(hipStream_t s, void* p, size_t bytes) {
+    if (!bytes) return BC_OK;
+    unsigned char* c = (unsigned char*)p;
+    const int64_t head = std::min<int64_t>((int64_t)bytes, (int64_t)((16 - ((uintptr_t)c & 15)) & 15));
+    const int64_t nvec = ((int64_t)bytes - head) / 16;
+    const int64_t work = std::max<int64_t>(nvec, std::min<int64_t>((int64_t)bytes, 4096));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_zero_bytes, dim3(grid), dim3(256), 0, s, c, head, nvec, (int64_t)bytes);
+    BC_HIP(hipGetLastError());
+    return BC_OK;
 }
 
 // ------------------------------------------------------------- validation ------
@@ -225,19 +248,22 @@ int graph_create(const bc_csr* csr, hipStream_t stream, bc_graph** out) {
 
 // ------------------------------------------------------------ plain Brandes ----
 
-// Plain target-set Brandes over g for the host-validated targets S (host copy);
-// S_dev (device copy or null) is used to mark targets. Scores go to out_dev.
-// Plain Brandes with the LDS-resident kernel: groups of resident_sources_per_group(nS)
-// targets over the whole graph.
-int plain_resident(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, double scale,
-                   double* out_dev) {
+// Plain target-set Brandes with the resident kernel: groups of
+// resident_sources_per_group(nS) of the host-validated targets S (host copy) over the
+// whole graph; S_dev (device copy or null) marks the targets. Scores go to out_dev.
+// With grow, W is sized to run every group at once. Without, W keeps its capacity and
+// the groups run in waves of as many as fit; each wave's scores are added to the
+// previous waves' (the same groups and sources, so the same d, sigma and per-group
+// dependencies; the sum of the group rows only regroups). Nothing here clears memory
+// with a memset: fill kernels do.
+int plain_resident(bc_graph* g, Arena& W, bool grow, const int32_t* S, int32_t nS, const int32_t* S_dev,
+                   double scale, double* out_dev) {
     hipStream_t s = g->stream;
     const int32_t n = g->n;
     const int32_t spg = resident_sources_per_group(nS);
     const int32_t ngroups = (nS + spg - 1) / spg;
     std::vector<GroupDesc> groups(ngroups);
-    size_t need = resident_launch_bytes(ngroups) + (size_t)n + (size_t)nS * 4 + 2 * ((size_t)ngroups * 8 + 256) +
-                  65536;
+    size_t per_group = 0;
     for (int32_t j = 0; j < ngroups; ++j) {
         GroupDesc& G = groups[j];
         G.lo = 0;
@@ -249,17 +275,29 @@ int plain_resident(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_d
         const int32_t first = j * spg;
         G.nsrc = std::min(spg, nS - first);
         for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? S[first + b] : -1;
-        need += resident_group_bytes(G);
+        per_group = std::max(per_group, resident_group_bytes(G) + resident_launch_bytes(1) + 2 * 8);
     }
-    BC_TRY(g->work.reserve(need));
-    uint8_t* d_flag = g->work.take<uint8_t>(n);
+    // shared by all waves: target flags and (host targets) their device copy
+    const size_t fixed = ((size_t)n + 255) / 256 * 256 + ((size_t)nS * 4 + 255) / 256 * 256 + 8 * 256 + 65536;
+    if (grow) {
+        BC_TRY(W.reserve(fixed + (size_t)ngroups * per_group));
+    } else {
+        W.reset();
+        if (fixed + per_group > W.cap)
+            return fail(BC_E_NOMEM, "plain: one source group over " + std::to_string(n) + " nodes needs " +
+                                        std::to_string(fixed + per_group) + " bytes of workspace, more than the " +
+                                        std::to_string(W.cap) + " available");
+    }
+    uint8_t* d_flag = W.take<uint8_t>(n);
     const int32_t* d_S = S_dev;
     if (!d_S) {
-        int32_t* t = g->work.take<int32_t>(nS);
+        int32_t* t = W.take<int32_t>(nS);
+        if (!t) return fail(BC_E_NOMEM, "plain: workspace too small");
         BC_HIP(hipMemcpyAsync(t, S, (size_t)nS * 4, hipMemcpyHostToDevice, s));
         d_S = t;
     }
-    BC_HIP(hipMemsetAsync(d_flag, 0, n, s));
+    if (!d_flag) return fail(BC_E_NOMEM, "plain: workspace too small");
+    BC_TRY(zero_device(s, d_flag, (size_t)n));
     hipLaunchKernelGGL(k_mark_targets, dim3((nS + 255) / 256), dim3(256), 0, s, d_S, nS, d_flag);
     BC_HIP(hipGetLastError());
     for (GroupDesc& G : groups) {
@@ -268,11 +306,19 @@ int plain_resident(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_d
         G.g.len = g->d_len;
         G.g.nflag = d_flag;
         G.g.twin = g->d_twin;
-        if (!resident_alloc(g->work, G)) return fail(BC_E_NOMEM, "plain: workspace too small");
     }
-    BC_TRY(run_resident(s, g->work, groups));
-    return reduce_scores(s, g->work, groups, n, nullptr, nullptr, nullptr, nullptr, scale, out_dev,
-                         false);
+    const size_t mark = W.used;
+    const int32_t per_wave =
+        (int32_t)std::max<size_t>(1, std::min<size_t>(ngroups, (W.cap - std::min(W.cap, mark + 65536)) / per_group));
+    for (int32_t g0 = 0; g0 < ngroups; g0 += per_wave) {
+        W.used = mark;
+        std::vector<GroupDesc> wave(groups.begin() + g0, groups.begin() + std::min(ngroups, g0 + per_wave));
+        for (GroupDesc& G : wave)
+            if (!resident_alloc(W, G)) return fail(BC_E_NOMEM, "plain: workspace too small");
+        BC_TRY(run_resident(s, W, wave));
+        BC_TRY(reduce_scores(s, W, wave, n, nullptr, nullptr, nullptr, nullptr, scale, out_dev, g0 > 0));
+    }
+    return BC_OK;
 }
 
 int plain_run(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, uint32_t flags,
@@ -282,11 +328,12 @@ int plain_run(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, u
     const double scale = (flags & BC_ORDERED) ? 1.0 : 0.5;
     if (n == 0) return BC_OK;
     if (nS < 2) {
-        BC_HIP(hipMemsetAsync(out_dev, 0, (size_t)n * 8, s));
+        BC_TRY(zero_device(s, out_dev, (size_t)n * 8));
         BC_HIP(hipStreamSynchronize(s));
         return BC_OK;
     }
-    if (!(flags & BC_ENGINE_ONLY) && resident_takes(n)) return plain_resident(g, S, nS, S_dev, scale, out_dev);
+    if (!(flags & BC_ENGINE_ONLY) && resident_takes(n))
+        return plain_resident(g, g->work, true, S, nS, S_dev, scale, out_dev);
     const int64_t max_dist = (int64_t)(n - 1) * g->maxw;
     const int64_t steps = max_steps_bound(n, LANES, max_dist);
     const int32_t ngroups = (nS + LANES - 1) / LANES;
@@ -343,6 +390,107 @@ int plain_run(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, u
     return BC_OK;
 }
 
+// Run resident groups whose forward state is exported (GF_EXPORT) and copy d and sigma
+// out, source-major over a range of n nodes, as the count entry points report them.
+// Group j holds the call's sources [j * spg, j * spg + nsrc_j). The groups run in chunks
+// whose output rows fit about 1 GiB. make(g0, g1) gives the descriptors of groups
+// [g0, g1) without buffers; bind(W, groups), after the workspace is reserved, takes what
+// the chunk's groups share from W and fills in their graph pointers.
+int run_exported(hipStream_t s, Arena& W, int32_t n, int32_t nsrc, int32_t spg,
+                 const std::function<std::vector<GroupDesc>(int32_t, int32_t)>& make,
+                 const std::function<int(Arena&, std::vector<GroupDesc>&)>& bind, size_t bind_bytes,
+                 int64_t* d, uint64_t* sigma) {
+    const int32_t ngroups = (nsrc + spg - 1) / spg;
+    const int64_t row_bytes = (int64_t)n * 12;
+    const int32_t per_chunk = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>(ngroups, ((int64_t)1 << 30) / std::max<int64_t>(row_bytes * spg, 1)));
+    std::vector<uint32_t> hd;
+    std::vector<uint64_t> hs;
+    for (int32_t g0 = 0; g0 < ngroups; g0 += per_chunk) {
+        const int32_t g1 = std::min(ngroups, g0 + per_chunk);
+        std::vector<GroupDesc> groups = make(g0, g1);
+        int64_t rows = 0;
+        size_t need = resident_launch_bytes(groups.size()) + bind_bytes + 4 * 65536;
+        for (const GroupDesc& G : groups) {
+            need += resident_group_bytes(G) + 2 * 256;
+            rows += G.nsrc;
+        }
+        need += (size_t)rows * (size_t)row_bytes + 512;
+        BC_TRY(W.reserve(need));
+        BC_TRY(bind(W, groups));
+        uint32_t* od = W.take<uint32_t>((size_t)std::max<int64_t>(rows * n, 1));
+        uint64_t* os = W.take<uint64_t>((size_t)std::max<int64_t>(rows * n, 1));
+        if (!od || !os) return fail(BC_E_NOMEM, "counts: workspace too small");
+        int64_t r = 0;
+        for (GroupDesc& G : groups) {
+            G.flags |= GF_EXPORT;
+            G.odist = od + r * n;
+            G.osig = os + r * n;
+            r += G.nsrc;
+            if (!resident_alloc(W, G)) return fail(BC_E_NOMEM, "counts: workspace too small");
+        }
+        BC_TRY(run_resident(s, W, groups));
+        hd.resize((size_t)(rows * n));
+        hs.resize((size_t)(rows * n));
+        if (rows * n) {
+            BC_HIP(hipMemcpyAsync(hd.data(), od, hd.size() * 4, hipMemcpyDeviceToHost, s));
+            BC_HIP(hipMemcpyAsync(hs.data(), os, hs.size() * 8, hipMemcpyDeviceToHost, s));
+            BC_HIP(hipStreamSynchronize(s));
+        }
+        const int64_t first = (int64_t)g0 * spg * n;
+        for (int64_t i = 0; i < rows * n; ++i) {
+            const uint32_t t = hd[(size_t)i];
+            if (d) d[first + i] = (t == INF32) ? -1 : (int64_t)t;
+            if (sigma) sigma[first + i] = (t == INF32) ? 0 : hs[(size_t)i];
+        }
+    }
+    return BC_OK;
+}
+
+// Path counts of G from the kernel that produces every score: the groups of a plain
+// Brandes pass over the same sources (resident_sources_per_group each, the sources
+// flagged as targets, forward and backward sweeps), which also export each source's
+// forward state.
+static int sssp_resident(bc_graph* g, const int32_t* src, int32_t nsrc, int64_t* d, uint64_t* sigma) {
+    hipStream_t s = g->stream;
+    const int32_t n = g->n;
+    const int32_t spg = resident_sources_per_group(nsrc);
+    auto make = [&](int32_t g0, int32_t g1) {
+        std::vector<GroupDesc> groups(g1 - g0);
+        for (int32_t j = g0; j < g1; ++j) {
+            GroupDesc& G = groups[j - g0];
+            G.lo = 0;
+            G.hi = n;
+            G.arc_lo = 0;
+            G.arcs = g->nnz;
+            G.flags = GF_BACKWARD;
+            G.ring_len = g->maxw + 1;
+            const int32_t first = j * spg;
+            G.nsrc = std::min(spg, nsrc - first);
+            for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? src[first + b] : -1;
+        }
+        return groups;
+    };
+    auto bind = [&](Arena& W, std::vector<GroupDesc>& groups) -> int {
+        uint8_t* d_flag = W.take<uint8_t>(n);
+        int32_t* t = W.take<int32_t>(nsrc);
+        if (!d_flag || !t) return fail(BC_E_NOMEM, "counts: workspace too small");
+        BC_HIP(hipMemcpyAsync(t, src, (size_t)nsrc * 4, hipMemcpyHostToDevice, s));
+        BC_HIP(hipMemsetAsync(d_flag, 0, n, s));
+        hipLaunchKernelGGL(k_mark_targets, dim3((nsrc + 255) / 256), dim3(256), 0, s, t, nsrc, d_flag);
+        BC_HIP(hipGetLastError());
+        for (GroupDesc& G : groups) {
+            G.g.row_ptr = g->d_row_ptr;
+            G.g.col = g->d_col;
+            G.g.len = g->d_len;
+            G.g.nflag = d_flag;
+            G.g.twin = g->d_twin;
+        }
+        return BC_OK;
+    };
+    return run_exported(s, g->work, n, nsrc, spg, make, bind, (size_t)n + (size_t)nsrc * 4 + 512, d, sigma);
+}
+
 int sssp_run(const bc_graph* gc, const int32_t* src, int32_t nsrc, int64_t* d, uint64_t* sigma) {
     bc_graph* g = const_cast<bc_graph*>(gc);
     hipStream_t s = g->stream;
@@ -351,6 +499,7 @@ int sssp_run(const bc_graph* gc, const int32_t* src, int32_t nsrc, int64_t* d, u
     for (int32_t i = 0; i < nsrc; ++i)
         if (src[i] < 0 || src[i] >= n) return fail(BC_E_INVAL, "source out of range");
     if (nsrc == 0 || n == 0) return BC_OK;
+    if (resident_takes(n)) return sssp_resident(g, src, nsrc, d, sigma);
     const int64_t steps = max_steps_bound(n, LANES, (int64_t)(n - 1) * g->maxw);
     const int32_t ngroups = (nsrc + LANES - 1) / LANES;
     std::vector<uint32_t> ht((size_t)n * LANES);

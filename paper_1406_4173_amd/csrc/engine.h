@@ -12,6 +12,8 @@
 // engine iteration, so groups of different graphs, sizes and phases share launches.
 #pragma once
 
+#include <functional>
+
 #include "common.h"
 
 namespace bcpp {
@@ -23,6 +25,7 @@ enum : uint32_t {
     GF_BACKWARD = 2u,  // run the dependency sweep after the forward search
     GF_CENT = 4u,      // then the interior-node Centrality pass over the tables
     GF_UNIT = 8u,      // every arc has length 1 (plain stores replace atomics)
+    GF_EXPORT = 16u,   // resident backward groups: also write d and sigma after the forward
 };
 
 enum : int32_t { PH_DONE = 0, PH_FWD = 1, PH_BWD = 2, PH_CENT = 3 };
@@ -81,6 +84,10 @@ struct GroupDesc {
     // resident backward groups: the forward's per-wave queue record and step distances
     int32_t* rlist = nullptr;
     uint32_t* steps = nullptr;  // [hi-lo+1]
+    // GF_EXPORT: d and sigma of every node of the range after each source's forward
+    // sweep, source-major: row b (the group's b-th source) is odist[b * (hi-lo) ..]
+    uint32_t* odist = nullptr;
+    uint64_t* osig = nullptr;
     int32_t src[LANES];      // source node ids of g, -1 = unused lane
 };
 
@@ -180,6 +187,8 @@ int reduce_launch(hipStream_t s, const ReducePtrs& R, int32_t n, const int32_t* 
 }  // namespace bcpp
 
 namespace bcpp {
+// Zero `bytes` bytes of device memory at p on stream s with a fill kernel.
+int zero_device(hipStream_t s, void* p, size_t bytes);
 // Device bytes an Engine needs for `slots` groups over `positions` scan positions.
 size_t engine_bytes(int32_t slots, int64_t positions);
 
@@ -220,8 +229,19 @@ struct ResidentLaunch {
     const RCtx* d_ctx = nullptr;
     const int32_t* d_src = nullptr;
     uint32_t* d_err = nullptr;
+    // profiler kind of the launches: BC_K_DIJKSTRA_SK when every group is forward-only
+    int kind = BC_K_RESIDENT;
 };
 int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& groups, ResidentLaunch* L);
 int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, size_t n, ResidentLaunch* L);
 int resident_launch(hipStream_t s, const ResidentLaunch& L);
+// Distances and path counts from resident groups run with GF_EXPORT, copied out
+// source-major over a range of n nodes (-1 and 0 where a node is unreachable).
+// Group j holds the sources [j * spg, j * spg + nsrc_j) of the call. make(g0, g1)
+// gives the descriptors of groups [g0, g1); bind(W, groups), once the workspace is
+// reserved (bind_bytes of it for bind), takes what they share from W and completes them.
+int run_exported(hipStream_t s, Arena& W, int32_t n, int32_t nsrc, int32_t spg,
+                 const std::function<std::vector<GroupDesc>(int32_t, int32_t)>& make,
+                 const std::function<int(Arena&, std::vector<GroupDesc>&)>& bind, size_t bind_bytes,
+                 int64_t* d, uint64_t* sigma);
 }  // namespace bcpp

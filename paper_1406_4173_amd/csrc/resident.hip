@@ -349,6 +349,8 @@ struct RGroup {
     uint32_t* gtb;    // [tw] their tight-arc bitmap (state in device memory only)
     int32_t* rlist;   // backward groups: per-wave record of the forward's queues
     uint32_t* steps;  // backward groups: distance of each forward step
+    uint32_t* odist;  // GF_EXPORT: [nsrc][hi-lo] d(s,v) after each source's forward sweep
+    uint64_t* osig;   //            [nsrc][hi-lo] sigma(s,v)
 };
 
 namespace {
@@ -370,6 +372,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                                 const int32_t* __restrict__ srcs,
                                                 uint32_t* __restrict__ err,
                                                 unsigned long long* __restrict__ prof) {
+    // prof: null, or this launch's counter of algorithmic bytes
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ uint32_t fwd_next[3];  // rotating: step k writes [k%3], clears [(k+1)%3]
     __shared__ uint32_t ovf_flag;
@@ -684,6 +687,16 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             D = nx;
         }
         if (ovf) ovf_flag = 1u;
+        if (bwd && (R.flags & GF_EXPORT)) {
+            // (the last step ended with a barrier: every count is final; the barrier
+            // after the interior rows orders these reads before the backward's writes)
+            GAS uint32_t* __restrict__ od = gas(R.odist) + (int64_t)b * n;
+            GAS uint64_t* __restrict__ os = gas(R.osig) + (int64_t)b * n;
+            for (int32_t v = tid; v < n; v += T) {
+                od[v] = D_(v);
+                os[v] = S_(v);
+            }
+        }
         if (!bwd) {
             // (the last step ended with a barrier: every count is final)
             for (int32_t v = tid; v < n; v += T) {
@@ -861,7 +874,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     if (ovf_flag && tid == 0) atomicOr(err, ERR_OVERFLOW);
     if (prof) {
         bytes = wsum_u64(bytes);
-        if (lane == 0 && bytes) atomicAdd(&prof[BC_K_RESIDENT], bytes);
+        if (lane == 0 && bytes) atomicAdd(prof, bytes);
     }
 }
 
@@ -1038,6 +1051,9 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
     std::vector<int32_t> src;
     std::map<std::pair<const void*, const void*>, int32_t> ctx_of;
     const SizeClasses sc;
+    bool all_forward = ng > 0;
+    for (size_t i = 0; i < ng; ++i) all_forward = all_forward && !(groups[i]->flags & GF_BACKWARD);
+    L->kind = all_forward ? BC_K_DIJKSTRA_SK : BC_K_RESIDENT;
     for (size_t i = 0; i < ng; ++i) {
         const GroupDesc& G = *groups[i];
         const int64_t range = (int64_t)G.hi - G.lo;
@@ -1094,6 +1110,10 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         r.gtb = tw > 0 && c == 3 ? G.gtb : nullptr;
         r.rlist = G.rlist;
         r.steps = G.steps;
+        r.odist = G.odist;
+        r.osig = G.osig;
+        if ((G.flags & GF_EXPORT) && (!G.odist || !G.osig || !(G.flags & GF_BACKWARD)))
+            return fail(BC_E_INVAL, "resident: export needs a backward group and output rows");
         if ((G.flags & GF_BACKWARD) && (!G.rlist || !G.steps))
             return fail(BC_E_INVAL, "resident: no record buffers for a backward group");
         cls[c].push_back(r);
@@ -1102,7 +1122,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
     RCtx* d_ctx = a.take<RCtx>(std::max<size_t>(ctx.size(), 1));
     int32_t* d_src = a.take<int32_t>(std::max<size_t>(src.size(), 1));
     if (!L->d_err || !d_ctx || !d_src) return fail(BC_E_NOMEM, "resident: workspace too small");
-    BC_HIP(hipMemsetAsync(L->d_err, 0, sizeof(uint32_t), s));
+    BC_TRY(zero_device(s, L->d_err, sizeof(uint32_t)));
     if (!ctx.empty()) BC_HIP(hipMemcpyAsync(d_ctx, ctx.data(), ctx.size() * sizeof(RCtx), hipMemcpyHostToDevice, s));
     if (!src.empty()) BC_HIP(hipMemcpyAsync(d_src, src.data(), src.size() * 4, hipMemcpyHostToDevice, s));
     L->d_ctx = d_ctx;
@@ -1125,10 +1145,10 @@ int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& group
 }
 
 int resident_launch(hipStream_t s, const ResidentLaunch& L) {
-    unsigned long long* prof = profiler().on ? profiler().d_bytes : nullptr;
+    unsigned long long* prof = profiler().on && profiler().d_bytes ? profiler().d_bytes + L.kind : nullptr;
     for (int c = 3; c >= 0; --c) {
         if (!L.count[c]) continue;
-        KTimer kt(BC_K_RESIDENT, s);
+        KTimer kt(L.kind, s);
         const dim3 grid((unsigned)L.count[c]);
         if (c == 3)
             hipLaunchKernelGGL((k_resident<1024, true>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,

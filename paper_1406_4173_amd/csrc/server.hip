@@ -13,6 +13,7 @@
 // when it runs alone (its groups hold the same sources in the same order), so its
 // result does not depend on what else is in flight.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -32,7 +33,8 @@ namespace bcpp {
 // First-fit allocator over one device buffer (the HBM budget).
 struct Pool {
     char* base = nullptr;
-    size_t cap = 0, used = 0, peak = 0;
+    size_t cap = 0, used = 0;
+    std::atomic<size_t> peak{0};  // read by bc_server_stats_get on other threads
     std::map<size_t, size_t> free_;  // offset -> size
 
     void init(char* b, size_t c) {
@@ -40,7 +42,8 @@ struct Pool {
         cap = c;
         free_.clear();
         free_[0] = c;
-        used = peak = 0;
+        used = 0;
+        peak = 0;
     }
     static size_t round(size_t x) { return (x + 4095) & ~size_t(4095); }
     bool alloc(size_t bytes, size_t* off) {
@@ -53,7 +56,7 @@ struct Pool {
             free_.erase(it);
             if (rest) free_[at] = rest;
             used += bytes;
-            peak = std::max(peak, used);
+            if (used > peak.load()) peak = used;
             return true;
         }
         return false;
@@ -91,7 +94,8 @@ struct Query {
     int32_t gid = 0;
     std::vector<int32_t> S;
     uint32_t flags = 0;
-    int state = Q_QUEUED;
+    // written by the loop thread, read by bc_query_poll / bc_server_stats_get
+    std::atomic<int> state{Q_QUEUED};
     int status = BC_OK;
     std::string err;
     std::vector<double> result;
@@ -291,7 +295,10 @@ static int start_bsk(bc_server* sv, Query* q, bool* started) {
         size_t need = resident_launch_bytes(groups.size()) + 2 * (groups.size() * 8 + 256) +
                       (size_t)n * 8 + 256 + 4096;
         for (const GroupDesc& G : groups) need += resident_group_bytes(G);
-        if (need > sv->pool.cap) return fail(BC_E_NOMEM, "server: query needs more than the configured budget");
+        // the query holds its skeleton store meanwhile: if both never fit together it
+        // can never start, whatever else finishes
+        if (need + (q->store.live ? Pool::round(q->store.size) : 0) > sv->pool.cap)
+            return fail(BC_E_NOMEM, "server: query needs more than the configured budget");
         if (!alloc_block(sv, need, q->bsk, q->a_bsk)) return BC_E_AGAIN;
         for (GroupDesc& G : groups)
             if (!resident_alloc(q->a_bsk, G)) return fail(BC_E_NOMEM, "server: block too small");
@@ -303,15 +310,22 @@ static int start_bsk(bc_server* sv, Query* q, bool* started) {
         q->d_err = L.d_err;
         q->d_out = q->a_bsk.take<double>(std::max(n, 1));
         if (!q->d_out) return fail(BC_E_NOMEM, "server: block too small");
+        BC_HIP(hipEventCreateWithFlags(&q->ev, hipEventDisableTiming));
         hipStream_t r = next_side_stream(sv);
         BC_HIP(hipEventRecord(sv->asm_ev, s));
         BC_HIP(hipStreamWaitEvent(r, sv->asm_ev, 0));
-        BC_TRY(resident_launch(r, L));
+        // once a launch is enqueued, a later failure waits for the side stream before
+        // the caller releases the blocks the launch uses
         const double scale = (q->flags & BC_ORDERED) ? 1.0 : 0.5;
-        BC_TRY(reduce_launch(r, R, n, nullptr, nullptr, sk->d_out_idx, sk->d_out_which, scale, q->d_out,
-                             false));
-        BC_HIP(hipEventCreateWithFlags(&q->ev, hipEventDisableTiming));
-        BC_HIP(hipEventRecord(q->ev, r));
+        int rc = resident_launch(r, L);
+        if (rc == BC_OK)
+            rc = reduce_launch(r, R, n, nullptr, nullptr, sk->d_out_idx, sk->d_out_which, scale, q->d_out, false);
+        if (rc == BC_OK && hipEventRecord(q->ev, r) != hipSuccess)
+            rc = fail(BC_E_DEVICE, "server: event record failed");
+        if (rc != BC_OK) {
+            (void)hipStreamSynchronize(r);
+            return rc;
+        }
         q->state = Q_RES;
         *started = true;
         return BC_OK;
@@ -440,12 +454,17 @@ static int admit_prepared(bc_server* sv, Query* q) {
         ResidentLaunch L;
         BC_TRY(resident_upload(sv->stream, q->a_tmp, q->groups, &L));
         q->d_err = L.d_err;
+        BC_HIP(hipEventCreateWithFlags(&q->ev, hipEventDisableTiming));
         hipStream_t r = next_side_stream(sv);
         BC_HIP(hipEventRecord(sv->asm_ev, sv->stream));
         BC_HIP(hipStreamWaitEvent(r, sv->asm_ev, 0));
-        BC_TRY(resident_launch(r, L));
-        BC_HIP(hipEventCreateWithFlags(&q->ev, hipEventDisableTiming));
-        BC_HIP(hipEventRecord(q->ev, r));
+        int rc = resident_launch(r, L);
+        if (rc == BC_OK && hipEventRecord(q->ev, r) != hipSuccess)
+            rc = fail(BC_E_DEVICE, "server: event record failed");
+        if (rc != BC_OK) {
+            (void)hipStreamSynchronize(r);
+            return rc;
+        }
         q->state = Q_RDSK;
         return BC_OK;
     }
@@ -559,6 +578,15 @@ static void server_loop(bc_server* sv) {
             else if (q->state == Q_DSK || q->state == Q_BSK)
                 active.push_back(q);
         }
+        // nothing can make progress: no launch in flight and no engine group installed,
+        // so no memory will be freed, and the oldest skeleton waiting for its Brandes_SK
+        // memory cannot get it; it fails, and its store goes back to the pool
+        if (active.empty() && res_run.empty() && !bsk_wait.empty()) {
+            Query* q = bsk_wait.front();
+            bsk_wait.erase(bsk_wait.begin());
+            fail_query(sv, q, BC_E_NOMEM, "server: Brandes_SK state does not fit the budget");
+            continue;
+        }
         if (active.empty()) continue;
         // one engine step for every installed group of every admitted query
         if (sv->eng.iterate(2) != BC_OK ||
@@ -607,12 +635,6 @@ static void server_loop(bc_server* sv) {
             if (rc != BC_OK) fail_query(sv, q, rc, bc_last_error());
         }
         active.insert(active.end(), started_now.begin(), started_now.end());
-        // nothing can make progress: the oldest waiting skeleton cannot get memory
-        if (active.empty() && res_run.empty() && !bsk_wait.empty()) {
-            Query* q = bsk_wait.front();
-            bsk_wait.erase(bsk_wait.begin());
-            fail_query(sv, q, BC_E_NOMEM, "server: Brandes_SK state does not fit the budget");
-        }
     }
     // shut down: let launches in flight end before their memory is released, then fail
     // whatever is left

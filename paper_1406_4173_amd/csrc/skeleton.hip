@@ -1091,6 +1091,41 @@ int sk_sssp_run(const bc_skeleton* sk, const int32_t* src, int32_t nsrc, int64_t
         ssrc[i] = idx[src[i]];
     }
     if (nsrc == 0 || N == 0) return BC_OK;
+    if (resident_takes(N)) {
+        // the groups of a Brandes_SK pass over these sources (with the Centrality pass
+        // when the skeleton has tables), exporting each source's forward state
+        const int32_t spg = resident_sources_per_group(nsrc);
+        auto make = [&](int32_t g0, int32_t g1) {
+            std::vector<GroupDesc> groups(g1 - g0);
+            for (int32_t j = g0; j < g1; ++j) {
+                GroupDesc& G = groups[j - g0];
+                G.g.row_ptr = sk->d_row_ptr;
+                G.g.col = sk->d_col;
+                G.g.len = sk->d_len;
+                G.g.mult = sk_mult(sk);
+                G.g.nflag = sk->d_nflag;
+                G.g.twin = sk->d_twin;
+                G.lo = 0;
+                G.hi = N;
+                G.arc_lo = 0;
+                G.arcs = sk->m_arcs;
+                G.ring_len = sk->max_len + 1;
+                G.flags = GF_BACKWARD | (sk->n_int ? GF_CENT : 0u);
+                G.trow = sk->d_trow;
+                G.tcol = sk->d_tcol;
+                G.tlen = sk->d_tlen;
+                G.tsig = sk->d_tsig;
+                G.t_lo = 0;
+                G.tn = sk->n_int;
+                const int32_t first = j * spg;
+                G.nsrc = std::min(spg, nsrc - first);
+                for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? ssrc[first + b] : -1;
+            }
+            return groups;
+        };
+        auto bind = [](Arena&, std::vector<GroupDesc>&) -> int { return BC_OK; };
+        return run_exported(s, g->work, N, nsrc, spg, make, bind, 0, d, sigma);
+    }
     const int64_t steps = max_steps_bound(N, LANES, sk->max_dist);
     std::vector<uint32_t> ht((size_t)N * LANES);
     std::vector<uint64_t> hs((size_t)N * LANES);

@@ -122,3 +122,79 @@ def test_server_budget_too_small_for_a_query(bcpp):
     assert isinstance(res[t_big], bcpp.BcError) and res[t_big].code == bcpp.BC_E_NOMEM
     assert_scores(res[t_small], oracle.bc(small, small.S))
     srv.close()
+
+
+def test_server_replay_of_the_serving_stream(bcpp):
+    """About 3 s of the serving workload's open-loop Poisson stream (200 queries/s,
+    |S| log-uniform in [16, 4096]) over 8 graphs of its pool, the largest of 45,607
+    nodes, replayed in real time. Queries with |S| >= 1,024 hold several sources per
+    group. A seeded sample of 24 finished queries (at least 6 with |S| >= 1,024 and 3
+    on graphs of 30,000 nodes or more) matches the oracle within 1e-9 and equals the
+    same query run alone (fresh graph handle, bc_partition_sk + bc_brandes_pp) bit for
+    bit; every query completes."""
+    import concurrent.futures as cf
+
+    idx = [49, 11, 7, 50, 25, 0, 1, 2]
+    full = inputs.serving_pool(64)
+    gs = [full[i] for i in idx]
+    assert max(g.n for g in gs) >= 45000
+    stream = inputs.serving_stream([g.n for g in gs], rate=200.0, seconds=3.0, seed_extra=7)
+    srv = bcpp.Server(64 << 30, max_inflight=64)
+    gids = [srv.add_graph(g) for g in gs]
+    tickets, meta = [], {}
+    t0 = time.perf_counter()
+    for ts, gi, S in stream:
+        while time.perf_counter() - t0 < ts:
+            time.sleep(0.0005)
+        t = srv.submit(gids[gi], S)
+        assert t is not None
+        tickets.append(t)
+        meta[t] = (gi, S)
+    res = wait_all(srv, tickets, {t: gs[meta[t][0]].n for t in tickets}, timeout=300.0)
+    assert all(not isinstance(r, Exception) for r in res.values())
+    st = srv.stats()
+    assert st["completed"] == len(tickets) and st["failed"] == 0
+    srv.close()
+    # the sample: cheapest oracle runs among the wide queries, the big graphs, the rest
+    cost = {t: len(meta[t][1]) * gs[meta[t][0]].m for t in tickets}
+    wide = sorted((t for t in tickets if len(meta[t][1]) >= 1024), key=cost.get)[:6]
+    big = sorted((t for t in tickets if gs[meta[t][0]].n >= 30000 and t not in wide), key=cost.get)[:3]
+    rng = np.random.default_rng(11)
+    rest = [t for t in tickets if t not in wide and t not in big and cost[t] < 2e7]
+    sample = wide + big + [rest[i] for i in rng.choice(len(rest), 24 - len(wide) - len(big), replace=False)]
+    assert len(sample) == 24 and len(wide) == 6 and len(big) == 3
+    with cf.ThreadPoolExecutor(16) as ex:
+        want = dict(zip(sample, ex.map(lambda t: oracle.bc(gs[meta[t][0]], meta[t][1]), sample)))
+    Gs = {}
+    for t in sample:
+        gi, S = meta[t]
+        assert_scores(res[t], want[t])
+        G = Gs.setdefault(gi, bcpp.Graph(gs[gi]))
+        alone = bcpp.brandes_pp(G, bcpp.partition_sk(G, gs[gi].part, gs[gi].k, S))
+        assert np.array_equal(res[t], alone), f"ticket {t}: in the mix != alone"
+
+
+def test_server_skeletons_waiting_for_memory_all_terminate(bcpp):
+    """A budget that holds a few skeletons but not every Brandes_SK state at once:
+    queries whose skeleton waits for memory while nothing else runs fail with
+    BC_E_NOMEM (a skeleton store plus its state beyond the budget fails at once);
+    every query ends, and those that complete match the oracle."""
+    rng = inputs.rng_for(inputs.SEED_BASE + 141)
+    g = inputs._community_graph(rng, 20000, 100, 8.0, 0.85, 4, "tight_budget")
+    srv = bcpp.Server(192 << 20, max_inflight=8)
+    gid = srv.add_graph(g)
+    Ss = [np.sort(rng.choice(g.n, ns, replace=False)).astype(np.int32) for ns in (1500, 40, 900, 2500, 60, 1200)]
+    tickets = [srv.submit(gid, S) for S in Ss]
+    res = wait_all(srv, tickets, {t: g.n for t in tickets}, timeout=120.0)
+    ok = 0
+    for t, S in zip(tickets, Ss):
+        r = res[t]
+        if isinstance(r, Exception):
+            assert isinstance(r, bcpp.BcError) and r.code == bcpp.BC_E_NOMEM, r
+        else:
+            assert_scores(r, oracle.bc(g, S))
+            ok += 1
+    assert ok >= 1
+    st = srv.stats()
+    assert st["completed"] + st["failed"] == len(tickets)
+    srv.close()

@@ -277,3 +277,77 @@ def test_skeleton_distance_and_count_preserving(oracle_lib):
             for b in nodes:
                 assert d[idx[a]][idx[b]] == dg[a][b], (seed, a, b)
                 assert c[idx[a]][idx[b]] == cg[a][b], (seed, a, b)
+
+
+def _interior_rebuild_mismatches(g, sk, dg, cg):
+    """Interior nodes whose d(s,v) and sigma(s,v), rebuilt from the skeleton's tables as
+    Sec. 5 Step 3 uses them (the minimum over the part's frontier f of d(s,f) + d(f,v),
+    and the sum of sigma(s,f) * sigma(f,v) over the f that attain it), differ from the
+    exact counts of G, for any target s; also frontier nodes that hold a table row and
+    entries that name a frontier of another part."""
+    fr, lab = sk["frontier"], sk["labels"]
+    bad = []
+    for v, row in sk["tables"].items():
+        if fr[v]:
+            bad.append(("frontier row", v))
+        for f, (dfv, sfv) in row.items():
+            if not fr[f] or lab[f] != lab[v] or sfv <= 0:
+                bad.append(("entry", v, f))
+    for s in (int(x) for x in g.S):
+        for v in range(g.n):
+            if fr[v] or v == s:
+                continue
+            best, cnt = None, 0
+            for f, (dfv, sfv) in sk["tables"].get(v, {}).items():
+                if dg[s][f] is None:
+                    continue
+                t = dg[s][f] + dfv
+                if best is None or t < best:
+                    best, cnt = t, cg[s][f] * sfv
+                elif t == best:
+                    cnt += cg[s][f] * sfv
+            if best != dg[s][v] or (best is not None and cnt != cg[s][v]):
+                bad.append(("rebuild", s, v))
+    return bad
+
+
+def test_skeleton_tables_rebuild_interior_counts(oracle_lib):
+    """The tables' membership and values: from every target s, the interior d(s,v) and
+    sigma(s,v) rebuilt from the tables (eq. localcentrality's minimum and sum over the
+    part's frontier) equal the exact ones of G (Floyd-Warshall counting), for every
+    interior node, on small random graphs with random partitions and targets."""
+    for seed in range(120):
+        rng = np.random.default_rng(7000 + seed)
+        n = int(rng.integers(4, 13))
+        g = inputs.random_graph(7100 + seed, n, float(rng.choice([0.25, 0.4, 0.6])),
+                                wmax=[None, 3][seed % 2], k=int(rng.integers(1, 4)),
+                                ns=int(rng.integers(1, 4)))
+        sk = oracle.skeleton(g, g.part, g.k, g.S, L=oracle_lib)
+        dg, cg = bf.floyd_warshall_counts(g)
+        assert not _interior_rebuild_mismatches(g, sk, dg, cg), seed
+
+
+def test_skeleton_tables_pin_catches_unrestricted_counts(oracle_lib, monkeypatch):
+    """The pin above fails when the tables carry unrestricted G_i path counts (paths
+    through other frontier nodes counted too) or keep frontier rows."""
+    real = oracle.dijkstra_sk
+    monkeypatch.setattr(oracle, "dijkstra_sk",
+                        lambda g, lab, fr, f, L=None: real(g, lab, np.zeros_like(fr), f, L))
+    caught = 0
+    for seed in range(120):
+        rng = np.random.default_rng(7000 + seed)
+        n = int(rng.integers(4, 13))
+        g = inputs.random_graph(7100 + seed, n, float(rng.choice([0.25, 0.4, 0.6])),
+                                wmax=[None, 3][seed % 2], k=int(rng.integers(1, 4)),
+                                ns=int(rng.integers(1, 4)))
+        sk = oracle.skeleton(g, g.part, g.k, g.S, L=oracle_lib)
+        dg, cg = bf.floyd_warshall_counts(g)
+        caught += bool(_interior_rebuild_mismatches(g, sk, dg, cg))
+    assert caught > 0
+    monkeypatch.setattr(oracle, "dijkstra_sk", real)
+    g = inputs.random_graph(7105, 10, 0.5, k=2, ns=2)
+    sk = oracle.skeleton(g, g.part, g.k, g.S, L=oracle_lib)
+    f = int(np.nonzero(sk["frontier"])[0][0])
+    sk["tables"][f] = {f: (0, 1)}
+    dg, cg = bf.floyd_warshall_counts(g)
+    assert _interior_rebuild_mismatches(g, sk, dg, cg)
