@@ -98,6 +98,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean query arrivals per second")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain Brandes line")
+    ap.add_argument("--only-plain", action="store_true",
+                    help="time plain Brandes alone (a profiling run of the plain pass; prints no line)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle sample")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -403,6 +405,10 @@ def main():
         bcpp.brandes_plain_dev(G, S_dev, out)
 
     calibration_copy(args)
+    if args.only_plain:
+        t_plain = timed(plain_step, args.steps, args.warmup, sync)
+        print(f"plain Brandes on {args.workload}: {t_plain * 1e3:.3f} ms per step", file=sys.stderr, flush=True)
+        return
 
     # timed Brandes++ steps, kernels timed with HIP events on the library's stream
     bcpp.profile_enable(True)

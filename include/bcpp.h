@@ -169,6 +169,18 @@ int bc_brandes_pp(const bc_graph* g, const bc_skeleton* sk, uint32_t flags,
 int bc_brandes_pp_dev(const bc_graph* g, const bc_skeleton* sk, uint32_t flags,
                       double* bc_out_dev);
 
+/* Brandes++All (Sec. 6, Alg. 3): the scores over all pairs of nodes (S = V) from the
+ * skeleton. For every ordered pair of parts (P_i, P_j) of part ([n] labels in [0,k)),
+ * i = j included, the skeleton is built with the nodes of P_i and P_j as singleton
+ * parts, and Brandes_SK with Centrality runs from the sources P_i, counting as
+ * destinations only the nodes of P_j (the indicator of eq. multibrandes is I[v in
+ * P_j]); the k^2 results are summed. Equal to bc_brandes_plain with S = V within the
+ * stated tolerance, for any partition. It builds k^2 skeletons and runs k * n sources,
+ * so it is much slower than bc_brandes_plain; it is the paper's all-pairs route.
+ * Flags: BC_ORDERED only. bc_out: [n] doubles (host). */
+int bc_brandes_pp_all(const bc_graph* g, const int32_t* part, int32_t k, uint32_t flags,
+                      double* bc_out);
+
 /* ---------------------------------------------------------------- batching ---- */
 
 /* Many independent graphs in one device run: each graph g_i with its own partition
@@ -197,7 +209,12 @@ void bc_batch_destroy(bc_batch* b);
  * the device (continuous batching: a query admitted later joins the running launches
  * at the next step). */
 int bc_server_create(size_t hbm_budget_bytes, int32_t max_inflight, bc_server** out);
-/* Register a graph and its partition (copied). *gid receives its id. */
+/* Register a graph and its partition (copied). *gid receives its id. Dijkstra_SK
+ * (Sec. 4) runs once here for every part of the partition as given; a query's build
+ * takes these results for the parts that hold none of its targets (their nodes,
+ * induced subgraphs and frontiers are the same in the query's P', Sec. 5 Step 1) and
+ * runs Dijkstra_SK only in the parts its targets touch. They stay in device memory,
+ * outside hbm_budget_bytes (bc_server_stats.cache_bytes). */
 int bc_server_add_graph(bc_server* s, const bc_csr* g, const int32_t* part, int32_t k,
                         int32_t* gid);
 /* Queue a Brandes++ query (S copied). BC_E_AGAIN if the queue is full. */
@@ -213,6 +230,9 @@ typedef struct bc_server_stats {
     int64_t iterations;       /* device steps issued */
     double p50_ms, p99_ms;    /* submit-to-completion latency of completed queries */
     int64_t peak_bytes;       /* peak device memory admitted */
+    int64_t cache_bytes;      /* device memory of the graphs' kept Dijkstra_SK results */
+    int64_t dsk_groups_cached;  /* Dijkstra_SK groups taken from them (parts without targets) */
+    int64_t dsk_groups_run;     /* Dijkstra_SK groups run for queries */
 } bc_server_stats;
 int bc_server_stats_get(bc_server* s, bc_server_stats* out);
 void bc_server_destroy(bc_server* s);

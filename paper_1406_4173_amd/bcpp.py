@@ -50,7 +50,8 @@ class bc_sk_stats(ctypes.Structure):
 class bc_server_stats(ctypes.Structure):
     _fields_ = [("submitted", _i64), ("completed", _i64), ("failed", _i64), ("queued", _i64),
                 ("inflight", _i64), ("iterations", _i64), ("p50_ms", ctypes.c_double),
-                ("p99_ms", ctypes.c_double), ("peak_bytes", _i64)]
+                ("p99_ms", ctypes.c_double), ("peak_bytes", _i64), ("cache_bytes", _i64),
+                ("dsk_groups_cached", _i64), ("dsk_groups_run", _i64)]
 
 
 _lib = None
@@ -83,6 +84,7 @@ def lib():
             "bc_skeleton_sssp_counts": (ctypes.c_int, [_P, _P, _i32, _P, _P]),
             "bc_brandes_pp": (ctypes.c_int, [_P, _P, _u32, _P]),
             "bc_brandes_pp_dev": (ctypes.c_int, [_P, _P, _u32, _P]),
+            "bc_brandes_pp_all": (ctypes.c_int, [_P, _P, _i32, _u32, _P]),
             "bc_batch_create": (ctypes.c_int, [_i32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
             "bc_batch_run": (ctypes.c_int, [_P, _u32, _P]),
             "bc_batch_destroy": (None, [_P]),
@@ -186,6 +188,14 @@ def brandes_plain_dev(G: Graph, S_dev, out_dev, ordered: bool = False, engine_on
                                       _flags(ordered, engine_only),
                                       ctypes.c_void_p(out_dev.data_ptr())))
     return out_dev
+
+
+def brandes_pp_all(G: Graph, part, k: int, ordered: bool = False):
+    """Brandes++All (bc_brandes_pp_all): all-pairs scores through k^2 skeletons."""
+    part = _i32a(part)
+    out = np.empty(G.n, np.float64)
+    _check(lib().bc_brandes_pp_all(G.h, _p(part), int(k), BC_ORDERED if ordered else 0, _p(out)))
+    return out
 
 
 class Skeleton:

@@ -189,6 +189,11 @@ int reduce_launch(hipStream_t s, const ReducePtrs& R, int32_t n, const int32_t* 
 namespace bcpp {
 // Zero `bytes` bytes of device memory at p on stream s with a fill kernel.
 int zero_device(hipStream_t s, void* p, size_t bytes);
+// Exclusive prefix sum out[i] = in[0] + .. + in[i-1] of n items (T = int32_t or
+// int64_t; in == out allowed), with scan_scratch_bytes(n) bytes of scratch.
+size_t scan_scratch_bytes(int64_t n);
+template <class T>
+int exclusive_scan(hipStream_t s, const T* in, T* out, int64_t n, void* scratch);
 // Device bytes an Engine needs for `slots` groups over `positions` scan positions.
 size_t engine_bytes(int32_t slots, int64_t positions);
 

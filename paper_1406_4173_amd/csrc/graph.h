@@ -38,6 +38,8 @@ struct bc_skeleton {
     bc_sk_stats stats{};
     // skeleton targets in skeleton ids (the sources of Brandes_SK), in target order
     std::vector<int32_t> h_src;
+    // skeleton id of every target, in target order (-1: an isolated target)
+    std::vector<int32_t> h_target_sk;
     // device arrays (all in `store`)
     int64_t* d_row_ptr = nullptr;  // [n_sk+1]
     int32_t* d_col = nullptr;      // [m_arcs]

@@ -85,6 +85,21 @@ struct Block {
     bool live = false;
 };
 
+// Dijkstra_SK results of a registered graph's parts, kept from one build without
+// targets. A part that holds no target of a query has the same nodes, induced
+// subgraph and frontier in the query's P' (a node next to a target of another part
+// was a frontier already), and its nodes keep their order in the renumbering, so its
+// Dijkstra_SK groups would write exactly these lanes: the query's build takes them
+// instead of running the groups (Sec. 5: parts are independent).
+struct DskCache {
+    bool ok = false;
+    std::vector<int32_t> first, count, nf;  // per part: cached groups [first, first+count), |F_p|
+    std::vector<uint32_t*> dist;            // per cached group: its output lanes
+    std::vector<uint64_t*> sig;
+    Arena store;
+    size_t bytes = 0;
+};
+
 // Q_RDSK / Q_RES: Dijkstra_SK, or Brandes_SK + Centrality, running as resident
 // launches on a side stream (Q_DSK / Q_BSK: the same on the shared engine)
 enum { Q_QUEUED = 0, Q_DSK = 1, Q_BSK = 2, Q_DONE = 3, Q_FAILED = 4, Q_RES = 5, Q_RDSK = 6 };
@@ -129,6 +144,8 @@ struct bc_server {
     std::vector<std::unique_ptr<bc_graph>> graphs;
     std::vector<std::vector<int32_t>> parts;
     std::vector<int32_t> ks;
+    std::vector<std::unique_ptr<DskCache>> caches;
+    std::atomic<int64_t> cache_bytes{0}, dsk_cached{0}, dsk_run{0};
     // queries
     uint64_t next_ticket = 1;
     std::deque<uint64_t> incoming;  // submitted, not yet seen by the loop
@@ -434,6 +451,28 @@ static int admit_prepared(bc_server* sv, Query* q) {
     bool res = !(q->flags & BC_ENGINE_ONLY);
     for (auto& G : q->groups) res = res && resident_takes((int64_t)G.hi - G.lo);
     if (res) {
+        // parts without a target take their Dijkstra_SK lanes from the graph's cache
+        std::vector<uint8_t> preset(b.groups.size(), 0);
+        const DskCache* C = nullptr;
+        const int32_t* part = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            C = sv->caches[q->gid].get();
+            part = sv->parts[q->gid].data();
+        }
+        if (C && C->ok) {
+            std::vector<uint8_t> has_t(b.k_in, 0);
+            for (int32_t t : q->S) has_t[part[t]] = 1;
+            for (int32_t p = 0; p < b.k_in; ++p) {
+                if (has_t[p] || b.p_ng[p] == 0 || C->count[p] != b.p_ng[p] || C->nf[p] != b.pnf[p]) continue;
+                for (int32_t j = 0; j < b.p_ng[p]; ++j) {
+                    GroupDesc& G = b.groups[b.p_g0[p] + j];
+                    G.dist = C->dist[C->first[p] + j];
+                    G.sigma = C->sig[C->first[p] + j];
+                    preset[b.p_g0[p] + j] = 1;
+                }
+            }
+        }
         // Dijkstra_SK as one resident launch on a side stream; parts larger than LDS
         // keep their one-source state in the query's block. A query without
         // Dijkstra_SK groups launches nothing and goes on to Brandes_SK when polled
@@ -450,7 +489,11 @@ static int admit_prepared(bc_server* sv, Query* q) {
             G.gsig = q->a_tmp.take<uint64_t>((size_t)(G.hi - G.lo));
             if (!G.gdist || !G.gsig) return fail(BC_E_NOMEM, "server: block too small");
         }
-        q->groups = b.groups;
+        q->groups.clear();
+        for (size_t i = 0; i < b.groups.size(); ++i)
+            if (!preset[i]) q->groups.push_back(b.groups[i]);
+        sv->dsk_cached += (int64_t)(b.groups.size() - q->groups.size());
+        sv->dsk_run += (int64_t)q->groups.size();
         ResidentLaunch L;
         BC_TRY(resident_upload(sv->stream, q->a_tmp, q->groups, &L));
         q->d_err = L.d_err;
@@ -482,6 +525,51 @@ static int admit_prepared(bc_server* sv, Query* q) {
     // at its next step and moves it on to Brandes_SK
     if (!q->groups.empty()) BC_TRY(install_groups(sv, q));
     q->state = Q_DSK;
+    return BC_OK;
+}
+
+// The Dijkstra_SK results of every part of g under its own partition (no targets),
+// for DskCache. Leaves c->ok false when the groups do not all take the resident kernel.
+static int build_dsk_cache(bc_graph* g, const int32_t* part, int32_t k, DskCache* c) {
+    hipStream_t s = g->stream;
+    SkBuild b;
+    BC_TRY(b.prepare(g, part, k, nullptr, 0, false));
+    for (auto& G : b.groups)
+        if (!resident_takes((int64_t)G.hi - G.lo)) return BC_OK;
+    size_t need = b.temp_bytes() + resident_launch_bytes(b.groups.size()) + 8192;
+    size_t bytes = 0;
+    for (auto& G : b.groups) {
+        const size_t r = (size_t)(G.hi - G.lo);
+        if ((int64_t)r > resident_max_range()) need += r * 12 + 512;
+        bytes += ((r * 64 * 4 + 255) & ~(size_t)255) + ((r * 64 * 8 + 255) & ~(size_t)255);
+    }
+    Arena W;
+    BC_TRY(W.reserve(need));
+    BC_TRY(b.upload(W, s));
+    for (auto& G : b.groups) {
+        if ((int64_t)G.hi - G.lo <= resident_max_range()) continue;
+        G.gdist = W.take<uint32_t>((size_t)(G.hi - G.lo));
+        G.gsig = W.take<uint64_t>((size_t)(G.hi - G.lo));
+        if (!G.gdist || !G.gsig) return fail(BC_E_NOMEM, "server: cache workspace too small");
+    }
+    BC_TRY(run_resident(s, W, b.groups));
+    BC_TRY(c->store.reserve(bytes + 4096));
+    for (auto& G : b.groups) {
+        const size_t lanes = (size_t)(G.hi - G.lo) * 64;
+        uint32_t* d = c->store.take<uint32_t>(lanes);
+        uint64_t* q = c->store.take<uint64_t>(lanes);
+        if (!d || !q) return fail(BC_E_NOMEM, "server: cache store too small");
+        BC_HIP(hipMemcpyAsync(d, G.dist, lanes * 4, hipMemcpyDeviceToDevice, s));
+        BC_HIP(hipMemcpyAsync(q, G.sigma, lanes * 8, hipMemcpyDeviceToDevice, s));
+        c->dist.push_back(d);
+        c->sig.push_back(q);
+    }
+    BC_HIP(hipStreamSynchronize(s));
+    c->first.assign(b.p_g0.begin(), b.p_g0.begin() + k);
+    c->count.assign(b.p_ng.begin(), b.p_ng.begin() + k);
+    c->nf.assign(b.pnf.begin(), b.pnf.begin() + k);
+    c->bytes = c->store.cap;
+    c->ok = true;
     return BC_OK;
 }
 
@@ -719,10 +807,19 @@ int bc_server_add_graph(bc_server* s, const bc_csr* g, const int32_t* part, int3
         if (part[v] < 0 || part[v] >= k) return fail(BC_E_INVAL, "partition label out of range");
     bc_graph* gr = nullptr;
     BC_TRY(graph_create(g, s->stream, &gr));
+    std::unique_ptr<bc_graph> keep(gr);
+    // Dijkstra_SK of every part without targets, kept for the queries (built before the
+    // graph is visible to the loop, so nothing else uses the graph's buffers meanwhile)
+    auto cache = std::make_unique<DskCache>();
+    if (g->n > 0) BC_TRY(build_dsk_cache(gr, part, k, cache.get()));
+    gr->work.release();
+    gr->pre.release();
+    s->cache_bytes += (int64_t)cache->bytes;
     std::lock_guard<std::mutex> lk(s->mu);
-    s->graphs.emplace_back(gr);
+    s->graphs.push_back(std::move(keep));
     s->parts.emplace_back(part, part + g->n);
     s->ks.push_back(k);
+    s->caches.push_back(std::move(cache));
     *gid = (int32_t)s->graphs.size() - 1;
     return BC_OK;
 }
@@ -799,6 +896,9 @@ int bc_server_stats_get(bc_server* s, bc_server_stats* out) {
     out->p50_ms = pct(0.50);
     out->p99_ms = pct(0.99);
     out->peak_bytes = (int64_t)s->pool.peak;
+    out->cache_bytes = s->cache_bytes;
+    out->dsk_groups_cached = s->dsk_cached;
+    out->dsk_groups_run = s->dsk_run;
     return BC_OK;
 }
 

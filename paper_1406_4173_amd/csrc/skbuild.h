@@ -101,7 +101,9 @@ struct SkBuild {
 
     int prepare(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
                 bool given_singletons);
-    // Device bytes of upload(): phase 2 arrays plus the Dijkstra_SK group states.
+    // Device bytes of upload(): phase 2 arrays plus the Dijkstra_SK group states. A group
+    // whose output lanes (dist, sigma) are set before upload() keeps them: it gets no
+    // state, and the caller does not run it.
     size_t temp_bytes() const;
     int upload(Arena& W, hipStream_t s);
     // After the Dijkstra_SK groups have run: count, size and fill the skeleton.
@@ -134,5 +136,9 @@ std::vector<GroupDesc> bsk_groups(const bc_skeleton* sk, const int32_t* src, int
 // Brandes_SK + Centrality groups of the whole skeleton for the LDS-resident kernel
 // (resident_sources_per_group sources each, in target order); buffers not yet carved.
 std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk);
+// The same for the sources src (skeleton ids) with the target flags nflag ([n_sk]
+// NF_TARGET bits: the nodes whose paths count as destinations).
+std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk, const std::vector<int32_t>& src,
+                                           const uint8_t* nflag);
 
 }  // namespace bcpp

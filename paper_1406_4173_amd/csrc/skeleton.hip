@@ -604,7 +604,8 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
 size_t SkBuild::temp_bytes() const {
     const size_t ng = groups.size();
     size_t need = 0;
-    for (const auto& G : groups) need += group_bytes(G, 0);
+    for (const auto& G : groups)
+        if (!(G.dist && G.sigma)) need += group_bytes(G, 0);
     const size_t N = (size_t)std::max(n, 1), K = (size_t)std::max(nsk, 1), I = (size_t)std::max(nint, 1);
     need += N * (8 + 8 + 4 + 4 + 4 + 8 + 8 + 1 + 4 + 1) + 16 +  // keys, vals, old, nid, counts, irp, blk, out
             (size_t)n_intra * (weighted ? 8 : 4) + (size_t)nR * 8 + K * (8 + 4 + 8 + 4 + 4 + 1) + 16 +
@@ -728,6 +729,9 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
         G.g.col = d_icol;
         G.g.len = d_iw;
         G.g.nflag = d_blk;
+        // a group whose output lanes a caller has already set (results kept from an
+        // earlier build of the same part) takes no state here and is not run
+        if (G.dist && G.sigma) continue;
         if (!group_alloc(W, G, 0)) return fail(BC_E_NOMEM, "partition: group state does not fit");
     }
     BC_TRY(h2d(d_desc, groups.data(), (size_t)ng * sizeof(GroupDesc)));
@@ -846,6 +850,7 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
     sk->n = n;
     sk->max_len = (int32_t)std::max<uint32_t>({1u, rmax, clique_max});
     // Brandes_SK sources: targets that have a neighbour (isolated targets reach nobody)
+    sk->h_target_sk = srcsk;
     sk->h_src.clear();
     for (int32_t f : srcsk)
         if (f >= 0) sk->h_src.push_back(f);
@@ -962,7 +967,12 @@ std::vector<GroupDesc> bsk_groups(const bc_skeleton* sk, const int32_t* src, int
 // --------------------------------------------------------------- Brandes++ -----
 
 std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk) {
-    const int32_t nsrc = (int32_t)sk->h_src.size();
+    return resident_bsk_groups(sk, sk->h_src, sk->d_nflag);
+}
+
+std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk, const std::vector<int32_t>& src,
+                                           const uint8_t* nflag) {
+    const int32_t nsrc = (int32_t)src.size();
     const int32_t spg = resident_sources_per_group(nsrc);
     const int32_t ngroups = (nsrc + spg - 1) / spg;
     std::vector<GroupDesc> groups(ngroups);
@@ -972,7 +982,7 @@ std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk) {
         G.g.col = sk->d_col;
         G.g.len = sk->d_len;
         G.g.mult = sk_mult(sk);
-        G.g.nflag = sk->d_nflag;
+        G.g.nflag = nflag;
         G.g.twin = sk->d_twin;
         G.lo = 0;
         G.hi = sk->n_sk;
@@ -988,7 +998,7 @@ std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk) {
         G.tn = sk->n_int;
         const int32_t first = j * spg;
         G.nsrc = std::min(spg, nsrc - first);
-        for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? sk->h_src[first + b] : -1;
+        for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? src[first + b] : -1;
     }
     return groups;
 }
