@@ -126,6 +126,18 @@ int bc_partition_sk(const bc_graph* g, const int32_t* part, int32_t k, const int
                     int32_t nS, bc_skeleton** out);
 void bc_skeleton_destroy(bc_skeleton* sk);
 
+/* A partition for bc_partition_sk computed on the device (the paper takes P from
+ * third-party clustering tools, Sec. 7; scores do not depend on P, only Brandes++'s
+ * speed does). Size-constrained label propagation: each node starts alone; in each of
+ * `rounds` rounds the nodes whose SplitMix64 hash of (seed, round, node) is odd move to
+ * the label most common among their neighbours among labels held by fewer than
+ * max_part nodes after the previous round (0 = no cap), if it is strictly more common
+ * than their own (ties between other labels go to the smallest); labels are then
+ * renumbered 0..k-1 in increasing order. Deterministic for given arguments. part_out:
+ * [n] host array; *k_out receives k. */
+int bc_partition_lp(const bc_graph* g, int32_t max_part, int32_t rounds, uint64_t seed,
+                    int32_t* part_out, int32_t* k_out);
+
 typedef struct bc_sk_stats {
     int32_t n;              /* nodes of G */
     int32_t n_sk;           /* |V_SK|: frontier nodes of P' */

@@ -85,6 +85,7 @@ def lib():
             "bc_brandes_pp": (ctypes.c_int, [_P, _P, _u32, _P]),
             "bc_brandes_pp_dev": (ctypes.c_int, [_P, _P, _u32, _P]),
             "bc_brandes_pp_all": (ctypes.c_int, [_P, _P, _i32, _u32, _P]),
+            "bc_partition_lp": (ctypes.c_int, [_P, _i32, _i32, ctypes.c_uint64, _P, ctypes.POINTER(_i32)]),
             "bc_batch_create": (ctypes.c_int, [_i32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
             "bc_batch_run": (ctypes.c_int, [_P, _u32, _P]),
             "bc_batch_destroy": (None, [_P]),
@@ -188,6 +189,15 @@ def brandes_plain_dev(G: Graph, S_dev, out_dev, ordered: bool = False, engine_on
                                       _flags(ordered, engine_only),
                                       ctypes.c_void_p(out_dev.data_ptr())))
     return out_dev
+
+
+def partition_lp(G: Graph, max_part: int = 0, rounds: int = 20, seed: int = 1406):
+    """bc_partition_lp: (labels [n] int32, k) from size-constrained label propagation."""
+    part = np.empty(G.n, np.int32)
+    k = _i32(0)
+    _check(lib().bc_partition_lp(G.h, int(max_part), int(rounds), ctypes.c_uint64(seed), _p(part),
+                                 ctypes.byref(k)))
+    return part, k.value
 
 
 def brandes_pp_all(G: Graph, part, k: int, ordered: bool = False):

@@ -224,13 +224,14 @@ int run_resident(hipStream_t s, Arena& a, const GroupDesc* const* groups, size_t
 // resident_launch only enqueues kernels, so it can go on a stream with work still
 // pending. After the launch completes, *d_err has ERR_OVERFLOW set if a count reached
 // 2^64. Classes 0-2 hold the state in LDS (256, 512, 1024 threads), class 3 in device
-// memory.
+// memory, class 4 its distances as one byte per node in LDS and its counts in device
+// memory (ranges beyond LDS whose arcs are at most 63 long).
 struct RGroup;
 struct RCtx;
 struct ResidentLaunch {
-    RGroup* d_rg[4] = {nullptr, nullptr, nullptr, nullptr};
-    int32_t count[4] = {0, 0, 0, 0};
-    size_t lds[4] = {0, 0, 0, 0};
+    RGroup* d_rg[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int32_t count[5] = {0, 0, 0, 0, 0};
+    size_t lds[5] = {0, 0, 0, 0, 0};
     const RCtx* d_ctx = nullptr;
     const int32_t* d_src = nullptr;
     uint32_t* d_err = nullptr;

@@ -366,7 +366,7 @@ __device__ __forceinline__ GAS T* gas(T* p) {
 }
 
 
-template <int T, bool GLOBAL>
+template <int T, bool GLOBAL, bool BYTE>
 __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                                 const RCtx* __restrict__ ctxs,
                                                 const int32_t* __restrict__ srcs,
@@ -392,8 +392,21 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     uint64_t* __restrict__ sig = reinterpret_cast<uint64_t*>(lds + (((size_t)n * 4 + 15) & ~(size_t)15));
     GAS uint32_t* __restrict__ gdist = gas(R.gdist);
     GAS uint64_t* __restrict__ gsig = gas(R.gsig);
+    // BYTE (ranges beyond LDS with arcs of at most 63): the distance state is one byte
+    // per node in LDS: 0xFF unreached; 0x00..0x7F pending, the tentative distance mod
+    // 128; 0x80 | (d mod 127) settled. Pending distances lie within the longest arc
+    // above the step's D, and a settled neighbour of a node at distance D lies within
+    // the arc's length of D on either side, so these residues decide every comparison
+    // the sweeps make exactly. A node's exact distance goes to gdist when it settles
+    // (read only for settled nodes); path counts stay in gsig as with GLOBAL.
+    uint8_t* __restrict__ db = lds;
+    uint32_t* db32 = reinterpret_cast<uint32_t*>(lds);
+    auto settled_b = [](uint32_t b) { return b >= 0x80u && b != 0xFFu; };
     auto D_ = [&](int32_t i) -> uint32_t {
-        if constexpr (GLOBAL)
+        if constexpr (BYTE)
+            return settled_b(db[i]) ? __hip_atomic_load(gdist + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : INF32;
+        else if constexpr (GLOBAL)
             return __hip_atomic_load(gdist + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         else
             return dist[i];
@@ -464,7 +477,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     // the bucket being retired, so no write races the retiring. (With the state in LDS a
     // scan step costs a few LDS reads per thread, less than the bitmaps' atomics and the
     // occupancy their LDS would take.)
-    const bool bucket = GLOBAL && R.lg >= 0;
+    const bool bucket = GLOBAL && !BYTE && R.lg >= 0;
     const int lg = bucket ? R.lg : 0;
     const uint32_t RM = bucket ? (1u << lg) - 1u : 0u;
     const int32_t W = (n + 31) >> 5;
@@ -515,9 +528,16 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
 
     for (int b = 0; b < R.nsrc; ++b) {
         const int32_t s = srcs[R.src_off + b] - lo;
-        for (int32_t v = tid; v < n; v += T) {
-            setD(v, (v == s) ? 0u : INF32);
-            setS(v, (v == s) ? 1ull : 0ull);
+        if constexpr (BYTE) {
+            // every node unreached but s, pending at distance 0
+            for (int32_t i = tid; i < ((n + 3) >> 2); i += T)
+                db32[i] = (i == (s >> 2)) ? ~(0xFFu << ((s & 3) * 8)) : 0xFFFFFFFFu;
+            for (int32_t v = tid; v < n; v += T) setS(v, (v == s) ? 1ull : 0ull);
+        } else {
+            for (int32_t v = tid; v < n; v += T) {
+                setD(v, (v == s) ? 0u : INF32);
+                setS(v, (v == s) ? 1ull : 0ull);
+            }
         }
         if (tight)
             for (int32_t i = tid; i < R.tw; i += T) {
@@ -578,14 +598,25 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         // one read of u's distance serves both tests below: if another
                         // lane lowers it meanwhile, the offer test passes at worst for an
                         // offer that then changes nothing
-                        const uint32_t du = D_(u);
+                        uint32_t du = 0, uw = 0;
+                        bool parent = false;
+                        if constexpr (BYTE) {
+                            // u settled at D - L: a settled neighbour lies in [D - L, D],
+                            // L + 1 <= 64 values with distinct residues mod 127
+                            uw = db32[u >> 2];
+                            const uint32_t bu = (uw >> ((u & 3) * 8)) & 0xFFu;
+                            parent = L <= D && settled_b(bu) && (bu & 0x7Fu) == (D - L) % 127u;
+                        } else {
+                            du = D_(u);
+                            parent = du != INF32 && du + L == D;
+                        }
                         // u is a parent of v if it settled at D - L in an earlier step (eq.
                         // parentsall / eq. multiparents); the count adds in with an atomic,
                         // exact for integers, and a wrap of any addition is an overflow
                         if (v != s && L <= D) {
                             // Dijkstra_SK (eq. frontierparents): a frontier parent other
                             // than the source is tight but adds no paths
-                            if (du != INF32 && du + L == D &&
+                            if (parent &&
                                 !(restrict_ && u != s && nflag && (nflag[lo + u] & NF_BLOCKED))) {
                                 if (tight) {
                                     const uint64_t t = (uint64_t)(te - abase);
@@ -611,7 +642,24 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         }
                         // offers: all above D, so they never meet the parent test above
                         const uint32_t nv = D + L;
-                        if (nv < du) {
+                        if constexpr (BYTE) {
+                            // lower u's byte to nv's residue unless u is settled or already
+                            // pending at most L above D (offsets of pending bytes from D
+                            // are at most the longest arc); a compare-and-swap on the word
+                            // holding it, retried while other bytes of the word change
+                            const int sh = (u & 3) * 8;
+                            for (;;) {
+                                const uint32_t bu = (uw >> sh) & 0xFFu;
+                                if (settled_b(bu) || (bu != 0xFFu && ((bu - D) & 127u) <= L)) break;
+                                const uint32_t nw = (uw & ~(0xFFu << sh)) | ((nv & 127u) << sh);
+                                const uint32_t prev = atomicCAS(&db32[u >> 2], uw, nw);
+                                if (prev == uw) {
+                                    mn = min(mn, nv);
+                                    break;
+                                }
+                                uw = prev;
+                            }
+                        } else if (nv < du) {
                             if (bucket) {
                                 // a bit per successful offer (a failed one leaves none)
                                 const uint32_t old = minD(u, nv);
@@ -640,6 +688,24 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                 } else {
                     for_bucket<T>(row, W, wq, [&](int32_t v) { return D_(v) == D; }, fbody);
                 }
+            } else if constexpr (BYTE) {
+                // pending at D: settle (its byte and its exact distance) as it is selected;
+                // within the step nothing else writes a node pending at D, and a node
+                // settled at D passes no parent test of the step (arcs are 1..126 long)
+                const uint32_t dres = D & 127u, sres = 0x80u | (D % 127u);
+                for_selected<T, 2, 16>(
+                    n, wq,
+                    [&](int32_t v) {
+                        const uint32_t b = db[v];
+                        if (b == dres) {
+                            db[v] = (uint8_t)sres;
+                            gdist[v] = D;
+                            return true;
+                        }
+                        if (b < 0x80u) mn = min(mn, D + ((b - D) & 127u));
+                        return false;
+                    },
+                    fbody);
             } else {
                 for_selected<T, GLOBAL ? 8 : 2, OWN_BLK>(
                     n, wq,
@@ -810,8 +876,17 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                             if (prof) bytes += 20ull;
                             const int32_t x = col[e] - lo;
                             const uint32_t L = len ? len[e] : 1u;
-                            const uint32_t dx = D_(x);
-                            if (dx != INF32 && dx == D + L) {
+                            bool child;
+                            if constexpr (BYTE) {
+                                // a settled neighbour of a node at D lies in [D - L, D + L],
+                                // at most 127 values: residues mod 127 are distinct
+                                const uint32_t bx = db[x];
+                                child = settled_b(bx) && (bx & 0x7Fu) == (D + L) % 127u;
+                            } else {
+                                const uint32_t dx = D_(x);
+                                child = dx != INF32 && dx == D + L;
+                            }
+                            if (child) {
                                 c = __longlong_as_double((long long)S_(x));
                                 if (mult) c *= (double)mult[e];
                             }
@@ -879,6 +954,14 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
 }
 
 size_t lds_bytes(int64_t range) { return (((size_t)range * 4 + 15) & ~(size_t)15) + (size_t)range * 8; }
+// LDS of the one-byte distance state (BYTE)
+size_t byte_lds_bytes(int64_t range) { return ((size_t)range + 15) & ~(size_t)15; }
+// The one-byte distance state for ranges beyond LDS: arcs at most 63 long (ring_len is
+// the longest arc + 1) and one byte per node within LDS; BCPP_BYTE=0 switches it off.
+bool byte_state_on() {
+    const char* e = getenv("BCPP_BYTE");
+    return !(e && strcmp(e, "0") == 0);
+}
 
 // Bucket bitmaps of a group: log2 of the bucket count for arcs up to ring_len - 1 long
 // (at most 64 buckets), or -1 when the longest arc is unknown or too long.
@@ -913,13 +996,15 @@ int query_limits() {
     const size_t stat = 16 * WQ * 4 + 1024;
     size_t usable = (size_t)v > stat ? (size_t)v - stat : 0;
     if (usable > 65536) {
-        if (hipFuncSetAttribute((const void*)k_resident<1024, true>,
+        if (hipFuncSetAttribute((const void*)k_resident<1024, true, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_resident<1024, false>,
+            hipFuncSetAttribute((const void*)k_resident<1024, true, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_resident<512, false>,
+            hipFuncSetAttribute((const void*)k_resident<1024, false, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_resident<256, false>,
+            hipFuncSetAttribute((const void*)k_resident<512, false, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_resident<256, false, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess) {
             (void)hipGetLastError();
             usable = 65536 - stat;
@@ -1045,8 +1130,9 @@ size_t resident_launch_bytes(size_t ngroups) {
 int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, size_t ng, ResidentLaunch* L) {
     *L = ResidentLaunch();
     BC_TRY(query_limits());
-    // one launch per size class; class 3 keeps its state in device memory
-    std::vector<RGroup> cls[4];
+    // one launch per size class; class 3 keeps its state in device memory, class 4 its
+    // distance state as one byte per node in LDS and its path counts in device memory
+    std::vector<RGroup> cls[5];
     std::vector<RCtx> ctx;
     std::vector<int32_t> src;
     std::map<std::pair<const void*, const void*>, int32_t> ctx_of;
@@ -1065,10 +1151,15 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         size_t need;
         if (state > limits().lds) {
             if (!G.gdist || !G.gsig) return fail(BC_E_INVAL, "resident: no state buffers for a large range");
-            c = 3;
             if (G.gtb && G.g.twin && (G.flags & GF_BACKWARD) && G.arcs > 0) tw = (int32_t)((G.arcs + 31) / 32);
-            lg = (lg0 >= 0 && bb <= limits().lds) ? lg0 : -1;
-            need = lg >= 0 ? bb : 0;
+            if (byte_state_on() && G.ring_len >= 2 && G.ring_len <= 64 && byte_lds_bytes(range) <= limits().lds) {
+                c = 4;
+                need = byte_lds_bytes(range);
+            } else {
+                c = 3;
+                lg = (lg0 >= 0 && bb <= limits().lds) ? lg0 : -1;
+                need = lg >= 0 ? bb : 0;
+            }
         } else {
             c = sc.of(range);
             need = state;
@@ -1107,7 +1198,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         r.isig = G.sigma;
         r.gdist = G.gdist;
         r.gsig = G.gsig;
-        r.gtb = tw > 0 && c == 3 ? G.gtb : nullptr;
+        r.gtb = tw > 0 && c >= 3 ? G.gtb : nullptr;
         r.rlist = G.rlist;
         r.steps = G.steps;
         r.odist = G.odist;
@@ -1127,7 +1218,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
     if (!src.empty()) BC_HIP(hipMemcpyAsync(d_src, src.data(), src.size() * 4, hipMemcpyHostToDevice, s));
     L->d_ctx = d_ctx;
     L->d_src = d_src;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < 5; ++c) {
         L->count[c] = (int32_t)cls[c].size();
         if (cls[c].empty()) continue;
         L->d_rg[c] = a.take<RGroup>(cls[c].size());
@@ -1146,21 +1237,24 @@ int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& group
 
 int resident_launch(hipStream_t s, const ResidentLaunch& L) {
     unsigned long long* prof = profiler().on && profiler().d_bytes ? profiler().d_bytes + L.kind : nullptr;
-    for (int c = 3; c >= 0; --c) {
+    for (int c = 4; c >= 0; --c) {
         if (!L.count[c]) continue;
         KTimer kt(L.kind, s);
         const dim3 grid((unsigned)L.count[c]);
-        if (c == 3)
-            hipLaunchKernelGGL((k_resident<1024, true>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
+        if (c == 4)
+            hipLaunchKernelGGL((k_resident<1024, true, true>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
+                               L.d_src, L.d_err, prof);
+        else if (c == 3)
+            hipLaunchKernelGGL((k_resident<1024, true, false>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
                                L.d_src, L.d_err, prof);
         else if (c == 2)
-            hipLaunchKernelGGL((k_resident<1024, false>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
-                               L.d_src, L.d_err, prof);
+            hipLaunchKernelGGL((k_resident<1024, false, false>), grid, dim3(1024), L.lds[c], s, L.d_rg[c],
+                               L.d_ctx, L.d_src, L.d_err, prof);
         else if (c == 1)
-            hipLaunchKernelGGL((k_resident<512, false>), grid, dim3(512), L.lds[c], s, L.d_rg[c], L.d_ctx,
+            hipLaunchKernelGGL((k_resident<512, false, false>), grid, dim3(512), L.lds[c], s, L.d_rg[c], L.d_ctx,
                                L.d_src, L.d_err, prof);
         else
-            hipLaunchKernelGGL((k_resident<256, false>), grid, dim3(256), L.lds[c], s, L.d_rg[c], L.d_ctx,
+            hipLaunchKernelGGL((k_resident<256, false, false>), grid, dim3(256), L.lds[c], s, L.d_rg[c], L.d_ctx,
                                L.d_src, L.d_err, prof);
     }
     BC_HIP(hipGetLastError());

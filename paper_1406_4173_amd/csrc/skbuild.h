@@ -54,7 +54,7 @@ struct SkBuild {
     std::vector<GroupDesc> groups;  // Dijkstra_SK groups
     std::vector<DskInfo> info;
     int64_t largest = 0, kprime = 0, clique_pairs = 0, table_pairs = 0;
-    size_t cub_bytes = 0;  // scratch of the device scans
+    size_t scan_bytes = 0;  // scratch of the device scans (exclusive_scan)
     int32_t ntiles = 1;    // tiles of the renumbering sort
     // phase 1 (graph scratch arena)
     int32_t* p_part = nullptr;
@@ -73,7 +73,7 @@ struct SkBuild {
     int64_t *d_icnt = nullptr, *d_rcnt = nullptr;    // row counts before the scans
     int64_t *d_poff = nullptr, *d_fbase = nullptr;   // per part (copies of the host values)
     int32_t *d_ppnf = nullptr, *d_pg0 = nullptr, *d_png = nullptr, *d_ibase = nullptr;
-    void* d_cub = nullptr;
+    void* d_scan = nullptr;
     int32_t* d_old = nullptr;  // renumbered position -> original node
     int32_t* d_nid = nullptr;  // original node -> renumbered position
     int64_t* d_irp = nullptr;  // intra-part CSR, renumbered

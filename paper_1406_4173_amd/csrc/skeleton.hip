@@ -11,7 +11,6 @@
 #include <memory>
 #include <numeric>
 
-#include <hipcub/hipcub.hpp>
 
 #include "engine.h"
 #include "graph.h"
@@ -583,20 +582,9 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
     if (rows >= INT32_MAX) return fail(BC_E_INVAL, "too many interior nodes");
     nint = (int32_t)rows;
     // scratch of the device scans (CSR offsets, and the radix sort's digit offsets)
-    cub_bytes = 0;
     ntiles = (int32_t)std::max<int64_t>((n + RS_TILE - 1) / RS_TILE, 1);
-    if (n > 0) {
-        size_t b = 0;
-        BC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int32_t*)nullptr, (int32_t*)nullptr,
-                                                (int64_t)ntiles * 256, s));
-        cub_bytes = std::max(cub_bytes, b);
-        BC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, n + 1, s));
-        cub_bytes = std::max(cub_bytes, b);
-        BC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, nsk + 1, s));
-        cub_bytes = std::max(cub_bytes, b);
-        BC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, (int64_t*)nullptr, (int64_t*)nullptr, nint + 1, s));
-        cub_bytes = std::max(cub_bytes, b);
-    }
+    scan_bytes = scan_scratch_bytes(std::max<int64_t>({(int64_t)ntiles * 256, (int64_t)n + 1, (int64_t)nsk + 1,
+                                                      (int64_t)nint + 1}));
     tr.mark("groups, interior rows");
     return BC_OK;
 }
@@ -610,7 +598,7 @@ size_t SkBuild::temp_bytes() const {
     need += N * (8 + 8 + 4 + 4 + 4 + 8 + 8 + 1 + 4 + 1) + 16 +  // keys, vals, old, nid, counts, irp, blk, out
             (size_t)n_intra * (weighted ? 8 : 4) + (size_t)nR * 8 + K * (8 + 4 + 8 + 4 + 4 + 1) + 16 +
             ng * (sizeof(DskInfo) + sizeof(GroupDesc)) + I * 20 + (size_t)std::max(nS, 1) * 4 +
-            (size_t)(nlab + 1) * (8 * 2 + 4 * 4) + (size_t)ntiles * 256 * 4 * 2 + cub_bytes +
+            (size_t)(nlab + 1) * (8 * 2 + 4 * 4) + (size_t)ntiles * 256 * 4 * 2 + scan_bytes +
             (K + 1) * 16 + (I + 1) * 16 + 56 * 256;
     return need;
 }
@@ -632,18 +620,15 @@ int SkBuild::issue_phase2(hipStream_t s) const {
         for (int ps = 0; ps < passes; ++ps) {
             const int i = ps & 1;
             hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(256), 0, s, n, kb[i], 8 * ps, ntiles, d_hist);
-            size_t cb = cub_bytes;
-            BC_HIP(hipcub::DeviceScan::ExclusiveSum(d_cub, cb, d_hist, d_hoff, (int64_t)ntiles * 256, s));
+            BC_TRY(exclusive_scan<int32_t>(s, d_hist, d_hoff, (int64_t)ntiles * 256, d_scan));
             hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(256), 0, s, n, kb[i], vb[i], kb[i ^ 1], vb[i ^ 1],
                                8 * ps, ntiles, d_hoff);
         }
         hipLaunchKernelGGL(k_p2_nid, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, d_nid);
         hipLaunchKernelGGL(k_p2_count, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, g->d_row_ptr, g->d_col,
                            p_lab, p_fr, d_poff, d_fbase, d_icnt, d_rcnt, d_rdeg);
-        size_t cb = cub_bytes;
-        BC_HIP(hipcub::DeviceScan::ExclusiveSum(d_cub, cb, d_icnt, d_irp, n + 1, s));
-        cb = cub_bytes;
-        BC_HIP(hipcub::DeviceScan::ExclusiveSum(d_cub, cb, d_rcnt, d_rptr, nsk + 1, s));
+        BC_TRY(exclusive_scan<int64_t>(s, d_icnt, d_irp, (int64_t)n + 1, d_scan));
+        BC_TRY(exclusive_scan<int64_t>(s, d_rcnt, d_rptr, (int64_t)nsk + 1, d_scan));
         hipLaunchKernelGGL(k_p2_fill, dim3(blocks_for(n)), dim3(256), 0, s, n, d_old, d_nid, g->d_row_ptr,
                            g->d_col, g->d_len, p_lab, p_fr, d_poff, d_fbase, d_irp, d_rptr, d_icol, d_iw,
                            d_rcol, d_rw, d_rmax);
@@ -699,7 +684,7 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
     d_rmax = W.take<uint32_t>(1);
     d_hist = W.take<int32_t>((size_t)ntiles * 256);
     d_hoff = W.take<int32_t>((size_t)ntiles * 256);
-    d_cub = W.take<unsigned char>(std::max<size_t>(cub_bytes, 1));
+    d_scan = W.take<unsigned char>(std::max<size_t>(scan_bytes, 1));
     d_desc = W.take<GroupDesc>(std::max(ng, 1));
     d_slen = W.take<int64_t>(nsk + 1);
     d_srow = W.take<int64_t>(nsk + 1);
@@ -710,7 +695,7 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
         !d_blk || !d_rcnt || !d_rdeg || !d_rptr || !d_rcol || !d_rw || !d_cdeg || !d_info || !d_il || !d_ig0 ||
         !d_ing || !d_tdeg || !d_inode || !d_out_idx || !d_out_which || !d_nodes || !d_sflag || !d_srcsk ||
         !d_poff || !d_fbase || !d_ppnf || !d_pg0 || !d_png || !d_ibase || !d_maxlen || !d_rmax || !d_hist ||
-        !d_hoff || !d_cub || !d_desc)
+        !d_hoff || !d_scan || !d_desc)
         return fail(BC_E_NOMEM, "partition: workspace too small");
     auto h2d = [&](void* d, const void* h, size_t b) -> int {
         if (b) BC_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s));
@@ -756,10 +741,8 @@ int SkBuild::issue_count(hipStream_t s) const {
                        d_cdeg, ng > 0 ? d_tdeg : nullptr, d_slen, d_tlen);
     BC_HIP(hipGetLastError());
     if (n > 0) {
-        size_t cb = cub_bytes;
-        BC_HIP(hipcub::DeviceScan::ExclusiveSum(d_cub, cb, d_slen, d_srow, nsk + 1, s));
-        cb = cub_bytes;
-        BC_HIP(hipcub::DeviceScan::ExclusiveSum(d_cub, cb, d_tlen, d_trow, nint + 1, s));
+        BC_TRY(exclusive_scan<int64_t>(s, d_slen, d_srow, (int64_t)nsk + 1, d_scan));
+        BC_TRY(exclusive_scan<int64_t>(s, d_tlen, d_trow, (int64_t)nint + 1, d_scan));
     } else {
         zero_bytes(s, d_srow, 8);
         zero_bytes(s, d_trow, 8);

@@ -134,3 +134,21 @@ def test_skeleton_counts_engine(bcpp, monkeypatch):
     for seed, (n, p, wmax, k, ns) in enumerate([(80, 0.06, None, 5, 10), (300, 0.02, 3, 10, 30)]):
         g = inputs.random_graph(4000 + seed, n, p, wmax=wmax, k=k, ns=ns)
         check_skeleton_counts(bcpp, g, g.S, ns)
+
+
+@pytest.mark.parametrize("byte", ["1", "0"], ids=["byte-state", "device-state"])
+def test_counts_large_ranges_both_state_layouts(bcpp, monkeypatch, byte):
+    """Ranges beyond LDS keep their distance state as one byte per node in LDS when arcs
+    are at most 63 long (else, or with BCPP_BYTE=0, in device memory): both layouts give
+    the oracle's counts bit for bit, on G (weights 1..12 and 1..60) and on a skeleton."""
+    monkeypatch.setenv("BCPP_BYTE", byte)
+    for wmax, seed in ((12, 1), (60, 2)):
+        rng = inputs.rng_for(inputs.SEED_BASE + 133, seed)
+        g = inputs._community_graph(rng, 16000, 300, 7.0, 0.95, wmax, "layouts")
+        S = np.sort(rng.choice(g.n, 12, replace=False)).astype(np.int32)
+        check_graph_counts(bcpp, g, S)
+    rng = inputs.rng_for(inputs.SEED_BASE + 134)
+    g = inputs._community_graph(rng, 40000, 800, 8.0, 0.94, 4, "layouts_sk")
+    S = np.sort(rng.choice(g.n, 60, replace=False)).astype(np.int32)
+    sk = check_skeleton_counts(bcpp, g, S, 10)
+    assert sk.stats()["n_sk"] > 13000
