@@ -112,6 +112,24 @@ int bc_brandes_plain(const bc_graph* g, const int32_t* S, int32_t nS, uint32_t f
 int bc_brandes_plain_dev(const bc_graph* g, const int32_t* S_dev, int32_t nS,
                          uint32_t flags, double* bc_out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops or harnesses that forbid hipMalloc): bc_brandes_plain_dev that
+ * allocates nothing. Every buffer its kernels use beyond S_dev and bc_out_dev (target
+ * flags, per-group score rows, forward records, one-source state of ranges beyond LDS,
+ * launch records, error word) comes from one fixed device array of
+ * bc_noalloc_scratch_bytes() bytes (256 MiB) that the library holds on each GPU it has
+ * run on until the process ends. Source groups run in waves of as many as fit in it
+ * (each wave's scores are added to the previous waves'), so results agree with
+ * bc_brandes_plain_dev within the stated tolerance, not always bit for bit. Fails with
+ * BC_E_NOMEM, before any device work, when one group over g does not fit (about 5 MB
+ * per group at 100,000 nodes and 800,000 arcs). Flags: BC_ORDERED only. Calls on one
+ * GPU share its array, which keeps the last call's contents: calls that overlap on one
+ * GPU (from different threads or streams) race and must be serialised by the caller.
+ * Returns after the work is complete on the device. */
+int bc_brandes_plain_noalloc(const bc_graph* g, const int32_t* S_dev, int32_t nS,
+                             uint32_t flags, double* bc_out_dev);
+size_t bc_noalloc_scratch_bytes(void);
+
 /* ---------------------------------------------------------------- Brandes++ ---- */
 
 /* Build_SK (Sec. 5, Alg. 2 with the partition P' of Step 1): every target leaves its

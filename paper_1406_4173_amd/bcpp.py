@@ -77,6 +77,8 @@ def lib():
             "bc_sssp_counts": (ctypes.c_int, [_P, _P, _i32, _P, _P]),
             "bc_brandes_plain": (ctypes.c_int, [_P, _P, _i32, _u32, _P]),
             "bc_brandes_plain_dev": (ctypes.c_int, [_P, _P, _i32, _u32, _P]),
+            "bc_brandes_plain_noalloc": (ctypes.c_int, [_P, _P, _i32, _u32, _P]),
+            "bc_noalloc_scratch_bytes": (ctypes.c_size_t, []),
             "bc_partition_sk": (ctypes.c_int, [_P, _P, _i32, _P, _i32, ctypes.POINTER(_P)]),
             "bc_skeleton_destroy": (None, [_P]),
             "bc_skeleton_stats": (ctypes.c_int, [_P, ctypes.POINTER(bc_sk_stats)]),
@@ -189,6 +191,19 @@ def brandes_plain_dev(G: Graph, S_dev, out_dev, ordered: bool = False, engine_on
                                       _flags(ordered, engine_only),
                                       ctypes.c_void_p(out_dev.data_ptr())))
     return out_dev
+
+
+def brandes_plain_noalloc(G: Graph, S_dev, out_dev, ordered: bool = False):
+    """bc_brandes_plain_noalloc: as brandes_plain_dev, with every buffer beyond S_dev and
+    out_dev taken from the library's fixed device scratch array."""
+    _check(lib().bc_brandes_plain_noalloc(G.h, ctypes.c_void_p(S_dev.data_ptr()), S_dev.numel(),
+                                          BC_ORDERED if ordered else 0,
+                                          ctypes.c_void_p(out_dev.data_ptr())))
+    return out_dev
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().bc_noalloc_scratch_bytes())
 
 
 def partition_lp(G: Graph, max_part: int = 0, rounds: int = 20, seed: int = 1406):
@@ -406,5 +421,5 @@ def exported_symbols():
     import re
 
     hdr = open(os.path.join(HERE, "..", "include", "bcpp.h")).read()
-    pat = r"^(?:int|void|const char\*)\s+(bc_[a-z_]+)\s*\("
+    pat = r"^(?:int|void|size_t|const char\*)\s+(bc_[a-z_]+)\s*\("
     return sorted(set(re.findall(pat, hdr, re.MULTILINE)))
