@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 
 #include "engine.h"
 #include "tuned.h"
@@ -109,6 +110,58 @@ __device__ __forceinline__ double wseg_sum(double c, int seg) {
     for (int rr = 1; rr < 4; ++rr) {
         const double carry = readlane_f64(c, 16 * rr - 1);
         if ((lane >> 4) == rr && seg < 16 * rr) c += carry;
+    }
+    return c;
+}
+
+// The same segmented inclusive scan for the minimum of uint32 values.
+__device__ __forceinline__ uint32_t wseg_min_u32(uint32_t c, int seg) {
+    const int lane = threadIdx.x & 63;
+    const int lim = max(seg, lane & ~15);
+    uint32_t t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)c, DPP_ROW_SHR | 1, 0xf, 0xf, false);
+    if (lane - 1 >= lim) c = min(c, t);
+    t = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)c, DPP_ROW_SHR | 2, 0xf, 0xf, false);
+    if (lane - 2 >= lim) c = min(c, t);
+    t = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)c, DPP_ROW_SHR | 4, 0xf, 0xf, false);
+    if (lane - 4 >= lim) c = min(c, t);
+    t = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)c, DPP_ROW_SHR | 8, 0xf, 0xf, false);
+    if (lane - 8 >= lim) c = min(c, t);
+#pragma unroll
+    for (int rr = 1; rr < 4; ++rr) {
+        const uint32_t carry = (uint32_t)__builtin_amdgcn_readlane((int)c, 16 * rr - 1);
+        if ((lane >> 4) == rr && seg < 16 * rr) c = min(c, carry);
+    }
+    return c;
+}
+
+// uint64 value of the lane O places lower in the same 16-lane row (0 where there is none).
+template <int O>
+__device__ __forceinline__ uint64_t dpp_row_shr_u64(uint64_t x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, DPP_ROW_SHR | O, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), DPP_ROW_SHR | O, 0xf, 0xf, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// The same segmented inclusive scan for sums of uint64 values; *ovf is set where an
+// addition wraps (all terms are counts, so any wrap means the total reaches 2^64).
+__device__ __forceinline__ uint64_t wseg_sum_u64(uint64_t c, int seg, bool* ovf) {
+    const int lane = threadIdx.x & 63;
+    const int lim = max(seg, lane & ~15);
+    uint64_t t;
+    t = dpp_row_shr_u64<1>(c);
+    if (lane - 1 >= lim) { *ovf |= c + t < c; c += t; }
+    t = dpp_row_shr_u64<2>(c);
+    if (lane - 2 >= lim) { *ovf |= c + t < c; c += t; }
+    t = dpp_row_shr_u64<4>(c);
+    if (lane - 4 >= lim) { *ovf |= c + t < c; c += t; }
+    t = dpp_row_shr_u64<8>(c);
+    if (lane - 8 >= lim) { *ovf |= c + t < c; c += t; }
+#pragma unroll
+    for (int rr = 1; rr < 4; ++rr) {
+        const uint64_t carry = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(c >> 32), 16 * rr - 1) << 32) |
+                               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)c, 16 * rr - 1);
+        if ((lane >> 4) == rr && seg < 16 * rr) { *ovf |= c + carry < c; c += carry; }
     }
     return c;
 }
@@ -532,7 +585,8 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             // every node unreached but s, pending at distance 0
             for (int32_t i = tid; i < ((n + 3) >> 2); i += T)
                 db32[i] = (i == (s >> 2)) ? ~(0xFFu << ((s & 3) * 8)) : 0xFFFFFFFFu;
-            for (int32_t v = tid; v < n; v += T) setS(v, (v == s) ? 1ull : 0ull);
+            // counts are stored as nodes settle and read only for settled nodes
+            if (tid == 0) setS(s, 1ull);
         } else {
             for (int32_t v = tid; v < n; v += T) {
                 setD(v, (v == s) ? 0u : INF32);
@@ -588,95 +642,125 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         }
                         wcur += (int32_t)__popcll(__ballot(valid));
                     }
-                    for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int, int, int) {
+                    // device-memory counts: each node's count is the sum over its own arcs
+                    // (pull), so the wave sums its lanes' terms per node (segmented sums,
+                    // carried across rounds in the node's lane) and stores it once
+                    uint64_t sacc = 0;
+                    auto arc = [&](int owner, int64_t e, bool ok, int incl, int excl, int r, int32_t ucol, uint32_t L) {
                         const int32_t v = __shfl(q, owner, 64);
-                        if (!ok) return;
-                        if (prof) bytes += 12ull;
-                        const int32_t u = col[e] - lo;
-                        const uint32_t L = len ? len[e] : 1u;
-                        const int64_t te = tight ? twin[e] : 0;
-                        // one read of u's distance serves both tests below: if another
-                        // lane lowers it meanwhile, the offer test passes at worst for an
-                        // offer that then changes nothing
-                        uint32_t du = 0, uw = 0;
-                        bool parent = false;
-                        if constexpr (BYTE) {
-                            // u settled at D - L: a settled neighbour lies in [D - L, D],
-                            // L + 1 <= 64 values with distinct residues mod 127
-                            uw = db32[u >> 2];
-                            const uint32_t bu = (uw >> ((u & 3) * 8)) & 0xFFu;
-                            parent = L <= D && settled_b(bu) && (bu & 0x7Fu) == (D - L) % 127u;
-                        } else {
-                            du = D_(u);
-                            parent = du != INF32 && du + L == D;
-                        }
-                        // u is a parent of v if it settled at D - L in an earlier step (eq.
-                        // parentsall / eq. multiparents); the count adds in with an atomic,
-                        // exact for integers, and a wrap of any addition is an overflow
-                        if (v != s && L <= D) {
-                            // Dijkstra_SK (eq. frontierparents): a frontier parent other
-                            // than the source is tight but adds no paths
-                            if (parent &&
-                                !(restrict_ && u != s && nflag && (nflag[lo + u] & NF_BLOCKED))) {
-                                if (tight) {
-                                    const uint64_t t = (uint64_t)(te - abase);
-                                    if (t < tbits) {
-                                        if constexpr (GLOBAL)
-                                            __hip_atomic_fetch_or(gtb + (t >> 5), 1u << (t & 31),
-                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                        else
-                                            atomicOr(&tb[t >> 5], 1u << (t & 31));
+                        uint64_t xs = 0;
+                        if (ok) {
+                            if (prof) bytes += 12ull;
+                            const int32_t u = ucol - lo;
+                            // (device-memory groups read the reverse arc only for tight arcs)
+                            const int64_t te = tight && !GLOBAL ? twin[e] : 0;
+                            // one read of u's distance serves both tests below: if another
+                            // lane lowers it meanwhile, the offer test passes at worst for an
+                            // offer that then changes nothing
+                            uint32_t du = 0, uw = 0;
+                            bool parent = false;
+                            if constexpr (BYTE) {
+                                // u settled at D - L: a settled neighbour lies in [D - L, D],
+                                // L + 1 <= 64 values with distinct residues mod 127
+                                uw = db32[u >> 2];
+                                const uint32_t bu = (uw >> ((u & 3) * 8)) & 0xFFu;
+                                parent = L <= D && settled_b(bu) && (bu & 0x7Fu) == (D - L) % 127u;
+                            } else {
+                                du = D_(u);
+                                parent = du != INF32 && du + L == D;
+                            }
+                            // u is a parent of v if it settled at D - L in an earlier step (eq.
+                            // parentsall / eq. multiparents); the count adds in with an atomic,
+                            // exact for integers, and a wrap of any addition is an overflow
+                            if (v != s && L <= D) {
+                                // Dijkstra_SK (eq. frontierparents): a frontier parent other
+                                // than the source is tight but adds no paths
+                                if (parent &&
+                                    !(restrict_ && u != s && nflag && (nflag[lo + u] & NF_BLOCKED))) {
+                                    if (tight) {
+                                        const uint64_t t = (uint64_t)((GLOBAL ? twin[e] : te) - abase);
+                                        if (t < tbits) {
+                                            if constexpr (GLOBAL)
+                                                __hip_atomic_fetch_or(gtb + (t >> 5), 1u << (t & 31),
+                                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                            else
+                                                atomicOr(&tb[t >> 5], 1u << (t & 31));
+                                        }
+                                    }
+                                    uint64_t x = S_(u);
+                                    if (mult) {
+                                        const uint64_t m = mult[e];
+                                        if (__umul64hi(x, m) != 0) ovf = true;
+                                        x *= m;
+                                    }
+                                    if constexpr (GLOBAL) {
+                                        xs = x;
+                                    } else if (x) {
+                                        const uint64_t old = addS(v, x);
+                                        if (old + x < old) ovf = true;
                                     }
                                 }
-                                uint64_t x = S_(u);
-                                if (mult) {
-                                    const uint64_t m = mult[e];
-                                    if (__umul64hi(x, m) != 0) ovf = true;
-                                    x *= m;
-                                }
-                                if (x) {
-                                    const uint64_t old = addS(v, x);
-                                    if (old + x < old) ovf = true;
-                                }
                             }
-                        }
-                        // offers: all above D, so they never meet the parent test above
-                        const uint32_t nv = D + L;
-                        if constexpr (BYTE) {
-                            // lower u's byte to nv's residue unless u is settled or already
-                            // pending at most L above D (offsets of pending bytes from D
-                            // are at most the longest arc); a compare-and-swap on the word
-                            // holding it, retried while other bytes of the word change
-                            const int sh = (u & 3) * 8;
-                            for (;;) {
-                                const uint32_t bu = (uw >> sh) & 0xFFu;
-                                if (settled_b(bu) || (bu != 0xFFu && ((bu - D) & 127u) <= L)) break;
-                                const uint32_t nw = (uw & ~(0xFFu << sh)) | ((nv & 127u) << sh);
-                                const uint32_t prev = atomicCAS(&db32[u >> 2], uw, nw);
-                                if (prev == uw) {
+                            // offers: all above D, so they never meet the parent test above
+                            const uint32_t nv = D + L;
+                            if constexpr (BYTE) {
+                                // lower u's byte to nv's residue unless u is settled or already
+                                // pending at most L above D (offsets of pending bytes from D
+                                // are at most the longest arc); a compare-and-swap on the word
+                                // holding it, retried while other bytes of the word change
+                                const int sh = (u & 3) * 8;
+                                for (;;) {
+                                    const uint32_t bu = (uw >> sh) & 0xFFu;
+                                    if (settled_b(bu) || (bu != 0xFFu && ((bu - D) & 127u) <= L)) break;
+                                    const uint32_t nw = (uw & ~(0xFFu << sh)) | ((nv & 127u) << sh);
+                                    const uint32_t prev = atomicCAS(&db32[u >> 2], uw, nw);
+                                    if (prev == uw) {
+                                        mn = min(mn, nv);
+                                        break;
+                                    }
+                                    uw = prev;
+                                }
+                            } else if (nv < du) {
+                                if (bucket) {
+                                    // a bit per successful offer (a failed one leaves none)
+                                    const uint32_t old = minD(u, nv);
+                                    if (nv < old) {
+                                        const uint32_t bit = 1u << (u & 31);
+                                        const uint32_t ow = atomicOr(&bm[(size_t)(nv & RM) * W + (u >> 5)], bit);
+                                        if (!(ow & bit)) atomicAdd(&bc[cidx(nv)], 1u);
+                                    }
+                                } else {
+                                    // the smallest offer to a node always lands, so the least
+                                    // offer made is the least new tentative distance, and no
+                                    // offer has to wait for the atomic's old value
+                                    minD(u, nv);
                                     mn = min(mn, nv);
-                                    break;
                                 }
-                                uw = prev;
-                            }
-                        } else if (nv < du) {
-                            if (bucket) {
-                                // a bit per successful offer (a failed one leaves none)
-                                const uint32_t old = minD(u, nv);
-                                if (nv < old) {
-                                    const uint32_t bit = 1u << (u & 31);
-                                    const uint32_t ow = atomicOr(&bm[(size_t)(nv & RM) * W + (u >> 5)], bit);
-                                    if (!(ow & bit)) atomicAdd(&bc[cidx(nv)], 1u);
-                                }
-                            } else {
-                                // the smallest offer to a node always lands, so the least
-                                // offer made is the least new tentative distance, and no
-                                // offer has to wait for the atomic's old value
-                                minD(u, nv);
-                                mn = min(mn, nv);
                             }
                         }
+                        if constexpr (GLOBAL) {
+                            const int seg = max(__shfl(excl, owner, 64) - r, 0);
+                            xs = wseg_sum_u64(xs, seg, &ovf);
+                            const int ab = max(excl - r, 0), bb = min(incl - r, 64);
+                            const uint64_t part = (uint64_t)__shfl((long long)xs, max(bb - 1, 0), 64);
+                            if (bb > ab) {
+                                if (sacc + part < sacc) ovf = true;
+                                sacc += part;
+                            }
+                        }
+                    };
+                    for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
+                        int32_t c = 0;
+                        uint32_t L = 1u;
+                        if (ok) {
+                            c = col[e];
+                            L = len ? len[e] : 1u;
+                        }
+                        arc(owner, e, ok, incl, excl, r, c, L);
                     });
+                    if constexpr (GLOBAL) {
+                        if (valid && q != s) setS(q, sacc);
+                    }
                 };
             if (bucket) {
                 // both visits queue the same nodes in the same order, so the choice (made
@@ -759,47 +843,80 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             GAS uint32_t* __restrict__ od = gas(R.odist) + (int64_t)b * n;
             GAS uint64_t* __restrict__ os = gas(R.osig) + (int64_t)b * n;
             for (int32_t v = tid; v < n; v += T) {
-                od[v] = D_(v);
-                os[v] = S_(v);
+                const uint32_t dv = D_(v);
+                od[v] = dv;
+                os[v] = dv == INF32 ? 0ull : S_(v);
             }
         }
         if (!bwd) {
             // (the last step ended with a barrier: every count is final)
             for (int32_t v = tid; v < n; v += T) {
-                idist[(int64_t)v * 64 + b] = D_(v);
-                isig[(int64_t)v * 64 + b] = S_(v);
+                const uint32_t dv = D_(v);
+                idist[(int64_t)v * 64 + b] = dv;
+                isig[(int64_t)v * 64 + b] = dv == INF32 ? 0ull : S_(v);
             }
             __syncthreads();
             continue;
         }
 
         // ------------------------------------------- interior rows: d and sigma ----
+        // Each wave takes 64 table rows at a time and spreads their entries over its lanes
+        // (as the sweeps spread a queue's arcs): first the row minimum of d(s,f) + d(f,v)
+        // by segmented minima, then the sum of sigma(s,f) * sigma(f,v) over the entries
+        // that attain it by segmented sums (eq. localcentrality's tight frontiers).
         if (cent) {
-            for (int32_t i = tid; i < R.tn; i += T) {
-                const int64_t e0 = trow[R.t_lo + i], e1 = trow[R.t_lo + i + 1];
-                uint32_t dv = INF32;
-                for (int64_t e = e0; e < e1; ++e) {
-                    const uint32_t tf = D_(tcol[e] - lo);
-                    if (tf != INF32) dv = min(dv, tf + tlen[e]);
+            for (int32_t r0 = (tid >> 6) * 64; r0 < R.tn; r0 += T) {
+                const int32_t i = r0 + lane;
+                const bool valid = i < R.tn;
+                int64_t e0 = 0;
+                int deg = 0;
+                if (valid) {
+                    e0 = trow[R.t_lo + i];
+                    deg = (int)(trow[R.t_lo + i + 1] - e0);
+                    if (prof) bytes += 32ull * (unsigned long long)deg;
                 }
-                uint64_t sv = 0;
+                uint32_t rmin = INF32;
+                for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
+                    const int seg = max(__shfl(excl, owner, 64) - r, 0);
+                    uint32_t val = INF32;
+                    if (ok) {
+                        const uint32_t tf = D_(tcol[e] - lo);
+                        if (tf != INF32) val = tf + tlen[e];
+                    }
+                    val = wseg_min_u32(val, seg);
+                    const int ab = max(excl - r, 0), bb = min(incl - r, 64);
+                    const uint32_t part = (uint32_t)__shfl((int)val, max(bb - 1, 0), 64);
+                    if (bb > ab) rmin = min(rmin, part);
+                });
+                uint64_t rsum = 0;
                 bool o2 = false;
-                if (dv != INF32) {
-                    for (int64_t e = e0; e < e1; ++e) {
+                for_queue_arcs(e0, rmin != INF32 ? deg : 0, wq, [&](int owner, int64_t e, bool ok, int incl, int excl,
+                                                                    int r) {
+                    const int seg = max(__shfl(excl, owner, 64) - r, 0);
+                    const uint32_t m = (uint32_t)__shfl((int)rmin, owner, 64);
+                    uint64_t c = 0;
+                    if (ok) {
                         const int32_t f = tcol[e] - lo;
                         const uint32_t tf = D_(f);
-                        if (tf == INF32 || tf + tlen[e] != dv) continue;
-                        const uint64_t a = S_(f), m = tsig[e];
-                        if (__umul64hi(a, m) != 0) o2 = true;
-                        const uint64_t r = sv + a * m;
-                        if (r < sv) o2 = true;
-                        sv = r;
+                        if (tf != INF32 && tf + tlen[e] == m) {
+                            const uint64_t a = S_(f), t = tsig[e];
+                            if (__umul64hi(a, t) != 0) o2 = true;
+                            c = a * t;
+                        }
                     }
+                    c = wseg_sum_u64(c, seg, &o2);
+                    const int ab = max(excl - r, 0), bb = min(incl - r, 64);
+                    const uint64_t part = (uint64_t)__shfl((long long)c, max(bb - 1, 0), 64);
+                    if (bb > ab) {
+                        if (rsum + part < rsum) o2 = true;
+                        rsum += part;
+                    }
+                });
+                if (valid) {
+                    idist[i] = rmin;
+                    isig[i] = rsum;
                 }
-                idist[i] = dv;
-                isig[i] = sv;
                 if (o2) ovf_flag = 1u;
-                if (prof) bytes += 32ull * (unsigned long long)(e1 - e0);
             }
         }
         __syncthreads();
@@ -929,19 +1046,50 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         }
 
         // --------------------------------------------- interior rows: delta ----
+        // the same spread: sum of sigma(f,v) * coef(s,f) over the frontiers f for which v
+        // lies on a shortest path from s to f, times sigma(s,v) (eq. localcentrality)
         if (cent) {
-            for (int32_t i = tid; i < R.tn; i += T) {
-                const uint32_t dv = idist[i];
-                if (dv == INF32) continue;
-                const int64_t e0 = trow[R.t_lo + i], e1 = trow[R.t_lo + i + 1];
-                double acc = 0.0;
-                for (int64_t e = e0; e < e1; ++e) {
-                    const int32_t f = tcol[e] - lo;
-                    const uint32_t tf = D_(f);
-                    if (tf == INF32 || tf != dv + tlen[e]) continue;
-                    acc += (double)tsig[e] * __longlong_as_double((long long)S_(f));
+            for (int32_t r0 = (tid >> 6) * 64; r0 < R.tn; r0 += T) {
+                const int32_t i = r0 + lane;
+                const bool valid = i < R.tn;
+                uint32_t dv = INF32;
+                int64_t e0 = 0;
+                int deg = 0;
+                if (valid) {
+                    dv = idist[i];
+                    e0 = trow[R.t_lo + i];
+                    deg = dv == INF32 ? 0 : (int)(trow[R.t_lo + i + 1] - e0);
                 }
-                cint[i] += (double)isig[i] * acc;
+                double acc = 0.0;
+                for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
+                    const int seg = max(__shfl(excl, owner, 64) - r, 0);
+                    const uint32_t m = (uint32_t)__shfl((int)dv, owner, 64);
+                    double c = 0.0;
+                    if (ok) {
+                        const int32_t f = tcol[e] - lo;
+                        const uint32_t L = tlen[e];
+                        bool on;
+                        if constexpr (BYTE) {
+                            // d(s,f) lies in [d(s,v) - L, d(s,v) + L]: residues decide
+                            // when 2L + 1 <= 127, the exact distance otherwise
+                            if (L <= 63) {
+                                const uint32_t bf = db[f];
+                                on = settled_b(bf) && (bf & 0x7Fu) == (m + L) % 127u;
+                            } else {
+                                on = D_(f) == m + L;
+                            }
+                        } else {
+                            const uint32_t tf = D_(f);
+                            on = tf != INF32 && tf == m + L;
+                        }
+                        if (on) c = (double)tsig[e] * __longlong_as_double((long long)S_(f));
+                    }
+                    c = wseg_sum(c, seg);
+                    const int ab = max(excl - r, 0), bb = min(incl - r, 64);
+                    const double part = __shfl(c, max(bb - 1, 0), 64);
+                    if (bb > ab) acc += part;
+                });
+                if (valid && dv != INF32) cint[i] += (double)isig[i] * acc;
             }
         }
         __syncthreads();
@@ -1209,6 +1357,12 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
             return fail(BC_E_INVAL, "resident: no record buffers for a backward group");
         cls[c].push_back(r);
     }
+    // largest groups first in each class: workgroups start in index order, so the
+    // longest ones do not start last (each group's work is independent of its slot)
+    for (auto& cv : cls)
+        std::stable_sort(cv.begin(), cv.end(), [](const RGroup& x, const RGroup& y) {
+            return (int64_t)x.nsrc * ((int64_t)x.hi - x.lo + x.tn) > (int64_t)y.nsrc * ((int64_t)y.hi - y.lo + y.tn);
+        });
     L->d_err = a.take<uint32_t>(1);
     RCtx* d_ctx = a.take<RCtx>(std::max<size_t>(ctx.size(), 1));
     int32_t* d_src = a.take<int32_t>(std::max<size_t>(src.size(), 1));
@@ -1235,27 +1389,76 @@ int resident_upload(hipStream_t s, Arena& a, const std::vector<GroupDesc>& group
     return resident_upload(s, a, ptr.data(), ptr.size(), L);
 }
 
+static void launch_class(int c, hipStream_t s, const ResidentLaunch& L, unsigned long long* prof) {
+    const dim3 grid((unsigned)L.count[c]);
+    if (c == 4)
+        hipLaunchKernelGGL((k_resident<1024, true, true>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
+                           L.d_src, L.d_err, prof);
+    else if (c == 3)
+        hipLaunchKernelGGL((k_resident<1024, true, false>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
+                           L.d_src, L.d_err, prof);
+    else if (c == 2)
+        hipLaunchKernelGGL((k_resident<1024, false, false>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
+                           L.d_src, L.d_err, prof);
+    else if (c == 1)
+        hipLaunchKernelGGL((k_resident<512, false, false>), grid, dim3(512), L.lds[c], s, L.d_rg[c], L.d_ctx,
+                           L.d_src, L.d_err, prof);
+    else
+        hipLaunchKernelGGL((k_resident<256, false, false>), grid, dim3(256), L.lds[c], s, L.d_rg[c], L.d_ctx,
+                           L.d_src, L.d_err, prof);
+}
+
+// Streams and events on which the classes of a launch issued to stream s run side by
+// side: one set per issuing stream, made on first use (default priority) and kept.
+struct SideSet {
+    hipStream_t st[5] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[5] = {};
+};
+
+static int side_set(hipStream_t s, SideSet** out) {
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, SideSet> sets;
+    int dev = 0;
+    BC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = sets.find({dev, s});
+    if (it == sets.end()) {
+        SideSet z;
+        for (int c = 0; c < 5; ++c) {
+            BC_HIP(hipStreamCreateWithFlags(&z.st[c], hipStreamNonBlocking));
+            BC_HIP(hipEventCreateWithFlags(&z.join[c], hipEventDisableTiming));
+        }
+        BC_HIP(hipEventCreateWithFlags(&z.fork, hipEventDisableTiming));
+        it = sets.emplace(std::make_pair(dev, s), z).first;
+    }
+    *out = &it->second;
+    return BC_OK;
+}
+
 int resident_launch(hipStream_t s, const ResidentLaunch& L) {
     unsigned long long* prof = profiler().on && profiler().d_bytes ? profiler().d_bytes + L.kind : nullptr;
+    int ncls = 0;
+    for (int c = 0; c < 5; ++c) ncls += L.count[c] > 0;
+    if (ncls == 0) return BC_OK;
+    KTimer kt(L.kind, s);
+    if (ncls == 1) {
+        for (int c = 0; c < 5; ++c)
+            if (L.count[c]) launch_class(c, s, L, prof);
+        BC_HIP(hipGetLastError());
+        return BC_OK;
+    }
+    // several classes: each on a side stream, all after the work already on s, and s
+    // waits for all of them (under capture these become parallel branches of the graph)
+    SideSet* ss = nullptr;
+    BC_TRY(side_set(s, &ss));
+    BC_HIP(hipEventRecord(ss->fork, s));
     for (int c = 4; c >= 0; --c) {
         if (!L.count[c]) continue;
-        KTimer kt(L.kind, s);
-        const dim3 grid((unsigned)L.count[c]);
-        if (c == 4)
-            hipLaunchKernelGGL((k_resident<1024, true, true>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
-                               L.d_src, L.d_err, prof);
-        else if (c == 3)
-            hipLaunchKernelGGL((k_resident<1024, true, false>), grid, dim3(1024), L.lds[c], s, L.d_rg[c], L.d_ctx,
-                               L.d_src, L.d_err, prof);
-        else if (c == 2)
-            hipLaunchKernelGGL((k_resident<1024, false, false>), grid, dim3(1024), L.lds[c], s, L.d_rg[c],
-                               L.d_ctx, L.d_src, L.d_err, prof);
-        else if (c == 1)
-            hipLaunchKernelGGL((k_resident<512, false, false>), grid, dim3(512), L.lds[c], s, L.d_rg[c], L.d_ctx,
-                               L.d_src, L.d_err, prof);
-        else
-            hipLaunchKernelGGL((k_resident<256, false, false>), grid, dim3(256), L.lds[c], s, L.d_rg[c], L.d_ctx,
-                               L.d_src, L.d_err, prof);
+        BC_HIP(hipStreamWaitEvent(ss->st[c], ss->fork, 0));
+        launch_class(c, ss->st[c], L, prof);
+        BC_HIP(hipEventRecord(ss->join[c], ss->st[c]));
+        BC_HIP(hipStreamWaitEvent(s, ss->join[c], 0));
     }
     BC_HIP(hipGetLastError());
     return BC_OK;
