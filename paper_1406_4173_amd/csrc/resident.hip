@@ -430,6 +430,8 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     __shared__ uint32_t fwd_next[3];  // rotating: step k writes [k%3], clears [(k+1)%3]
     __shared__ uint32_t ovf_flag;
     __shared__ int32_t wqueue[T / 64][WQ];
+    // device-memory groups: per wave, the path counts of its queue's nodes being summed
+    __shared__ unsigned long long wsig[GLOBAL ? T / 64 : 1][64];
 
     const RGroup& R = rgs[blockIdx.x];
     const RCtx& C = ctxs[R.ctx];
@@ -455,6 +457,9 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     uint8_t* __restrict__ db = lds;
     uint32_t* db32 = reinterpret_cast<uint32_t*>(lds);
     auto settled_b = [](uint32_t b) { return b >= 0x80u && b != 0xFFu; };
+    // (x - L) mod 127 and (x + L) mod 127 for a residue x < 127 and 0 <= L <= 126
+    auto sub127 = [](uint32_t x, uint32_t L) { return x >= L ? x - L : x + 127u - L; };
+    auto add127 = [](uint32_t x, uint32_t L) { return x + L >= 127u ? x + L - 127u : x + L; };
     auto D_ = [&](int32_t i) -> uint32_t {
         if constexpr (BYTE)
             return settled_b(db[i]) ? __hip_atomic_load(gdist + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
@@ -621,6 +626,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         int32_t wcur = 0, wseg = 0, wstep0 = 0, nsteps = 0;
         for (int it = 0, k = 0;; ++it) {
             uint32_t mn = INF32;
+            const uint32_t d127 = D % 127u;
             if (bwd && tid == 0) steps[k] = D;
             auto fbody =
                 [&](int32_t q, bool valid) {
@@ -645,7 +651,8 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                     // device-memory counts: each node's count is the sum over its own arcs
                     // (pull), so the wave sums its lanes' terms per node (segmented sums,
                     // carried across rounds in the node's lane) and stores it once
-                    uint64_t sacc = 0;
+                    // (per wave: slot i of wsig sums the terms of queue slot i's node)
+                    if constexpr (GLOBAL) wsig[tid >> 6][lane] = 0ull;
                     auto arc = [&](int owner, int64_t e, bool ok, int incl, int excl, int r, int32_t ucol, uint32_t L) {
                         const int32_t v = __shfl(q, owner, 64);
                         uint64_t xs = 0;
@@ -664,7 +671,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                 // L + 1 <= 64 values with distinct residues mod 127
                                 uw = db32[u >> 2];
                                 const uint32_t bu = (uw >> ((u & 3) * 8)) & 0xFFu;
-                                parent = L <= D && settled_b(bu) && (bu & 0x7Fu) == (D - L) % 127u;
+                                parent = L <= D && settled_b(bu) && (bu & 0x7Fu) == sub127(d127, L);
                             } else {
                                 du = D_(u);
                                 parent = du != INF32 && du + L == D;
@@ -739,13 +746,9 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                             }
                         }
                         if constexpr (GLOBAL) {
-                            const int seg = max(__shfl(excl, owner, 64) - r, 0);
-                            xs = wseg_sum_u64(xs, seg, &ovf);
-                            const int ab = max(excl - r, 0), bb = min(incl - r, 64);
-                            const uint64_t part = (uint64_t)__shfl((long long)xs, max(bb - 1, 0), 64);
-                            if (bb > ab) {
-                                if (sacc + part < sacc) ovf = true;
-                                sacc += part;
+                            if (xs) {
+                                const unsigned long long o = atomicAdd(&wsig[tid >> 6][owner], (unsigned long long)xs);
+                                if (o + xs < o) ovf = true;
                             }
                         }
                     };
@@ -759,7 +762,8 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         arc(owner, e, ok, incl, excl, r, c, L);
                     });
                     if constexpr (GLOBAL) {
-                        if (valid && q != s) setS(q, sacc);
+                        // (the wave's own LDS atomics complete in order before this read)
+                        if (valid && q != s) setS(q, (uint64_t)wsig[tid >> 6][lane]);
                     }
                 };
             if (bucket) {
@@ -897,8 +901,23 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                     uint64_t c = 0;
                     if (ok) {
                         const int32_t f = tcol[e] - lo;
-                        const uint32_t tf = D_(f);
-                        if (tf != INF32 && tf + tlen[e] == m) {
+                        const uint32_t L = tlen[e];
+                        bool on;
+                        if constexpr (BYTE) {
+                            // d(s,f) lies in [m - L, m + L] (m = d(s,v)): residues decide
+                            // when L <= 63
+                            if (L <= 63) {
+                                const uint32_t bf = db[f];
+                                on = settled_b(bf) && (bf & 0x7Fu) == sub127(m % 127u, L);
+                            } else {
+                                const uint32_t tf = D_(f);
+                                on = tf != INF32 && tf + L == m;
+                            }
+                        } else {
+                            const uint32_t tf = D_(f);
+                            on = tf != INF32 && tf + L == m;
+                        }
+                        if (on) {
                             const uint64_t a = S_(f), t = tsig[e];
                             if (__umul64hi(a, t) != 0) o2 = true;
                             c = a * t;
@@ -927,6 +946,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         int32_t seg = wseg - 1;
         for (int k = nsteps - 1; k >= 1; --k) {
             D = steps[k];
+            const uint32_t d127 = D % 127u;
             auto body = [&](int32_t q, int64_t e0, int deg, bool valid) {
                     double prev = 0.0, ind = 0.0, acc = 0.0;
                     if (prof && valid) bytes += 8ull;
@@ -998,7 +1018,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                 // a settled neighbour of a node at D lies in [D - L, D + L],
                                 // at most 127 values: residues mod 127 are distinct
                                 const uint32_t bx = db[x];
-                                child = settled_b(bx) && (bx & 0x7Fu) == (D + L) % 127u;
+                                child = settled_b(bx) && (bx & 0x7Fu) == add127(d127, L);
                             } else {
                                 const uint32_t dx = D_(x);
                                 child = dx != INF32 && dx == D + L;
@@ -1074,7 +1094,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                             // when 2L + 1 <= 127, the exact distance otherwise
                             if (L <= 63) {
                                 const uint32_t bf = db[f];
-                                on = settled_b(bf) && (bf & 0x7Fu) == (m + L) % 127u;
+                                on = settled_b(bf) && (bf & 0x7Fu) == add127(m % 127u, L);
                             } else {
                                 on = D_(f) == m + L;
                             }
@@ -1126,7 +1146,8 @@ size_t bucket_bytes(int64_t range, int lg) {
 
 struct ResidentLimits {
     bool init = false;
-    size_t lds = 0;  // usable dynamic LDS per workgroup
+    size_t lds = 0;     // usable dynamic LDS per workgroup, state in LDS (classes 0-2)
+    size_t lds_dev = 0;  // the same for the device-memory classes (3, 4: more static LDS)
 };
 
 ResidentLimits& limits() {
@@ -1140,24 +1161,25 @@ int query_limits() {
     int dev = 0, v = 0;
     BC_HIP(hipGetDevice(&dev));
     BC_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    // keep room for the kernel's own static LDS (wave queues and step variables)
-    const size_t stat = 16 * WQ * 4 + 1024;
-    size_t usable = (size_t)v > stat ? (size_t)v - stat : 0;
-    if (usable > 65536) {
-        if (hipFuncSetAttribute((const void*)k_resident<1024, true, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_resident<1024, true, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_resident<1024, false, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_resident<512, false, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_resident<256, false, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)usable) != hipSuccess) {
+    // each instance: the device's LDS less its own static LDS (wave queues and step
+    // variables, and for device-memory groups the per-wave count sums)
+    const void* fns[5] = {(const void*)k_resident<1024, false, false>, (const void*)k_resident<512, false, false>,
+                          (const void*)k_resident<256, false, false>, (const void*)k_resident<1024, true, false>,
+                          (const void*)k_resident<1024, true, true>};
+    size_t use[5];
+    for (int i = 0; i < 5; ++i) {
+        hipFuncAttributes fa;
+        BC_HIP(hipFuncGetAttributes(&fa, fns[i]));
+        const size_t stat = (size_t)fa.sharedSizeBytes + 256;
+        use[i] = (size_t)v > stat ? (size_t)v - stat : 0;
+        if (use[i] > 65536 &&
+            hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)use[i]) != hipSuccess) {
             (void)hipGetLastError();
-            usable = 65536 - stat;
+            use[i] = 65536 > stat ? 65536 - stat : 0;
         }
     }
+    L.lds_dev = std::min(use[3], use[4]);
+    const size_t usable = std::min({use[0], use[1], use[2]});
     L.lds = usable;
     L.init = true;
     return BC_OK;
@@ -1300,12 +1322,12 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         if (state > limits().lds) {
             if (!G.gdist || !G.gsig) return fail(BC_E_INVAL, "resident: no state buffers for a large range");
             if (G.gtb && G.g.twin && (G.flags & GF_BACKWARD) && G.arcs > 0) tw = (int32_t)((G.arcs + 31) / 32);
-            if (byte_state_on() && G.ring_len >= 2 && G.ring_len <= 64 && byte_lds_bytes(range) <= limits().lds) {
+            if (byte_state_on() && G.ring_len >= 2 && G.ring_len <= 64 && byte_lds_bytes(range) <= limits().lds_dev) {
                 c = 4;
                 need = byte_lds_bytes(range);
             } else {
                 c = 3;
-                lg = (lg0 >= 0 && bb <= limits().lds) ? lg0 : -1;
+                lg = (lg0 >= 0 && bb <= limits().lds_dev) ? lg0 : -1;
                 need = lg >= 0 ? bb : 0;
             }
         } else {
