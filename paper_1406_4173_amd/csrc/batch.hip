@@ -211,6 +211,7 @@ static int batch_plain(bc_batch* b, uint32_t flags, double* d_out) {
         D.g.len = G->d_len;
         D.g.nflag = d_flag;
         D.g.twin = G->d_twin;
+        D.g.arc = G->d_arc;
     }
     BC_TRY(run_mixed(W, s, groups, resident, steps));
     BC_TRY(reduce_scores(s, W, groups, n, d_g0, d_g1, d_idx, nullptr, 0.5, d_out, false));
@@ -276,6 +277,7 @@ static int build_plain_plan(bc_batch* b) {
         D.g.len = G->d_len;
         D.g.nflag = d_flag;
         D.g.twin = G->d_twin;
+        D.g.arc = G->d_arc;
         if (!resident_alloc(P->mem, D)) return fail(BC_E_NOMEM, "batch: workspace too small");
     }
     ResidentLaunch L;
@@ -387,6 +389,7 @@ static int pp_groups(const bc_batch* b, const bc_skeleton* sk, bool allow_res, P
                 D.g.mult = sk_mult(sk);
                 D.g.nflag = sk->d_nflag;
                 D.g.twin = sk->d_twin;
+                D.g.arc = sk->d_arc;
                 D.lo = sk_lo;
                 D.hi = sk_hi;
                 D.arc_lo = sk->h_row_ptr[sk_lo];

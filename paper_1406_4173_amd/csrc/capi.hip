@@ -227,18 +227,25 @@ int graph_create(const bc_csr* csr, hipStream_t stream, bc_graph** out) {
             const int32_t* b1 = csr->col + csr->row_ptr[v + 1];
             twin[e] = std::lower_bound(b0, b1, u) - csr->col;
         }
-    size_t bytes = (size_t)(g->n + 1) * 8 + (size_t)g->nnz * (4 * (g->unit ? 1 : 2) + 8) + 4096;
+    // packed arc records: {head, length, reverse arc, multiplicity 1}
+    const bool pack = g->nnz > 0 && g->nnz < ((int64_t)1 << 31);
+    std::vector<ArcRec> arcs(pack ? (size_t)g->nnz : 0);
+    for (int64_t e = 0; pack && e < g->nnz; ++e)
+        arcs[(size_t)e] = ArcRec{(uint32_t)csr->col[e], csr->w ? (uint32_t)csr->w[e] : 1u, (uint32_t)twin[e], 1u};
+    size_t bytes = (size_t)(g->n + 1) * 8 + (size_t)g->nnz * (4 * (g->unit ? 1 : 2) + 8 + (pack ? 16 : 0)) + 4096;
     int rc = g->store.reserve(bytes);
     if (rc) return cleanup(rc);
     g->d_row_ptr = g->store.take<int64_t>(g->n + 1);
     g->d_col = g->store.take<int32_t>(std::max<int64_t>(g->nnz, 1));
     if (!g->unit) g->d_len = g->store.take<uint32_t>(std::max<int64_t>(g->nnz, 1));
     g->d_twin = g->store.take<int64_t>(std::max<int64_t>(g->nnz, 1));
+    if (pack) g->d_arc = g->store.take<ArcRec>((size_t)g->nnz);
     if (hipMemcpyAsync(g->d_row_ptr, csr->row_ptr, (size_t)(g->n + 1) * 8, hipMemcpyHostToDevice, stream) ||
         (g->nnz && hipMemcpyAsync(g->d_col, csr->col, (size_t)g->nnz * 4, hipMemcpyHostToDevice, stream)) ||
         (!g->unit && g->nnz &&
          hipMemcpyAsync(g->d_len, csr->w, (size_t)g->nnz * 4, hipMemcpyHostToDevice, stream)) ||
         (g->nnz && hipMemcpyAsync(g->d_twin, twin.data(), (size_t)g->nnz * 8, hipMemcpyHostToDevice, stream)) ||
+        (pack && hipMemcpyAsync(g->d_arc, arcs.data(), (size_t)g->nnz * 16, hipMemcpyHostToDevice, stream)) ||
         hipStreamSynchronize(stream)) {
         return cleanup(fail(BC_E_DEVICE, "graph upload failed"));
     }
@@ -306,6 +313,7 @@ int plain_resident(bc_graph* g, Arena& W, bool grow, const int32_t* S, int32_t n
         G.g.len = g->d_len;
         G.g.nflag = d_flag;
         G.g.twin = g->d_twin;
+        G.g.arc = g->d_arc;
     }
     const size_t mark = W.used;
     const int32_t per_wave =
@@ -373,6 +381,7 @@ int plain_run(bc_graph* g, const int32_t* S, int32_t nS, const int32_t* S_dev, u
             G.g.len = g->d_len;
             G.g.nflag = d_flag;
             G.g.twin = g->d_twin;
+            G.g.arc = g->d_arc;
             G.lo = 0;
             G.hi = n;
             G.arc_lo = 0;
@@ -485,6 +494,7 @@ static int sssp_resident(bc_graph* g, const int32_t* src, int32_t nsrc, int64_t*
             G.g.len = g->d_len;
             G.g.nflag = d_flag;
             G.g.twin = g->d_twin;
+            G.g.arc = g->d_arc;
         }
         return BC_OK;
     };

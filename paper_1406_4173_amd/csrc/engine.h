@@ -32,6 +32,11 @@ enum : int32_t { PH_DONE = 0, PH_FWD = 1, PH_BWD = 2, PH_CENT = 3 };
 
 enum : uint32_t { ERR_OVERFLOW = 1u, ERR_HIST = 2u, ERR_REC = 4u, ERR_TWIN = 8u };
 
+// An arc's head, length, reverse arc and multiplicity in one 16-byte record.
+struct __align__(16) ArcRec {
+    uint32_t head, len, twin, mult;
+};
+
 struct EGraph {
     const int64_t* row_ptr = nullptr;  // [nodes+1]
     const int32_t* col = nullptr;      // [arcs]
@@ -39,6 +44,10 @@ struct EGraph {
     const uint64_t* mult = nullptr;    // [arcs]; nullptr = all 1
     const uint8_t* nflag = nullptr;    // [nodes] NF_* bits; nullptr = none
     const int64_t* twin = nullptr;     // [arcs] index of the reverse arc (backward groups)
+    // [arcs] the same four per arc in one 16-byte record (head, length, reverse arc,
+    // multiplicity, each uint32), or nullptr; device-memory groups read it, so that an
+    // arc's reverse arc and multiplicity come in the line that holds its head
+    const ArcRec* arc = nullptr;
 };
 
 struct GroupDesc {

@@ -20,6 +20,7 @@ struct bc_graph {
     int32_t* d_col = nullptr;
     uint32_t* d_len = nullptr;  // null for unit weights
     int64_t* d_twin = nullptr;  // reverse arc of each arc
+    bcpp::ArcRec* d_arc = nullptr;    // packed arc records (EGraph::arc), or null
     bcpp::Arena store;  // graph arrays
     bcpp::Arena work;   // per-call workspace
     bcpp::Arena out;    // staging for host-pointer outputs
@@ -46,6 +47,8 @@ struct bc_skeleton {
     uint32_t* d_len = nullptr;     // [m_arcs]
     uint64_t* d_mult = nullptr;    // [m_arcs]
     int64_t* d_twin = nullptr;     // [m_arcs] reverse arc
+    bcpp::ArcRec* d_arc = nullptr;       // [m_arcs] packed arc records (EGraph::arc), or null
+    bcpp::ArcRec* d_arc_store = nullptr;  // their storage (filled by every build or replay)
     std::vector<int64_t> h_row_ptr;  // host copy of d_row_ptr
     uint8_t* d_nflag = nullptr;    // [n_sk] NF_TARGET
     int64_t* d_trow = nullptr;     // [n_int+1]

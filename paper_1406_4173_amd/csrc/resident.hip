@@ -418,6 +418,12 @@ __device__ __forceinline__ GAS T* gas(T* p) {
     return (GAS T*)p;
 }
 
+// One packed arc record (the four 32-bit fields are adjacent and 16-byte aligned).
+__device__ __forceinline__ ArcRec load_arc(const GAS ArcRec* p, int64_t e) {
+    const GAS uint32_t* q = (const GAS uint32_t*)(p + e);
+    return ArcRec{q[0], q[1], q[2], q[3]};
+}
+
 
 template <int T, bool GLOBAL, bool BYTE>
 __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
@@ -504,6 +510,9 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     const GAS int32_t* __restrict__ col = gas(C.g.col);
     const GAS uint32_t* __restrict__ len = gas(C.g.len);
     const GAS uint64_t* __restrict__ mult = gas(C.g.mult);
+    // packed arc records (device-memory groups): head, length, reverse arc and
+    // multiplicity of an arc in one 16-byte load
+    const GAS ArcRec* __restrict__ arcp = GLOBAL ? gas(C.g.arc) : nullptr;
     const GAS uint8_t* __restrict__ nflag = gas(C.g.nflag);
     const GAS int64_t* __restrict__ trow = gas(C.trow);
     const GAS int32_t* __restrict__ tcol = gas(C.tcol);
@@ -653,7 +662,8 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                     // carried across rounds in the node's lane) and stores it once
                     // (per wave: slot i of wsig sums the terms of queue slot i's node)
                     if constexpr (GLOBAL) wsig[tid >> 6][lane] = 0ull;
-                    auto arc = [&](int owner, int64_t e, bool ok, int incl, int excl, int r, int32_t ucol, uint32_t L) {
+                    auto arc = [&](int owner, int64_t e, bool ok, int incl, int excl, int r, int32_t ucol, uint32_t L,
+                                   uint32_t tw, uint32_t mu) {
                         const int32_t v = __shfl(q, owner, 64);
                         uint64_t xs = 0;
                         if (ok) {
@@ -685,7 +695,8 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                 if (parent &&
                                     !(restrict_ && u != s && nflag && (nflag[lo + u] & NF_BLOCKED))) {
                                     if (tight) {
-                                        const uint64_t t = (uint64_t)((GLOBAL ? twin[e] : te) - abase);
+                                        const uint64_t t =
+                                            (uint64_t)((GLOBAL ? (arcp ? (int64_t)tw : twin[e]) : te) - abase);
                                         if (t < tbits) {
                                             if constexpr (GLOBAL)
                                                 __hip_atomic_fetch_or(gtb + (t >> 5), 1u << (t & 31),
@@ -696,7 +707,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                     }
                                     uint64_t x = S_(u);
                                     if (mult) {
-                                        const uint64_t m = mult[e];
+                                        const uint64_t m = arcp ? (uint64_t)mu : mult[e];
                                         if (__umul64hi(x, m) != 0) ovf = true;
                                         x *= m;
                                     }
@@ -754,12 +765,20 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                     };
                     for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
                         int32_t c = 0;
-                        uint32_t L = 1u;
+                        uint32_t L = 1u, tw = 0u, mu = 1u;
                         if (ok) {
-                            c = col[e];
-                            L = len ? len[e] : 1u;
+                            if (arcp) {
+                                const ArcRec a = load_arc(arcp, e);
+                                c = (int32_t)a.head;
+                                L = a.len;
+                                tw = a.twin;
+                                mu = a.mult;
+                            } else {
+                                c = col[e];
+                                L = len ? len[e] : 1u;
+                            }
                         }
-                        arc(owner, e, ok, incl, excl, r, c, L);
+                        arc(owner, e, ok, incl, excl, r, c, L, tw, mu);
                     });
                     if constexpr (GLOBAL) {
                         // (the wave's own LDS atomics complete in order before this read)
@@ -995,8 +1014,14 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                     pos = select_bit(tb_ld, ~ao, (int)j);
                                 }
                                 const int64_t e = abase + pos;
-                                c = __longlong_as_double((long long)S_(col[e] - lo));
-                                if (mult) c *= (double)mult[e];
+                                if (arcp) {
+                                    const ArcRec a = load_arc(arcp, e);
+                                    c = __longlong_as_double((long long)S_((int32_t)a.head - lo));
+                                    if (mult) c *= (double)a.mult;
+                                } else {
+                                    c = __longlong_as_double((long long)S_(col[e] - lo));
+                                    if (mult) c *= (double)mult[e];
+                                }
                             }
                             c = wseg_sum(c, seg);
                             const int ab = max(excl - r, 0), b = min(incl - r, 64);
@@ -1011,8 +1036,13 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         double c = 0.0;
                         if (ok) {
                             if (prof) bytes += 20ull;
-                            const int32_t x = col[e] - lo;
-                            const uint32_t L = len ? len[e] : 1u;
+                            ArcRec a;
+                            if (arcp)
+                                a = load_arc(arcp, e);
+                            else
+                                a = ArcRec{(uint32_t)col[e], len ? len[e] : 1u, 0u, 1u};
+                            const int32_t x = (int32_t)a.head - lo;
+                            const uint32_t L = a.len;
                             bool child;
                             if constexpr (BYTE) {
                                 // a settled neighbour of a node at D lies in [D - L, D + L],
@@ -1025,7 +1055,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                             }
                             if (child) {
                                 c = __longlong_as_double((long long)S_(x));
-                                if (mult) c *= (double)mult[e];
+                                if (mult) c *= arcp ? (double)a.mult : (double)mult[e];
                             }
                         }
                         // per-node sums of the round: segmented inclusive scan

@@ -94,6 +94,7 @@ struct SkBuild {
     int32_t* d_srcsk = nullptr;  // target -> skeleton id, or -1 (isolated target)
     uint32_t* d_maxlen = nullptr;
     uint32_t* d_rmax = nullptr;
+    uint32_t* d_bigm = nullptr;  // a multiplicity beyond 32 bits (packed arc records unused)
     GroupDesc* d_desc = nullptr;
     // row lengths (with a trailing zero) and their exclusive scans: the skeleton's
     // and the interior table's row offsets, copied into the skeleton by the fill

@@ -152,6 +152,19 @@ __global__ void k_sk_twin(int32_t nsk, const int64_t* __restrict__ row_ptr,
     }
 }
 
+// Packed arc records {head, length, reverse arc, multiplicity} of the skeleton's m
+// arcs; *big is set if a multiplicity does not fit 32 bits (then the records are not
+// used).
+__global__ void k_pack_arcs(int64_t m, const int32_t* __restrict__ col, const uint32_t* __restrict__ len,
+                            const int64_t* __restrict__ twin, const uint64_t* __restrict__ mult,
+                            ArcRec* __restrict__ arc, uint32_t* __restrict__ big) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const uint64_t mu = mult[e];
+    if (mu > 0xFFFFFFFFull) atomicOr(big, 1u);
+    arc[e] = ArcRec{(uint32_t)col[e], len[e], (uint32_t)twin[e], (uint32_t)mu};
+}
+
 // Table rows of interior nodes: entries (f, d(f,v), sigma(f,v)) over the part's
 // frontier f with sigma > 0, in frontier order. Wave per interior row.
 __global__ void k_table(const GroupDesc* __restrict__ desc, const DskInfo* __restrict__ info,
@@ -682,6 +695,7 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
     d_ibase = W.take<int32_t>(NL);
     d_maxlen = W.take<uint32_t>(1);
     d_rmax = W.take<uint32_t>(1);
+    d_bigm = W.take<uint32_t>(1);
     d_hist = W.take<int32_t>((size_t)ntiles * 256);
     d_hoff = W.take<int32_t>((size_t)ntiles * 256);
     d_scan = W.take<unsigned char>(std::max<size_t>(scan_bytes, 1));
@@ -690,7 +704,7 @@ int SkBuild::upload(Arena& W, hipStream_t s) {
     d_srow = W.take<int64_t>(nsk + 1);
     d_tlen = W.take<int64_t>(nint + 1);
     d_trow = W.take<int64_t>(nint + 1);
-    if (!d_slen || !d_srow || !d_tlen || !d_trow) return fail(BC_E_NOMEM, "partition: workspace too small");
+    if (!d_slen || !d_srow || !d_tlen || !d_trow || !d_bigm) return fail(BC_E_NOMEM, "partition: workspace too small");
     if (!d_keys || !d_keys2 || !d_vals || !d_old || !d_nid || !d_icnt || !d_irp || !d_icol || (weighted && !d_iw) ||
         !d_blk || !d_rcnt || !d_rdeg || !d_rptr || !d_rcol || !d_rw || !d_cdeg || !d_info || !d_il || !d_ig0 ||
         !d_ing || !d_tdeg || !d_inode || !d_out_idx || !d_out_which || !d_nodes || !d_sflag || !d_srcsk ||
@@ -779,6 +793,11 @@ int SkBuild::issue_fill(hipStream_t s, const bc_skeleton* sk) const {
         if (nsk)
             hipLaunchKernelGGL(k_sk_twin, dim3((nsk + 3) / 4), dim3(256), 0, s, nsk, sk->d_row_ptr, d_rdeg,
                                sk->d_col, sk->d_twin);
+        const int64_t m = sk->h_row_ptr.empty() ? 0 : sk->h_row_ptr.back();
+        zero_bytes(s, d_bigm, 4);
+        if (m > 0 && sk->d_arc_store)
+            hipLaunchKernelGGL(k_pack_arcs, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, m, sk->d_col,
+                               sk->d_len, sk->d_twin, sk->d_mult, sk->d_arc_store, d_bigm);
     }
     BC_HIP(hipGetLastError());
     return BC_OK;
@@ -802,7 +821,7 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
     // ---- the skeleton's own store
     const size_t sbytes = (size_t)(nsk + 1) * 8 + (size_t)M * (4 + 4 + 8 + 8) + (size_t)nsk +
                           (size_t)(nint + 1) * 8 + (size_t)T * (4 + 4 + 8) + (size_t)nsk * 4 +
-                          (size_t)nint * 4 + (size_t)n * 5 + 32 * 256;
+                          (size_t)nint * 4 + (size_t)n * 5 + (size_t)M * 16 + 34 * 256;
     Arena* Ap = nullptr;
     BC_TRY(get_store(sbytes, Ap));
     Arena& A = *Ap;
@@ -820,10 +839,12 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
     sk->d_tnode = A.take<int32_t>(std::max(nint, 1));
     sk->d_out_idx = A.take<int32_t>(std::max(n, 1));
     sk->d_out_which = A.take<uint8_t>(std::max(n, 1));
+    sk->d_arc_store = M < ((int64_t)1 << 31) ? A.take<ArcRec>((size_t)std::max<int64_t>(M, 1)) : nullptr;
     if (!sk->d_out_which) return fail(BC_E_NOMEM, "skeleton store too small");
     BC_TRY(issue_fill(s, sk));
-    uint32_t clique_max = 0, rmax = 0;
+    uint32_t clique_max = 0, rmax = 0, bigm = 0;
     std::vector<int32_t> srcsk(nS);
+    BC_HIP(hipMemcpyAsync(&bigm, d_bigm, 4, hipMemcpyDeviceToHost, s));
     BC_HIP(hipMemcpyAsync(&clique_max, d_maxlen, 4, hipMemcpyDeviceToHost, s));
     BC_HIP(hipMemcpyAsync(&rmax, d_rmax, 4, hipMemcpyDeviceToHost, s));
     if (nS) BC_HIP(hipMemcpyAsync(srcsk.data(), d_srcsk, (size_t)nS * 4, hipMemcpyDeviceToHost, s));
@@ -831,6 +852,7 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
 
     sk->graph = g;
     sk->n = n;
+    sk->d_arc = bigm ? nullptr : sk->d_arc_store;
     sk->max_len = (int32_t)std::max<uint32_t>({1u, rmax, clique_max});
     // Brandes_SK sources: targets that have a neighbour (isolated targets reach nobody)
     sk->h_target_sk = srcsk;
@@ -928,6 +950,7 @@ std::vector<GroupDesc> bsk_groups(const bc_skeleton* sk, const int32_t* src, int
         D.g.mult = sk_mult(sk);
         D.g.nflag = sk->d_nflag;
         D.g.twin = sk->d_twin;
+        D.g.arc = sk->d_arc;
         D.lo = lo;
         D.hi = hi;
         D.arc_lo = sk->h_row_ptr[lo];
@@ -967,6 +990,7 @@ std::vector<GroupDesc> resident_bsk_groups(const bc_skeleton* sk, const std::vec
         G.g.mult = sk_mult(sk);
         G.g.nflag = nflag;
         G.g.twin = sk->d_twin;
+        G.g.arc = sk->d_arc;
         G.lo = 0;
         G.hi = sk->n_sk;
         G.arc_lo = 0;
@@ -1045,6 +1069,7 @@ int pp_run(const bc_graph* gc, const bc_skeleton* sk, uint32_t flags, double* ou
             G.g.mult = sk_mult(sk);
             G.g.nflag = sk->d_nflag;
             G.g.twin = sk->d_twin;
+            G.g.arc = sk->d_arc;
             G.lo = 0;
             G.hi = N;
             G.arc_lo = 0;
@@ -1098,6 +1123,7 @@ int sk_sssp_run(const bc_skeleton* sk, const int32_t* src, int32_t nsrc, int64_t
                 G.g.mult = sk_mult(sk);
                 G.g.nflag = sk->d_nflag;
                 G.g.twin = sk->d_twin;
+                G.g.arc = sk->d_arc;
                 G.lo = 0;
                 G.hi = N;
                 G.arc_lo = 0;
