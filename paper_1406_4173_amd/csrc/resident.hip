@@ -898,11 +898,45 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                     deg = (int)(trow[R.t_lo + i + 1] - e0);
                     if (prof) bytes += 32ull * (unsigned long long)deg;
                 }
+                // BYTE: one exact distance per row, its first entry's frontier f0; the
+                // frontiers of one row are all reachable or none (each has a path to v
+                // inside the part), and d(s,f) is within d(f,v) of d(s,v), so
+                // d(s,f) - d(s,f0) follows from the residues when d(f,v) + d(f0,v) <= 63
+                uint32_t adist = INF32, ares = 0u, alen = 0u;
+                if constexpr (BYTE) {
+                    if (valid && deg > 0) {
+                        const int32_t f0 = tcol[e0] - lo;
+                        alen = tlen[e0];
+                        const uint32_t b0 = db[f0];
+                        if (settled_b(b0)) {
+                            adist = D_(f0);
+                            ares = b0 & 0x7Fu;
+                        }
+                    }
+                }
                 uint32_t rmin = INF32;
                 for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
                     const int seg = max(__shfl(excl, owner, 64) - r, 0);
                     uint32_t val = INF32;
-                    if (ok) {
+                    if constexpr (BYTE) {
+                        const uint32_t ad = (uint32_t)__shfl((int)adist, owner, 64);
+                        const uint32_t ar = (uint32_t)__shfl((int)ares, owner, 64);
+                        const uint32_t al = (uint32_t)__shfl((int)alen, owner, 64);
+                        if (ok && ad != INF32) {
+                            const int32_t f = tcol[e] - lo;
+                            const uint32_t L = tlen[e];
+                            uint32_t tf;
+                            if (L + al <= 63u) {
+                                int dl = (int)(db[f] & 0x7Fu) - (int)ar;
+                                if (dl > 63) dl -= 127;
+                                if (dl < -63) dl += 127;
+                                tf = (uint32_t)((int)ad + dl);
+                            } else {
+                                tf = D_(f);
+                            }
+                            val = tf + L;
+                        }
+                    } else if (ok) {
                         const uint32_t tf = D_(tcol[e] - lo);
                         if (tf != INF32) val = tf + tlen[e];
                     }
