@@ -460,7 +460,12 @@ static int admit_prepared(bc_server* sv, Query* q) {
             C = sv->caches[q->gid].get();
             part = sv->parts[q->gid].data();
         }
-        if (C && C->ok) {
+        // (BCPP_SERVE_CACHE=0 runs every part's Dijkstra_SK, for comparisons)
+        static const bool use_cache = [] {
+            const char* e = getenv("BCPP_SERVE_CACHE");
+            return !(e && e[0] == '0');
+        }();
+        if (use_cache && C && C->ok) {
             std::vector<uint8_t> has_t(b.k_in, 0);
             for (int32_t t : q->S) has_t[part[t]] = 1;
             for (int32_t p = 0; p < b.k_in; ++p) {
