@@ -374,6 +374,49 @@ __device__ __forceinline__ void for_queue_arcs(int64_t e0, int deg, int32_t* own
     }
 }
 
+// for_queue_arcs with K rounds handed over at once: f(owner[K], e[K], ok[K]) gets the
+// queue's arcs r .. r + 64K - 1, arc r + 64k + lane in slot k, so that it can issue the
+// loads of K arcs per lane before it waits for any of them.
+template <int K, class F>
+__device__ __forceinline__ void for_queue_arcs_k(int64_t e0, int deg, int32_t* own, F&& f) {
+    const int lane = threadIdx.x & 63;
+    const int incl = wscan_add(deg);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    const int excl = incl - deg;
+    const int e0lo = (int)(uint32_t)(uint64_t)e0, e0hi = (int)(uint32_t)((uint64_t)e0 >> 32);
+    int carry = -1;
+    for (int r = 0; r < total; r += 64 * K) {
+        int ow[K];
+        int64_t ee[K];
+        bool ok[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int rk = r + 64 * k;
+            ow[k] = 0;
+            ee[k] = 0;
+            ok[k] = false;
+            if (rk < total) {
+                __builtin_amdgcn_wave_barrier();  // the previous round's reads first
+                own[lane] = -1;
+                if (deg > 0 && excl >= rk && excl < rk + 64) own[excl - rk] = lane;
+                __builtin_amdgcn_wave_barrier();
+                int o = own[lane];
+                if (lane == 0) o = max(o, carry);
+                const int i = wscan_max(o);
+                carry = __builtin_amdgcn_readlane(i, 63);
+                const int p = rk + lane;
+                const int ex = __shfl(excl, i, 64);
+                const uint64_t base =
+                    ((uint64_t)(uint32_t)__shfl(e0hi, i, 64) << 32) | (uint32_t)__shfl(e0lo, i, 64);
+                ow[k] = i;
+                ee[k] = (int64_t)base + (p - ex);
+                ok[k] = p < total;
+            }
+        }
+        f(ow, ee, ok);
+    }
+}
+
 }  // namespace
 
 // Compact launch records: a group (node range, its sources in a shared array, its
@@ -763,6 +806,92 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                             }
                         }
                     };
+                    // byte state with packed records: two arcs per lane in flight, each
+                    // stage (record loads, byte tests, count loads, offers, sums) over
+                    // both before the next, so that a lane waits once per stage
+                    bool done = false;
+                    if constexpr (BYTE) {
+                        if (arcp) {
+                            done = true;
+                            for_queue_arcs_k<2>(e0, deg, wq, [&](const int* ow, const int64_t* ee, const bool* ok) {
+                                ArcRec a[2];
+                                int32_t u[2];
+                                uint32_t uw[2];
+                                bool par[2];
+                                uint64_t x[2];
+#pragma unroll
+                                for (int j = 0; j < 2; ++j)
+                                    a[j] = ok[j] ? load_arc(arcp, ee[j]) : ArcRec{(uint32_t)lo, 1u, 0u, 1u};
+#pragma unroll
+                                for (int j = 0; j < 2; ++j) {
+                                    const int32_t v = __shfl(q, ow[j], 64);
+                                    u[j] = (int32_t)a[j].head - lo;
+                                    uw[j] = 0u;
+                                    par[j] = false;
+                                    if (ok[j]) {
+                                        if (prof) bytes += 12ull;
+                                        const uint32_t L = a[j].len;
+                                        uw[j] = db32[u[j] >> 2];
+                                        const uint32_t bu = (uw[j] >> ((u[j] & 3) * 8)) & 0xFFu;
+                                        // u settled at D - L (eq. parentsall / eq. multiparents);
+                                        // Dijkstra_SK: a frontier parent other than the source
+                                        // adds no paths (eq. frontierparents)
+                                        par[j] = v != s && L <= D && settled_b(bu) && (bu & 0x7Fu) == sub127(d127, L) &&
+                                                 !(restrict_ && u[j] != s && nflag && (nflag[lo + u[j]] & NF_BLOCKED));
+                                    }
+                                }
+#pragma unroll
+                                for (int j = 0; j < 2; ++j) {
+                                    x[j] = 0ull;
+                                    if (par[j]) {
+                                        if (tight) {
+                                            const uint64_t t = (uint64_t)((int64_t)a[j].twin - abase);
+                                            if (t < tbits)
+                                                __hip_atomic_fetch_or(gtb + (t >> 5), 1u << (t & 31), __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_AGENT);
+                                        }
+                                        x[j] = S_(u[j]);
+                                    }
+                                }
+                                // offers (all above D): lower u's byte to D + L's residue unless
+                                // u is settled or already pending at most L above D
+#pragma unroll
+                                for (int j = 0; j < 2; ++j) {
+                                    if (!ok[j]) continue;
+                                    const uint32_t L = a[j].len, nv = D + L;
+                                    const int sh = (u[j] & 3) * 8;
+                                    uint32_t w = uw[j];
+                                    for (;;) {
+                                        const uint32_t bu = (w >> sh) & 0xFFu;
+                                        if (settled_b(bu) || (bu != 0xFFu && ((bu - D) & 127u) <= L)) break;
+                                        const uint32_t nw = (w & ~(0xFFu << sh)) | ((nv & 127u) << sh);
+                                        const uint32_t prev = atomicCAS(&db32[u[j] >> 2], w, nw);
+                                        if (prev == w) {
+                                            mn = min(mn, nv);
+                                            break;
+                                        }
+                                        w = prev;
+                                    }
+                                }
+#pragma unroll
+                                for (int j = 0; j < 2; ++j) {
+                                    if (!par[j]) continue;
+                                    uint64_t xx = x[j];
+                                    if (mult) {
+                                        const uint64_t m = a[j].mult;
+                                        if (__umul64hi(xx, m) != 0) ovf = true;
+                                        xx *= m;
+                                    }
+                                    if (xx) {
+                                        const unsigned long long o =
+                                            atomicAdd(&wsig[tid >> 6][ow[j]], (unsigned long long)xx);
+                                        if (o + xx < o) ovf = true;
+                                    }
+                                }
+                            });
+                        }
+                    }
+                    if (!done)
                     for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
                         int32_t c = 0;
                         uint32_t L = 1u, tw = 0u, mu = 1u;
@@ -914,16 +1043,23 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         }
                     }
                 }
+                // One sweep over the row's entries: per round, the segmented minimum of
+                // the values, and the sum of sigma(s,f) * sigma(f,v) over the entries that
+                // attain the smaller of that minimum and the row's minimum so far; the row
+                // keeps the sum of its smallest value (a smaller round minimum restarts it)
                 uint32_t rmin = INF32;
+                uint64_t rsum = 0;
+                bool rovf = false;
                 for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
                     const int seg = max(__shfl(excl, owner, 64) - r, 0);
                     uint32_t val = INF32;
+                    int32_t f = 0;
+                    if (ok) f = tcol[e] - lo;
                     if constexpr (BYTE) {
                         const uint32_t ad = (uint32_t)__shfl((int)adist, owner, 64);
                         const uint32_t ar = (uint32_t)__shfl((int)ares, owner, 64);
                         const uint32_t al = (uint32_t)__shfl((int)alen, owner, 64);
                         if (ok && ad != INF32) {
-                            const int32_t f = tcol[e] - lo;
                             const uint32_t L = tlen[e];
                             uint32_t tf;
                             if (L + al <= 63u) {
@@ -937,53 +1073,39 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                             val = tf + L;
                         }
                     } else if (ok) {
-                        const uint32_t tf = D_(tcol[e] - lo);
+                        const uint32_t tf = D_(f);
                         if (tf != INF32) val = tf + tlen[e];
                     }
-                    val = wseg_min_u32(val, seg);
-                    const int ab = max(excl - r, 0), bb = min(incl - r, 64);
-                    const uint32_t part = (uint32_t)__shfl((int)val, max(bb - 1, 0), 64);
-                    if (bb > ab) rmin = min(rmin, part);
-                });
-                uint64_t rsum = 0;
-                bool o2 = false;
-                for_queue_arcs(e0, rmin != INF32 ? deg : 0, wq, [&](int owner, int64_t e, bool ok, int incl, int excl,
-                                                                    int r) {
-                    const int seg = max(__shfl(excl, owner, 64) - r, 0);
-                    const uint32_t m = (uint32_t)__shfl((int)rmin, owner, 64);
+                    const uint32_t sm = wseg_min_u32(val, seg);
+                    // the round minimum of this lane's row sits at the row's last lane here
+                    const int last = min(__shfl(incl, owner, 64) - r, 64) - 1;
+                    const uint32_t m = min((uint32_t)__shfl((int)sm, last, 64), (uint32_t)__shfl((int)rmin, owner, 64));
                     uint64_t c = 0;
-                    if (ok) {
-                        const int32_t f = tcol[e] - lo;
-                        const uint32_t L = tlen[e];
-                        bool on;
-                        if constexpr (BYTE) {
-                            // d(s,f) lies in [m - L, m + L] (m = d(s,v)): residues decide
-                            // when L <= 63
-                            if (L <= 63) {
-                                const uint32_t bf = db[f];
-                                on = settled_b(bf) && (bf & 0x7Fu) == sub127(m % 127u, L);
-                            } else {
-                                const uint32_t tf = D_(f);
-                                on = tf != INF32 && tf + L == m;
-                            }
-                        } else {
-                            const uint32_t tf = D_(f);
-                            on = tf != INF32 && tf + L == m;
-                        }
-                        if (on) {
-                            const uint64_t a = S_(f), t = tsig[e];
-                            if (__umul64hi(a, t) != 0) o2 = true;
-                            c = a * t;
-                        }
+                    bool lo2 = false;
+                    if (val != INF32 && val == m) {
+                        const uint64_t a = S_(f), t = tsig[e];
+                        if (__umul64hi(a, t) != 0) lo2 = true;
+                        c = a * t;
                     }
-                    c = wseg_sum_u64(c, seg, &o2);
+                    c = wseg_sum_u64(c, seg, &lo2);
+                    const unsigned long long ovm = __ballot(lo2);
                     const int ab = max(excl - r, 0), bb = min(incl - r, 64);
+                    const uint32_t pmin = (uint32_t)__shfl((int)sm, max(bb - 1, 0), 64);
                     const uint64_t part = (uint64_t)__shfl((long long)c, max(bb - 1, 0), 64);
-                    if (bb > ab) {
-                        if (rsum + part < rsum) o2 = true;
-                        rsum += part;
+                    if (bb > ab && pmin != INF32) {
+                        const int w = bb - ab;
+                        const bool povf = ((ovm >> ab) & (w >= 64 ? ~0ull : ((1ull << w) - 1ull))) != 0ull;
+                        if (pmin < rmin) {
+                            rmin = pmin;
+                            rsum = part;
+                            rovf = povf;
+                        } else if (pmin == rmin) {
+                            rovf = rovf || povf || rsum + part < rsum;
+                            rsum += part;
+                        }
                     }
                 });
+                bool o2 = rovf;
                 if (valid) {
                     idist[i] = rmin;
                     isig[i] = rsum;
