@@ -807,21 +807,56 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                         }
                     };
                     // byte state with packed records: two arcs per lane in flight, each
-                    // stage (record loads, byte tests, count loads, offers, sums) over
-                    // both before the next, so that a lane waits once per stage
+                    // stage (byte tests, count loads, offers, sums) over both before the
+                    // next, so that a lane waits once per stage; and the next two arcs'
+                    // records are loaded behind the count loads of the current two, so
+                    // that their wait overlaps the offers and sums
                     bool done = false;
                     if constexpr (BYTE) {
                         if (arcp) {
                             done = true;
-                            for_queue_arcs_k<2>(e0, deg, wq, [&](const int* ow, const int64_t* ee, const bool* ok) {
-                                ArcRec a[2];
+                            const int incl = wscan_add(deg);
+                            const int total = __builtin_amdgcn_readlane(incl, 63);
+                            const int excl = incl - deg;
+                            const int e0lo = (int)(uint32_t)(uint64_t)e0, e0hi = (int)(uint32_t)((uint64_t)e0 >> 32);
+                            int carry = -1;
+                            // the owner slot and arc of this lane in round rk (as for_queue_arcs
+                            // finds them; rounds in increasing order)
+                            auto owner_of = [&](int rk, int& o_, int64_t& e_, bool& ok_) {
+                                o_ = 0;
+                                e_ = 0;
+                                ok_ = false;
+                                if (rk >= total) return;
+                                __builtin_amdgcn_wave_barrier();  // the previous round's reads first
+                                wq[lane] = -1;
+                                if (deg > 0 && excl >= rk && excl < rk + 64) wq[excl - rk] = lane;
+                                __builtin_amdgcn_wave_barrier();
+                                int o = wq[lane];
+                                if (lane == 0) o = max(o, carry);
+                                const int i = wscan_max(o);
+                                carry = __builtin_amdgcn_readlane(i, 63);
+                                const int p = rk + lane;
+                                const int ex = __shfl(excl, i, 64);
+                                const uint64_t base =
+                                    ((uint64_t)(uint32_t)__shfl(e0hi, i, 64) << 32) | (uint32_t)__shfl(e0lo, i, 64);
+                                o_ = i;
+                                e_ = (int64_t)base + (p - ex);
+                                ok_ = p < total;
+                            };
+                            int ow[2];
+                            int64_t ee[2];
+                            bool ok[2];
+                            ArcRec a[2];
+#pragma unroll
+                            for (int j = 0; j < 2; ++j) owner_of(64 * j, ow[j], ee[j], ok[j]);
+#pragma unroll
+                            for (int j = 0; j < 2; ++j)
+                                a[j] = ok[j] ? load_arc(arcp, ee[j]) : ArcRec{(uint32_t)lo, 1u, 0u, 1u};
+                            for (int r = 0; r < total; r += 128) {
                                 int32_t u[2];
                                 uint32_t uw[2];
                                 bool par[2];
                                 uint64_t x[2];
-#pragma unroll
-                                for (int j = 0; j < 2; ++j)
-                                    a[j] = ok[j] ? load_arc(arcp, ee[j]) : ArcRec{(uint32_t)lo, 1u, 0u, 1u};
 #pragma unroll
                                 for (int j = 0; j < 2; ++j) {
                                     const int32_t v = __shfl(q, ow[j], 64);
@@ -853,6 +888,16 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                         x[j] = S_(u[j]);
                                     }
                                 }
+                                // the next two arcs: owners, then record loads
+                                int ow2[2];
+                                int64_t ee2[2];
+                                bool ok2[2];
+                                ArcRec a2[2];
+#pragma unroll
+                                for (int j = 0; j < 2; ++j) owner_of(r + 128 + 64 * j, ow2[j], ee2[j], ok2[j]);
+#pragma unroll
+                                for (int j = 0; j < 2; ++j)
+                                    a2[j] = ok2[j] ? load_arc(arcp, ee2[j]) : ArcRec{(uint32_t)lo, 1u, 0u, 1u};
                                 // offers (all above D): lower u's byte to D + L's residue unless
                                 // u is settled or already pending at most L above D
 #pragma unroll
@@ -886,6 +931,74 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                         const unsigned long long o =
                                             atomicAdd(&wsig[tid >> 6][ow[j]], (unsigned long long)xx);
                                         if (o + xx < o) ovf = true;
+                                    }
+                                }
+#pragma unroll
+                                for (int j = 0; j < 2; ++j) {
+                                    ow[j] = ow2[j];
+                                    ee[j] = ee2[j];
+                                    ok[j] = ok2[j];
+                                    a[j] = a2[j];
+                                }
+                            }
+                        }
+                    }
+                    if constexpr (!GLOBAL && T <= 512) {
+                        // LDS state on a small skeleton with clique arcs: the same staging,
+                        // two arcs per lane, from the packed records (a parent's
+                        // multiplicity then comes with its head instead of from a load of
+                        // its own). (The 1024-thread class keeps one arc per lane: there
+                        // the staging measured slower.)
+                        const GAS ArcRec* __restrict__ arcl = mult ? gas(C.g.arc) : nullptr;
+                        if (arcl) {
+                            done = true;
+                            for_queue_arcs_k<2>(e0, deg, wq, [&](const int* ow, const int64_t* ee, const bool* ok) {
+                                ArcRec a[2];
+                                int32_t u[2], vv[2];
+                                uint32_t du[2];
+                                bool par[2];
+#pragma unroll
+                                for (int j = 0; j < 2; ++j)
+                                    a[j] = ok[j] ? load_arc(arcl, ee[j]) : ArcRec{(uint32_t)lo, 1u, 0u, 1u};
+#pragma unroll
+                                for (int j = 0; j < 2; ++j) {
+                                    const int32_t v = __shfl(q, ow[j], 64);
+                                    vv[j] = v;
+                                    u[j] = (int32_t)a[j].head - lo;
+                                    du[j] = INF32;
+                                    par[j] = false;
+                                    if (ok[j]) {
+                                        if (prof) bytes += 12ull;
+                                        const uint32_t L = a[j].len;
+                                        du[j] = dist[u[j]];
+                                        par[j] = v != s && L <= D && du[j] != INF32 && du[j] + L == D &&
+                                                 !(restrict_ && u[j] != s && nflag && (nflag[lo + u[j]] & NF_BLOCKED));
+                                    }
+                                }
+#pragma unroll
+                                for (int j = 0; j < 2; ++j) {
+                                    if (!par[j]) continue;
+                                    if (tight) {
+                                        const uint64_t t = (uint64_t)((int64_t)a[j].twin - abase);
+                                        if (t < tbits) atomicOr(&tb[t >> 5], 1u << (t & 31));
+                                    }
+                                    uint64_t x = sig[u[j]];
+                                    if (mult) {
+                                        const uint64_t m = a[j].mult;
+                                        if (__umul64hi(x, m) != 0) ovf = true;
+                                        x *= m;
+                                    }
+                                    if (x) {
+                                        const uint64_t old = addS(vv[j], x);
+                                        if (old + x < old) ovf = true;
+                                    }
+                                }
+#pragma unroll
+                                for (int j = 0; j < 2; ++j) {
+                                    const uint32_t nv = D + a[j].len;
+                                    if (ok[j] && nv < du[j]) {
+                                        minD(u[j], nv);
+                                        mn = min(mn, nv);
                                     }
                                 }
                             });
