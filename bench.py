@@ -92,7 +92,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=15)
     ap.add_argument("--workload", default="pareto_100k",
                     choices=["planted_1k", "sbm_10k", "pareto_100k", "smallcut_100k", "batch_256", "p1_sweep",
-                             "serve_64"])
+                             "serve_64", "lp_pareto_100k", "pp_all_planted_1k"])
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="measured window of the serving workload (after a 2 s warm-up)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean query arrivals per second")
@@ -267,6 +267,102 @@ def bench_p1_sweep(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_lp(args):
+    """The device partitioner (bc_partition_lp, size-constrained label propagation) on
+    pareto_100k, and Brandes++ over its partition beside Brandes++ over the planted one
+    and plain Brandes (same targets, timed the same way as the single-graph workloads;
+    the partition is made once per graph, so its time is reported apart from the
+    step). Scores do not depend on the partition (Sec. 5); its cut decides the
+    skeleton's size. value = Brandes++ TEPS over the device partition."""
+    import numpy as np
+    import torch
+
+    from paper_1406_4173_amd import bcpp, inputs
+
+    dev = torch.device("cuda:0")
+    sync = torch.cuda.synchronize
+    g = inputs.pareto_100k()
+    G = bcpp.Graph(g, stream=torch.cuda.current_stream(dev))
+    S_dev = torch.tensor(g.S, dtype=torch.int32, device=dev)
+    S_host = np.ascontiguousarray(g.S, np.int32)
+    out = torch.empty(g.n, dtype=torch.float64, device=dev)
+    cap, rounds, seed = 0, 48, 5
+    res_lp = {}
+
+    def lp():
+        res_lp["p"] = bcpp.partition_lp(G, cap, rounds, seed)
+
+    t_lp = timed(lp, max(args.steps // 2, 1), 1, sync)
+    lp_part, lp_k = res_lp["p"]
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    col = np.asarray(g.col)
+    rows = {}
+    for name, part, k in (("device", lp_part, lp_k), ("planted", np.ascontiguousarray(g.part, np.int32), g.k)):
+        state = {}
+
+        def pp_step(part=part, k=k, state=state):
+            sk = bcpp.partition_sk(G, part, k, S_host)
+            bcpp.brandes_pp_dev(G, sk, out)
+            state["sk"] = sk
+
+        t = timed(pp_step, args.steps, args.warmup, sync)
+        st = state["sk"].stats()
+        rows[name] = {"parts": int(k), "cut": float(np.mean(part[src] != part[col])), "pp_ms": t * 1e3,
+                      "skeleton_nodes": st["n_sk"], "skeleton_arcs": st["r_arcs"] + st["clique_arcs"],
+                      "table_nnz": st["table_nnz"]}
+    t_plain = timed(lambda: bcpp.brandes_plain_dev(G, S_dev, out), args.steps, args.warmup, sync)
+    units = float(len(g.S) * g.m)
+    d = rows["device"]
+    res = {
+        "metric": "exact-BC TEPS (|S|*m/s), Brandes++ over the device partition, 1 GPU",
+        "value": units / (d["pp_ms"] * 1e-3), "unit": "TEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": d["pp_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32/u64/f64", "data": "synthetic",
+        "config": {"workload": "lp_pareto_100k", "n": g.n, "m": int(g.m), "targets": int(len(g.S)),
+                   "max_part": cap, "rounds": rounds, "seed": seed},
+        "partition_ms": t_lp * 1e3, "partitions": rows, "plain_ms": t_plain * 1e3,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def bench_pp_all(args):
+    """Brandes++All (bc_brandes_pp_all, Sec. 6, Alg. 3) on planted_1k: all-pairs scores
+    through one skeleton per ordered pair of its 8 parts (64 skeleton builds and
+    Brandes_SK + Centrality passes), beside plain Brandes and Brandes++ with S = V on the
+    same graph. value = Brandes++All TEPS (n * m / s)."""
+    import numpy as np
+    import torch
+
+    from paper_1406_4173_amd import bcpp, inputs
+
+    dev = torch.device("cuda:0")
+    sync = torch.cuda.synchronize
+    g = inputs.planted_1k()
+    G = bcpp.Graph(g, stream=torch.cuda.current_stream(dev))
+    part = np.ascontiguousarray(g.part, np.int32)
+    S_host = np.arange(g.n, dtype=np.int32)
+    S_dev = torch.tensor(S_host, device=dev)
+    out = torch.empty(g.n, dtype=torch.float64, device=dev)
+    t_all = timed(lambda: bcpp.brandes_pp_all(G, part, g.k), args.steps, min(args.warmup, 3), sync)
+
+    def pp_step():
+        bcpp.brandes_pp_dev(G, bcpp.partition_sk(G, part, g.k, S_host), out)
+
+    t_pp = timed(pp_step, args.steps, args.warmup, sync)
+    t_plain = timed(lambda: bcpp.brandes_plain_dev(G, S_dev, out), args.steps, args.warmup, sync)
+    units = float(g.n * g.m)
+    res = {
+        "metric": "exact-BC TEPS (n*m/s), Brandes++All on 1 GPU",
+        "value": units / t_all, "unit": "TEPS", "n_gpus": 1, "steps": args.steps, "warmup": min(args.warmup, 3),
+        "ms_per_step": t_all * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32/u64/f64", "data": "synthetic",
+        "config": {"workload": "pp_all_planted_1k", "n": g.n, "m": int(g.m), "parts": int(g.k),
+                   "skeletons": int(g.k) ** 2},
+        "pp_ms": t_pp * 1e3, "plain_ms": t_plain * 1e3,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def bench_serve(args):
     """Open-loop Poisson stream of Brandes++ queries over 64 resident graphs; TEPS =
     sum of |S| m over the queries submitted in the measured window, divided by the time
@@ -380,6 +476,10 @@ def main():
         return bench_serve(args)
     if args.workload == "p1_sweep":
         return bench_p1_sweep(args)
+    if args.workload == "lp_pareto_100k":
+        return bench_lp(args)
+    if args.workload == "pp_all_planted_1k":
+        return bench_pp_all(args)
     import numpy as np
     import torch
 
