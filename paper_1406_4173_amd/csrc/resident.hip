@@ -417,6 +417,81 @@ __device__ __forceinline__ void for_queue_arcs_k(int64_t e0, int deg, int32_t* o
     }
 }
 
+// for_queue_arcs in three stages per round, pipelined one round deep: x = load(e, ok)
+// issues the round's first loads; y = issue(owner, e, ok, incl, excl, r, x) uses them and
+// issues the loads that depend on them; then the next round's owners are found and its
+// load() issued, and only then finish(owner, e, ok, incl, excl, r, x, y) waits for the
+// dependent loads. Rounds run in order (finish of round r before issue of round r + 64),
+// so what finish leaves behind (a row's running minimum, its sums) is seen by the next
+// round exactly as in for_queue_arcs.
+template <class LD, class IS, class FN>
+__device__ __forceinline__ void for_queue_arcs_pipe(int64_t e0, int deg, int32_t* own, LD&& load, IS&& issue,
+                                                    FN&& finish) {
+    const int lane = threadIdx.x & 63;
+    const int incl = wscan_add(deg);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    const int excl = incl - deg;
+    const int e0lo = (int)(uint32_t)(uint64_t)e0, e0hi = (int)(uint32_t)((uint64_t)e0 >> 32);
+    int carry = -1;
+    auto owner_of = [&](int rk, int& o_, int64_t& e_, bool& ok_) {
+        o_ = 0;
+        e_ = 0;
+        ok_ = false;
+        if (rk >= total) return;
+        __builtin_amdgcn_wave_barrier();  // the previous round's reads first
+        own[lane] = -1;
+        if (deg > 0 && excl >= rk && excl < rk + 64) own[excl - rk] = lane;
+        __builtin_amdgcn_wave_barrier();
+        int o = own[lane];
+        if (lane == 0) o = max(o, carry);
+        const int i = wscan_max(o);
+        carry = __builtin_amdgcn_readlane(i, 63);
+        const int p = rk + lane;
+        const int ex = __shfl(excl, i, 64);
+        const uint64_t base = ((uint64_t)(uint32_t)__shfl(e0hi, i, 64) << 32) | (uint32_t)__shfl(e0lo, i, 64);
+        o_ = i;
+        e_ = (int64_t)base + (p - ex);
+        ok_ = p < total;
+    };
+    if (total == 0) return;
+    int ow;
+    int64_t e;
+    bool ok;
+    owner_of(0, ow, e, ok);
+    auto x = load(e, ok);
+    for (int r = 0; r < total; r += 64) {
+        const auto y = issue(ow, e, ok, incl, excl, r, x);
+        int ow2;
+        int64_t e2;
+        bool ok2;
+        owner_of(r + 64, ow2, e2, ok2);
+        const auto x2 = load(e2, ok2);
+        finish(ow, e, ok, incl, excl, r, x, y);
+        ow = ow2;
+        e = e2;
+        ok = ok2;
+        x = x2;
+    }
+}
+
+// One table entry (frontier f, d(f,v)) of an interior row, and what the interior
+// sweeps carry from a round's tests to its sums.
+struct IEnt {
+    int32_t f;
+    uint32_t L;
+};
+struct IMin {
+    uint32_t sm;  // segmented minimum up to this lane
+    int seg;
+    bool on;      // the entry attains the row's minimum so far
+    uint64_t a, t;  // sigma(s,f), sigma(f,v)
+};
+struct IDel {
+    int seg;
+    bool on;      // v lies on a shortest path from s to f
+    uint64_t t, cf;  // sigma(f,v), coef(s,f) (its bits)
+};
+
 }  // namespace
 
 // Compact launch records: a group (node range, its sources in a shared array, its
@@ -1163,61 +1238,75 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                 uint32_t rmin = INF32;
                 uint64_t rsum = 0;
                 bool rovf = false;
-                for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
-                    const int seg = max(__shfl(excl, owner, 64) - r, 0);
-                    uint32_t val = INF32;
-                    int32_t f = 0;
-                    if (ok) f = tcol[e] - lo;
-                    if constexpr (BYTE) {
-                        const uint32_t ad = (uint32_t)__shfl((int)adist, owner, 64);
-                        const uint32_t ar = (uint32_t)__shfl((int)ares, owner, 64);
-                        const uint32_t al = (uint32_t)__shfl((int)alen, owner, 64);
-                        if (ok && ad != INF32) {
-                            const uint32_t L = tlen[e];
-                            uint32_t tf;
-                            if (L + al <= 63u) {
-                                int dl = (int)(db[f] & 0x7Fu) - (int)ar;
-                                if (dl > 63) dl -= 127;
-                                if (dl < -63) dl += 127;
-                                tf = (uint32_t)((int)ad + dl);
-                            } else {
-                                tf = D_(f);
+                for_queue_arcs_pipe(
+                    e0, deg, wq,
+                    [&](int64_t e, bool ok) {
+                        IEnt x{0, 0u};
+                        if (ok) {
+                            x.f = tcol[e] - lo;
+                            x.L = tlen[e];
+                        }
+                        return x;
+                    },
+                    [&](int owner, int64_t e, bool ok, int incl, int excl, int r, const IEnt& x) {
+                        IMin y;
+                        y.seg = max(__shfl(excl, owner, 64) - r, 0);
+                        uint32_t val = INF32;
+                        if constexpr (BYTE) {
+                            const uint32_t ad = (uint32_t)__shfl((int)adist, owner, 64);
+                            const uint32_t ar = (uint32_t)__shfl((int)ares, owner, 64);
+                            const uint32_t al = (uint32_t)__shfl((int)alen, owner, 64);
+                            if (ok && ad != INF32) {
+                                uint32_t tf;
+                                if (x.L + al <= 63u) {
+                                    int dl = (int)(db[x.f] & 0x7Fu) - (int)ar;
+                                    if (dl > 63) dl -= 127;
+                                    if (dl < -63) dl += 127;
+                                    tf = (uint32_t)((int)ad + dl);
+                                } else {
+                                    tf = D_(x.f);
+                                }
+                                val = tf + x.L;
                             }
-                            val = tf + L;
+                        } else if (ok) {
+                            const uint32_t tf = D_(x.f);
+                            if (tf != INF32) val = tf + x.L;
                         }
-                    } else if (ok) {
-                        const uint32_t tf = D_(f);
-                        if (tf != INF32) val = tf + tlen[e];
-                    }
-                    const uint32_t sm = wseg_min_u32(val, seg);
-                    // the round minimum of this lane's row sits at the row's last lane here
-                    const int last = min(__shfl(incl, owner, 64) - r, 64) - 1;
-                    const uint32_t m = min((uint32_t)__shfl((int)sm, last, 64), (uint32_t)__shfl((int)rmin, owner, 64));
-                    uint64_t c = 0;
-                    bool lo2 = false;
-                    if (val != INF32 && val == m) {
-                        const uint64_t a = S_(f), t = tsig[e];
-                        if (__umul64hi(a, t) != 0) lo2 = true;
-                        c = a * t;
-                    }
-                    c = wseg_sum_u64(c, seg, &lo2);
-                    const unsigned long long ovm = __ballot(lo2);
-                    const int ab = max(excl - r, 0), bb = min(incl - r, 64);
-                    const uint32_t pmin = (uint32_t)__shfl((int)sm, max(bb - 1, 0), 64);
-                    const uint64_t part = (uint64_t)__shfl((long long)c, max(bb - 1, 0), 64);
-                    if (bb > ab && pmin != INF32) {
-                        const int w = bb - ab;
-                        const bool povf = ((ovm >> ab) & (w >= 64 ? ~0ull : ((1ull << w) - 1ull))) != 0ull;
-                        if (pmin < rmin) {
-                            rmin = pmin;
-                            rsum = part;
-                            rovf = povf;
-                        } else if (pmin == rmin) {
-                            rovf = rovf || povf || rsum + part < rsum;
-                            rsum += part;
+                        y.sm = wseg_min_u32(val, y.seg);
+                        // the round minimum of this lane's row sits at the row's last lane here
+                        const int last = min(__shfl(incl, owner, 64) - r, 64) - 1;
+                        const uint32_t m =
+                            min((uint32_t)__shfl((int)y.sm, last, 64), (uint32_t)__shfl((int)rmin, owner, 64));
+                        y.on = val != INF32 && val == m;
+                        y.a = y.on ? S_(x.f) : 0ull;
+                        y.t = y.on ? tsig[e] : 0ull;
+                        return y;
+                    },
+                    [&](int owner, int64_t e, bool ok, int incl, int excl, int r, const IEnt& x, const IMin& y) {
+                        uint64_t c = 0;
+                        bool lo2 = false;
+                        if (y.on) {
+                            if (__umul64hi(y.a, y.t) != 0) lo2 = true;
+                            c = y.a * y.t;
                         }
-                    }
-                });
+                        c = wseg_sum_u64(c, y.seg, &lo2);
+                        const unsigned long long ovm = __ballot(lo2);
+                        const int ab = max(excl - r, 0), bb = min(incl - r, 64);
+                        const uint32_t pmin = (uint32_t)__shfl((int)y.sm, max(bb - 1, 0), 64);
+                        const uint64_t part = (uint64_t)__shfl((long long)c, max(bb - 1, 0), 64);
+                        if (bb > ab && pmin != INF32) {
+                            const int w = bb - ab;
+                            const bool povf = ((ovm >> ab) & (w >= 64 ? ~0ull : ((1ull << w) - 1ull))) != 0ull;
+                            if (pmin < rmin) {
+                                rmin = pmin;
+                                rsum = part;
+                                rovf = povf;
+                            } else if (pmin == rmin) {
+                                rovf = rovf || povf || rsum + part < rsum;
+                                rsum += part;
+                            }
+                        }
+                    });
                 bool o2 = rovf;
                 if (valid) {
                     idist[i] = rmin;
@@ -1380,34 +1469,47 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                     deg = dv == INF32 ? 0 : (int)(trow[R.t_lo + i + 1] - e0);
                 }
                 double acc = 0.0;
-                for_queue_arcs(e0, deg, wq, [&](int owner, int64_t e, bool ok, int incl, int excl, int r) {
-                    const int seg = max(__shfl(excl, owner, 64) - r, 0);
-                    const uint32_t m = (uint32_t)__shfl((int)dv, owner, 64);
-                    double c = 0.0;
-                    if (ok) {
-                        const int32_t f = tcol[e] - lo;
-                        const uint32_t L = tlen[e];
-                        bool on;
-                        if constexpr (BYTE) {
-                            // d(s,f) lies in [d(s,v) - L, d(s,v) + L]: residues decide
-                            // when 2L + 1 <= 127, the exact distance otherwise
-                            if (L <= 63) {
-                                const uint32_t bf = db[f];
-                                on = settled_b(bf) && (bf & 0x7Fu) == add127(m % 127u, L);
-                            } else {
-                                on = D_(f) == m + L;
-                            }
-                        } else {
-                            const uint32_t tf = D_(f);
-                            on = tf != INF32 && tf == m + L;
+                for_queue_arcs_pipe(
+                    e0, deg, wq,
+                    [&](int64_t e, bool ok) {
+                        IEnt x{0, 0u};
+                        if (ok) {
+                            x.f = tcol[e] - lo;
+                            x.L = tlen[e];
                         }
-                        if (on) c = (double)tsig[e] * __longlong_as_double((long long)S_(f));
-                    }
-                    c = wseg_sum(c, seg);
-                    const int ab = max(excl - r, 0), bb = min(incl - r, 64);
-                    const double part = __shfl(c, max(bb - 1, 0), 64);
-                    if (bb > ab) acc += part;
-                });
+                        return x;
+                    },
+                    [&](int owner, int64_t e, bool ok, int incl, int excl, int r, const IEnt& x) {
+                        IDel y;
+                        y.seg = max(__shfl(excl, owner, 64) - r, 0);
+                        const uint32_t m = (uint32_t)__shfl((int)dv, owner, 64);
+                        y.on = false;
+                        if (ok) {
+                            if constexpr (BYTE) {
+                                // d(s,f) lies in [d(s,v) - L, d(s,v) + L]: residues decide
+                                // when 2L + 1 <= 127, the exact distance otherwise
+                                if (x.L <= 63) {
+                                    const uint32_t bf = db[x.f];
+                                    y.on = settled_b(bf) && (bf & 0x7Fu) == add127(m % 127u, x.L);
+                                } else {
+                                    y.on = D_(x.f) == m + x.L;
+                                }
+                            } else {
+                                const uint32_t tf = D_(x.f);
+                                y.on = tf != INF32 && tf == m + x.L;
+                            }
+                        }
+                        y.t = y.on ? tsig[e] : 0ull;
+                        y.cf = y.on ? S_(x.f) : 0ull;
+                        return y;
+                    },
+                    [&](int owner, int64_t e, bool ok, int incl, int excl, int r, const IEnt& x, const IDel& y) {
+                        double c = y.on ? (double)y.t * __longlong_as_double((long long)y.cf) : 0.0;
+                        c = wseg_sum(c, y.seg);
+                        const int ab = max(excl - r, 0), bb = min(incl - r, 64);
+                        const double part = __shfl(c, max(bb - 1, 0), 64);
+                        if (bb > ab) acc += part;
+                    });
                 if (valid && dv != INF32) cint[i] += (double)isig[i] * acc;
             }
         }
