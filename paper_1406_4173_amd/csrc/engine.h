@@ -221,6 +221,10 @@ bool resident_takes(int64_t range);
 // Sources per resident group for a source set of nsrc (a function of nsrc only, so a
 // graph is split the same way alone and inside a batch).
 int32_t resident_sources_per_group(int64_t nsrc);
+// Sources per Dijkstra_SK group for a part whose nodes plus arcs are part_work: 64, or
+// with a tuned work budget per group, budget / part_work within [8, 64]. A function of
+// the part alone, so a part is split the same way in every build that holds it.
+int32_t dsk_sources_per_group(int64_t part_work);
 size_t resident_group_bytes(const GroupDesc& G);
 bool resident_alloc(Arena& a, GroupDesc& G);
 // Workspace run_resident takes from the arena for `ngroups` groups.

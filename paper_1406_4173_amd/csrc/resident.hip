@@ -1612,7 +1612,15 @@ struct SizeClasses {
     int64_t small = tune_value("BCPP_TUNE_SMALL", tuned_small_range);
     int64_t mid = tune_value("BCPP_TUNE_MID", tuned_mid_range);
     int64_t dense_shift = std::min<int64_t>(63, tune_value("BCPP_TUNE_DENSE_SHIFT", tuned_dense_shift));
-    int of(int64_t range) const { return range <= small ? 0 : range <= mid ? 1 : 2; }
+    // Dijkstra_SK groups: each runs up to 64 sources of one part one after another, and
+    // the launch lasts as long as its longest group, so larger parts take wider
+    // workgroups sooner than scoring groups do
+    int64_t dsk_small = tune_value("BCPP_TUNE_DSK_SMALL", tuned_dsk_small_range);
+    int64_t dsk_mid = tune_value("BCPP_TUNE_DSK_MID", tuned_dsk_mid_range);
+    int of(int64_t range, bool dsk) const {
+        const int64_t a = dsk ? dsk_small : small, b = dsk ? dsk_mid : mid;
+        return range <= a ? 0 : range <= b ? 1 : 2;
+    }
 };
 
 }  // namespace
@@ -1626,6 +1634,12 @@ int64_t resident_max_range() {
     int64_t n = (int64_t)(cap / 12);
     while (n > 0 && lds_bytes(n) > cap) --n;
     return n;
+}
+
+int32_t dsk_sources_per_group(int64_t part_work) {
+    const int64_t budget = tune_value("BCPP_TUNE_DSK_WORK", tuned_dsk_group_work);
+    if (budget <= 0 || part_work <= 0) return LANES;
+    return (int32_t)std::min<int64_t>(LANES, std::max<int64_t>(8, budget / part_work));
 }
 
 int32_t resident_sources_per_group(int64_t nsrc) {
@@ -1732,7 +1746,7 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
                 need = lg >= 0 ? bb : 0;
             }
         } else {
-            c = sc.of(range);
+            c = sc.of(range, !(G.flags & GF_BACKWARD));
             need = state;
             // the tight-arc bitmap, where it fits beside the state
             if (tight_arcs_on() && (G.flags & GF_BACKWARD) && G.g.twin && tight_pays(range, G.arcs)) {

@@ -575,7 +575,10 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
         clique_pairs += (int64_t)pnf[p] * (pnf[p] - 1);
         table_pairs += (int64_t)pnf[p] * (psize[p] - pnf[p]);
         p_g0[p] = (int32_t)groups.size();
-        for (int64_t c = 0; c < pnf[p]; c += LANES) {
+        // sources per group: fewer for larger parts (a launch lasts as long as its
+        // longest group), the same for a part in every build
+        const int64_t spg = dsk_sources_per_group(psize[p] + (int64_t)parc[p]);
+        for (int64_t c = 0; c < pnf[p]; c += spg) {
             GroupDesc G;
             G.lo = (int32_t)poff[p];
             G.hi = (int32_t)(poff[p] + psize[p]);
@@ -583,7 +586,7 @@ int SkBuild::prepare(const bc_graph* gr, const int32_t* part, int32_t k, const i
             G.arcs = (int64_t)parc[p];
             G.flags = GF_RESTRICT | (weighted ? 0u : GF_UNIT);
             G.ring_len = g->maxw + 1;
-            G.nsrc = (int32_t)std::min<int64_t>(LANES, pnf[p] - c);
+            G.nsrc = (int32_t)std::min<int64_t>(spg, pnf[p] - c);
             for (int b = 0; b < LANES; ++b) G.src[b] = b < G.nsrc ? (int32_t)(poff[p] + c + b) : -1;
             groups.push_back(G);
             info.push_back({pnf[p], (int32_t)c, G.nsrc, (int32_t)fbase[p]});

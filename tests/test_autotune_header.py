@@ -19,10 +19,11 @@ def values(text):
 
 def test_written_header_holds_the_choice_and_compiles(tmp_path):
     out = tmp_path / "tuned.h"
-    autotune.write_header(str(out), 2000, 5000, 256, 1, ["a sweep row", "chosen: ..."])
+    autotune.write_header(str(out), 2000, 5000, 256, 1, ["a sweep row", "chosen: ..."], (500, 1000, 200000))
     text = out.read_text()
     assert values(text) == {"tuned_small_range": 2000, "tuned_mid_range": 5000, "tuned_spg_div": 256,
-                            "tuned_dense_shift": 1}
+                            "tuned_dense_shift": 1, "tuned_dsk_small_range": 500, "tuned_dsk_mid_range": 1000,
+                            "tuned_dsk_group_work": 200000}
     assert "//   a sweep row" in text
     if shutil.which("g++") is None:
         pytest.skip("no host compiler")
@@ -33,7 +34,10 @@ def test_written_header_holds_the_choice_and_compiles(tmp_path):
 
 def test_committed_header_is_consistent():
     v = values(open(TUNED).read())
-    assert set(v) == {"tuned_small_range", "tuned_mid_range", "tuned_spg_div", "tuned_dense_shift"}
+    assert set(v) == {"tuned_small_range", "tuned_mid_range", "tuned_spg_div", "tuned_dense_shift",
+                      "tuned_dsk_small_range", "tuned_dsk_mid_range", "tuned_dsk_group_work"}
     assert 0 <= v["tuned_small_range"] <= v["tuned_mid_range"]
+    assert 0 <= v["tuned_dsk_small_range"] <= v["tuned_dsk_mid_range"]
+    assert v["tuned_dsk_group_work"] >= 0
     assert v["tuned_spg_div"] >= 1
     assert 0 <= v["tuned_dense_shift"] <= 63
