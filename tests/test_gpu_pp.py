@@ -213,6 +213,24 @@ def test_pp_bucket_and_scan_steps_agree(bcpp, monkeypatch):
     assert_scores(got["0"], oracle.bc(g, g.S))
 
 
+def test_dijkstra_sk_launch_shapes_change_no_bit(bcpp, monkeypatch):
+    """Dijkstra_SK's launch shapes (thread classes, sources per group) are free choices:
+    with every part's sources dealt 8 to a group and the widest workgroups, and with
+    64 to a group on the narrowest, the skeleton equals the oracle's exactly and the
+    Brandes++ scores are bitwise those of the tuned shapes."""
+    g = inputs.planted_1k()
+    S = inputs.random_targets(23, g.n, 40)
+    G = bcpp.Graph(g)
+    tuned = bcpp.brandes_pp(G, bcpp.partition_sk(G, g.part, g.k, S))
+    for small, mid, work in (("0", "0", "1"), ("100000", "100000", "0")):
+        monkeypatch.setenv("BCPP_TUNE_DSK_SMALL", small)
+        monkeypatch.setenv("BCPP_TUNE_DSK_MID", mid)
+        monkeypatch.setenv("BCPP_TUNE_DSK_WORK", work)
+        G2, sk = skeleton_matches_oracle(bcpp, g, g.part, g.k, S)
+        assert np.array_equal(bcpp.brandes_pp(G2, sk), tuned)
+    assert_scores(tuned, oracle.bc(g, S))
+
+
 @pytest.mark.parametrize("intra", [0.9, 0.998])
 def test_pp_small_cut_sweep_graphs(bcpp, intra):
     # the two ends of the small-cut sweep (100,000 nodes, communities of 20): a large
