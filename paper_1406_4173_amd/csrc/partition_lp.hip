@@ -8,6 +8,9 @@
 // function of (graph, cap, rounds, seed). Labels are then renumbered 0..k-1 in
 // increasing order of the surviving labels. Betweenness does not depend on the
 // partition (Sec. 5); only Brandes++'s speed does.
+// One thread per node counts its neighbours' labels by pairwise comparison, which is
+// quadratic in the node's degree: meant for sparse graphs (mean degree 6 to 12 here);
+// a graph with hubs of thousands of arcs would want a per-node wave and a hash.
 #include "engine.h"
 #include "graph.h"
 

@@ -339,101 +339,32 @@ __device__ __forceinline__ void for_bucket(uint32_t* __restrict__ row, int32_t W
 }
 
 // Arc expansion of a queue: lane i holds queued node q (valid) whose arcs are
-// [rp[lo+q], rp[lo+q+1]). Round r hands the queue's arcs r .. r+63, in node order, one
-// per lane, to f(owner, e, ok, incl, excl, r): owner = queue slot of the arc's node,
-// e = the arc, ok = false past the last arc; incl/excl are the calling lane's own
-// inclusive/exclusive arc offsets (its slot's range [excl, incl)). All lanes stay
-// converged, so f may use cross-lane operations before it branches on ok.
+// [rp[lo+q], rp[lo+q+1]) (the calling lane's slot holds the arcs [e0, e0 + deg), deg = 0
+// for an empty slot). Round r covers the queue's arcs r .. r+63, in node order, one per
+// lane: owner = queue slot of the arc's node, e = the arc, ok = false past the last arc;
+// incl/excl are each lane's own inclusive/exclusive arc offsets (its slot's range
+// [excl, incl)).
 // The owner of arc p is the last slot with arcs whose range starts at or before p:
 // each slot with arcs starting in the round writes its index at that position of the
 // 64-entry LDS scratch own (position 0 holds the previous round's last owner), and a
-// max-scan over the lanes fills the gaps. own is free while f runs. It is the first
+// max-scan over the lanes fills the gaps. own is free between rounds. It is the first
 // half of the wave's queue, which the caller has read into q already: own must not be
 // declared restrict, or that read may be moved past the writes here.
-// The calling lane's slot holds the arcs [e0, e0 + deg) (deg = 0 for an empty slot).
-template <class F>
-__device__ __forceinline__ void for_queue_arcs(int64_t e0, int deg, int32_t* own, F&& f) {
-    const int lane = threadIdx.x & 63;
-    const int incl = wscan_add(deg);
-    const int total = __builtin_amdgcn_readlane(incl, 63);
-    const int excl = incl - deg;
-    const int e0lo = (int)(uint32_t)(uint64_t)e0, e0hi = (int)(uint32_t)((uint64_t)e0 >> 32);
-    int carry = -1;
-    for (int r = 0; r < total; r += 64) {
-        own[lane] = -1;
-        if (deg > 0 && excl >= r && excl < r + 64) own[excl - r] = lane;
-        __builtin_amdgcn_wave_barrier();  // other lanes' writes before the read
-        int o = own[lane];
-        if (lane == 0) o = max(o, carry);
-        const int i = wscan_max(o);
-        carry = __builtin_amdgcn_readlane(i, 63);
-        const int p = r + lane;
-        const int ex = __shfl(excl, i, 64);
-        const uint64_t base = ((uint64_t)(uint32_t)__shfl(e0hi, i, 64) << 32) | (uint32_t)__shfl(e0lo, i, 64);
-        f(i, (int64_t)base + (p - ex), p < total, incl, excl, r);
+struct QueueRounds {
+    int32_t* own;
+    int deg, incl, excl, total, e0lo, e0hi, carry;
+    __device__ __forceinline__ QueueRounds(int64_t e0, int deg_, int32_t* own_) : own(own_), deg(deg_) {
+        incl = wscan_add(deg);
+        total = __builtin_amdgcn_readlane(incl, 63);
+        excl = incl - deg;
+        e0lo = (int)(uint32_t)(uint64_t)e0;
+        e0hi = (int)(uint32_t)((uint64_t)e0 >> 32);
+        carry = -1;
     }
-}
-
-// for_queue_arcs with K rounds handed over at once: f(owner[K], e[K], ok[K]) gets the
-// queue's arcs r .. r + 64K - 1, arc r + 64k + lane in slot k, so that it can issue the
-// loads of K arcs per lane before it waits for any of them.
-template <int K, class F>
-__device__ __forceinline__ void for_queue_arcs_k(int64_t e0, int deg, int32_t* own, F&& f) {
-    const int lane = threadIdx.x & 63;
-    const int incl = wscan_add(deg);
-    const int total = __builtin_amdgcn_readlane(incl, 63);
-    const int excl = incl - deg;
-    const int e0lo = (int)(uint32_t)(uint64_t)e0, e0hi = (int)(uint32_t)((uint64_t)e0 >> 32);
-    int carry = -1;
-    for (int r = 0; r < total; r += 64 * K) {
-        int ow[K];
-        int64_t ee[K];
-        bool ok[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int rk = r + 64 * k;
-            ow[k] = 0;
-            ee[k] = 0;
-            ok[k] = false;
-            if (rk < total) {
-                __builtin_amdgcn_wave_barrier();  // the previous round's reads first
-                own[lane] = -1;
-                if (deg > 0 && excl >= rk && excl < rk + 64) own[excl - rk] = lane;
-                __builtin_amdgcn_wave_barrier();
-                int o = own[lane];
-                if (lane == 0) o = max(o, carry);
-                const int i = wscan_max(o);
-                carry = __builtin_amdgcn_readlane(i, 63);
-                const int p = rk + lane;
-                const int ex = __shfl(excl, i, 64);
-                const uint64_t base =
-                    ((uint64_t)(uint32_t)__shfl(e0hi, i, 64) << 32) | (uint32_t)__shfl(e0lo, i, 64);
-                ow[k] = i;
-                ee[k] = (int64_t)base + (p - ex);
-                ok[k] = p < total;
-            }
-        }
-        f(ow, ee, ok);
-    }
-}
-
-// for_queue_arcs in three stages per round, pipelined one round deep: x = load(e, ok)
-// issues the round's first loads; y = issue(owner, e, ok, incl, excl, r, x) uses them and
-// issues the loads that depend on them; then the next round's owners are found and its
-// load() issued, and only then finish(owner, e, ok, incl, excl, r, x, y) waits for the
-// dependent loads. Rounds run in order (finish of round r before issue of round r + 64),
-// so what finish leaves behind (a row's running minimum, its sums) is seen by the next
-// round exactly as in for_queue_arcs.
-template <class LD, class IS, class FN>
-__device__ __forceinline__ void for_queue_arcs_pipe(int64_t e0, int deg, int32_t* own, LD&& load, IS&& issue,
-                                                    FN&& finish) {
-    const int lane = threadIdx.x & 63;
-    const int incl = wscan_add(deg);
-    const int total = __builtin_amdgcn_readlane(incl, 63);
-    const int excl = incl - deg;
-    const int e0lo = (int)(uint32_t)(uint64_t)e0, e0hi = (int)(uint32_t)((uint64_t)e0 >> 32);
-    int carry = -1;
-    auto owner_of = [&](int rk, int& o_, int64_t& e_, bool& ok_) {
+    // This lane's owner slot, arc and validity in round rk (all lanes converged; rounds
+    // asked for in increasing order, each once; ok = false for every lane past the end)
+    __device__ __forceinline__ void round(int rk, int& o_, int64_t& e_, bool& ok_) {
+        const int lane = threadIdx.x & 63;
         o_ = 0;
         e_ = 0;
         ok_ = false;
@@ -441,7 +372,7 @@ __device__ __forceinline__ void for_queue_arcs_pipe(int64_t e0, int deg, int32_t
         __builtin_amdgcn_wave_barrier();  // the previous round's reads first
         own[lane] = -1;
         if (deg > 0 && excl >= rk && excl < rk + 64) own[excl - rk] = lane;
-        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_wave_barrier();  // other lanes' writes before the read
         int o = own[lane];
         if (lane == 0) o = max(o, carry);
         const int i = wscan_max(o);
@@ -452,21 +383,63 @@ __device__ __forceinline__ void for_queue_arcs_pipe(int64_t e0, int deg, int32_t
         o_ = i;
         e_ = (int64_t)base + (p - ex);
         ok_ = p < total;
-    };
-    if (total == 0) return;
+    }
+};
+
+// One round at a time: f(owner, e, ok, incl, excl, r). All lanes stay converged, so f
+// may use cross-lane operations before it branches on ok.
+template <class F>
+__device__ __forceinline__ void for_queue_arcs(int64_t e0, int deg, int32_t* own, F&& f) {
+    QueueRounds Q(e0, deg, own);
+    for (int r = 0; r < Q.total; r += 64) {
+        int i;
+        int64_t e;
+        bool ok;
+        Q.round(r, i, e, ok);
+        f(i, e, ok, Q.incl, Q.excl, r);
+    }
+}
+
+// K rounds handed over at once: f(owner[K], e[K], ok[K]) gets the queue's arcs r ..
+// r + 64K - 1, arc r + 64k + lane in slot k, so that it can issue the loads of K arcs
+// per lane before it waits for any of them.
+template <int K, class F>
+__device__ __forceinline__ void for_queue_arcs_k(int64_t e0, int deg, int32_t* own, F&& f) {
+    QueueRounds Q(e0, deg, own);
+    for (int r = 0; r < Q.total; r += 64 * K) {
+        int ow[K];
+        int64_t ee[K];
+        bool ok[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) Q.round(r + 64 * k, ow[k], ee[k], ok[k]);
+        f(ow, ee, ok);
+    }
+}
+
+// Three stages per round, pipelined one round deep: x = load(e, ok) issues the round's
+// first loads; y = issue(owner, e, ok, incl, excl, r, x) uses them and issues the loads
+// that depend on them; then the next round's owners are found and its load() issued,
+// and only then finish(owner, e, ok, incl, excl, r, x, y) waits for the dependent loads. Rounds run in order (finish of
+// round r before issue of round r + 64), so what finish leaves behind (a row's running
+// minimum, its sums) is seen by the next round exactly as in for_queue_arcs.
+template <class LD, class IS, class FN>
+__device__ __forceinline__ void for_queue_arcs_pipe(int64_t e0, int deg, int32_t* own, LD&& load, IS&& issue,
+                                                    FN&& finish) {
+    QueueRounds Q(e0, deg, own);
+    if (Q.total == 0) return;
     int ow;
     int64_t e;
     bool ok;
-    owner_of(0, ow, e, ok);
+    Q.round(0, ow, e, ok);
     auto x = load(e, ok);
-    for (int r = 0; r < total; r += 64) {
-        const auto y = issue(ow, e, ok, incl, excl, r, x);
+    for (int r = 0; r < Q.total; r += 64) {
+        const auto y = issue(ow, e, ok, Q.incl, Q.excl, r, x);
         int ow2;
         int64_t e2;
         bool ok2;
-        owner_of(r + 64, ow2, e2, ok2);
+        Q.round(r + 64, ow2, e2, ok2);
         const auto x2 = load(e2, ok2);
-        finish(ow, e, ok, incl, excl, r, x, y);
+        finish(ow, e, ok, Q.incl, Q.excl, r, x, y);
         ow = ow2;
         e = e2;
         ok = ok2;
@@ -890,44 +863,17 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                     if constexpr (BYTE) {
                         if (arcp) {
                             done = true;
-                            const int incl = wscan_add(deg);
-                            const int total = __builtin_amdgcn_readlane(incl, 63);
-                            const int excl = incl - deg;
-                            const int e0lo = (int)(uint32_t)(uint64_t)e0, e0hi = (int)(uint32_t)((uint64_t)e0 >> 32);
-                            int carry = -1;
-                            // the owner slot and arc of this lane in round rk (as for_queue_arcs
-                            // finds them; rounds in increasing order)
-                            auto owner_of = [&](int rk, int& o_, int64_t& e_, bool& ok_) {
-                                o_ = 0;
-                                e_ = 0;
-                                ok_ = false;
-                                if (rk >= total) return;
-                                __builtin_amdgcn_wave_barrier();  // the previous round's reads first
-                                wq[lane] = -1;
-                                if (deg > 0 && excl >= rk && excl < rk + 64) wq[excl - rk] = lane;
-                                __builtin_amdgcn_wave_barrier();
-                                int o = wq[lane];
-                                if (lane == 0) o = max(o, carry);
-                                const int i = wscan_max(o);
-                                carry = __builtin_amdgcn_readlane(i, 63);
-                                const int p = rk + lane;
-                                const int ex = __shfl(excl, i, 64);
-                                const uint64_t base =
-                                    ((uint64_t)(uint32_t)__shfl(e0hi, i, 64) << 32) | (uint32_t)__shfl(e0lo, i, 64);
-                                o_ = i;
-                                e_ = (int64_t)base + (p - ex);
-                                ok_ = p < total;
-                            };
+                            QueueRounds Q(e0, deg, wq);
                             int ow[2];
                             int64_t ee[2];
                             bool ok[2];
                             ArcRec a[2];
 #pragma unroll
-                            for (int j = 0; j < 2; ++j) owner_of(64 * j, ow[j], ee[j], ok[j]);
+                            for (int j = 0; j < 2; ++j) Q.round(64 * j, ow[j], ee[j], ok[j]);
 #pragma unroll
                             for (int j = 0; j < 2; ++j)
                                 a[j] = ok[j] ? load_arc(arcp, ee[j]) : ArcRec{(uint32_t)lo, 1u, 0u, 1u};
-                            for (int r = 0; r < total; r += 128) {
+                            for (int r = 0; r < Q.total; r += 128) {
                                 int32_t u[2];
                                 uint32_t uw[2];
                                 bool par[2];
@@ -969,7 +915,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                                 bool ok2[2];
                                 ArcRec a2[2];
 #pragma unroll
-                                for (int j = 0; j < 2; ++j) owner_of(r + 128 + 64 * j, ow2[j], ee2[j], ok2[j]);
+                                for (int j = 0; j < 2; ++j) Q.round(r + 128 + 64 * j, ow2[j], ee2[j], ok2[j]);
 #pragma unroll
                                 for (int j = 0; j < 2; ++j)
                                     a2[j] = ok2[j] ? load_arc(arcp, ee2[j]) : ArcRec{(uint32_t)lo, 1u, 0u, 1u};
