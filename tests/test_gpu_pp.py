@@ -161,6 +161,21 @@ def test_pp_overflow(bcpp, engine_only):
     assert ei.value.code == bcpp.BC_E_OVERFLOW
 
 
+def test_pp_near_overflow_grid_reports_none(bcpp):
+    """34 x 35 grid, corner to corner: the largest path count is C(67, 33) < 2^64. With
+    5-row strips as parts every interior row holds up to 70 table entries, so a row's
+    entries span two rounds of the interior sweep, and products of counts over entries
+    that are not tight may pass 2^64: none of that may be reported as overflow (eq.
+    localcentrality sums only the tight entries), and the scores match the oracle."""
+    g = inputs.grid(34, 35)
+    G = bcpp.Graph(g)
+    part = (np.arange(g.n) // 35 // 5).astype(np.int32)
+    S = [0, g.n - 1]
+    sk = bcpp.partition_sk(G, part, 7, S)
+    assert max(len(r) for r in oracle.skeleton(g, part, 7, S)["tables"].values()) > 64
+    assert_scores(bcpp.brandes_pp(G, sk), oracle.bc(g, S))
+
+
 @PATHS
 def test_pp_planted_1k_full(bcpp, engine_only):
     g = inputs.planted_1k()
