@@ -622,8 +622,11 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     const bool bwd = (R.flags & GF_BACKWARD) != 0;
     // Node ownership blocks of the scan: a step's nodes cluster (communities are runs of
     // ids), and the step lasts as long as its busiest wave, so LDS-state groups deal
-    // 16-node blocks round the waves. Device-memory state keeps 64-node blocks, those of
-    // the bucket visit.
+    // 16-node blocks round the waves. Device-memory state keeps 64-node blocks (those of
+    // the bucket visit; with the byte state, a wave's 64 consecutive nodes share the lines
+    // of their arc records and counts, which outweighs the finer balance: pareto_100k's
+    // plain pass 28.6 ms with 16-node blocks, 26.6 ms with 64; whole per-wave slices
+    // lose the balance, 43 ms against 40 for Brandes_SK).
     constexpr int OWN_BLK = GLOBAL ? 64 : 16;
     const bool restrict_ = (R.flags & GF_RESTRICT) != 0;
     // Bucket bitmaps (state in device memory and R.lg >= 0), in LDS: bucket d mod 2^lg
@@ -1063,7 +1066,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
                 // within the step nothing else writes a node pending at D, and a node
                 // settled at D passes no parent test of the step (arcs are 1..126 long)
                 const uint32_t dres = D & 127u, sres = 0x80u | (D % 127u);
-                for_selected<T, 2, 16>(
+                for_selected<T, 4, OWN_BLK>(
                     n, wq,
                     [&](int32_t v) {
                         const uint32_t b = db[v];
