@@ -688,7 +688,17 @@ __global__ void k_reduce(const double* const* __restrict__ cacc,
         const double* const* parts = (which && which[v]) ? cint : cacc;
         const int32_t a = g0 ? g0[v] : ga;
         const int32_t b = g1 ? g1[v] : gb;
-        for (int32_t g = a; g < b; ++g) s += parts[g][i];
+        // eight groups' loads in flight at a time, added in group order (the same sum,
+        // bit for bit, as one group after another)
+        int32_t g = a;
+        for (; g + 8 <= b; g += 8) {
+            double x[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) x[j] = parts[g + j][i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += x[j];
+        }
+        for (; g < b; ++g) s += parts[g][i];
     }
     s *= scale;
     out[v] = accumulate ? out[v] + s : s;
