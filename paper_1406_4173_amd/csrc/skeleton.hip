@@ -884,8 +884,149 @@ int SkBuild::assemble(Arena& W, hipStream_t s, bc_skeleton* sk,
     return BC_OK;
 }
 
+// The skeleton when every node is a target, listed in id order: every part of P' is a
+// singleton, so every node with a neighbour is a frontier node, every arc a cut arc
+// <w, 1>, there are no clique arcs and no tables, and the renumbering (parts of P' in
+// label order, target i labelled k + i) keeps id order, only dropping the isolated
+// nodes, which are not frontier nodes (Sec. 5 with S = V: G_SK is G less its isolated
+// nodes). This is exactly what the general build assembles. Without isolated nodes it
+// reads G's arrays instead of copying them; with some, the arcs keep their positions
+// (isolated nodes have none) and only their heads are renumbered.
+__global__ void k_identity_nodes(int32_t n, int32_t nsk, const int32_t* __restrict__ remap,
+                                 int32_t* __restrict__ nodes, int32_t* __restrict__ out_idx,
+                                 uint8_t* __restrict__ out_which, uint8_t* __restrict__ nflag) {
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) {
+        const int32_t f = remap ? remap[v] : v;
+        out_idx[v] = f;
+        out_which[v] = 0;
+        if (f >= 0) nodes[f] = v;
+    }
+    if (v < nsk) nflag[v] = (uint8_t)NF_TARGET;
+}
+
+// Per arc: the all-ones multiplicity, and (with isolated nodes dropped) the renumbered
+// head, the length (1 for unit weights), the reverse arc and the packed record.
+__global__ void k_identity_arcs(int64_t m, const int32_t* __restrict__ remap, const int32_t* __restrict__ col,
+                                const uint32_t* __restrict__ len, const int64_t* __restrict__ twin,
+                                int32_t* __restrict__ col_out, uint32_t* __restrict__ len_out,
+                                int64_t* __restrict__ twin_out, ArcRec* __restrict__ arc_out,
+                                uint64_t* __restrict__ mult) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    mult[e] = 1ull;
+    const uint32_t L = len ? len[e] : 1u;
+    if (len_out) len_out[e] = L;
+    if (col_out) {
+        const int32_t c = remap[col[e]];
+        col_out[e] = c;
+        twin_out[e] = twin[e];
+        if (arc_out) arc_out[e] = ArcRec{(uint32_t)c, L, (uint32_t)twin[e], 1u};
+    }
+}
+
+static bool identity_skeleton_applies(const bc_graph* g, const int32_t* S, int32_t nS, bool given_singletons) {
+    // (BCPP_SK_IDENTITY=0 takes the general build, for comparisons)
+    const char* e = getenv("BCPP_SK_IDENTITY");
+    if ((e && e[0] == '0') || given_singletons || g->n < 1 || nS != g->n || !S) return false;
+    for (int32_t i = 0; i < nS; ++i)
+        if (S[i] != i) return false;
+    return true;
+}
+
+static int identity_skeleton(const bc_graph* g, const int32_t* part, int32_t k, bc_skeleton** out) {
+    const int32_t n = g->n;
+    if (!part) return fail(BC_E_INVAL, "null partition");
+    if (k < 1) return fail(BC_E_INVAL, "k must be >= 1");
+    for (int32_t v = 0; v < n; ++v)
+        if (part[v] < 0 || part[v] >= k)
+            return fail(BC_E_INVAL, "partition label out of range at node " + std::to_string(v));
+    const int64_t m = g->nnz;
+    // skeleton ids: the nodes with a neighbour, in id order
+    std::vector<int32_t> remap(n);
+    std::vector<int64_t> rp;
+    int32_t nsk = 0;
+    for (int32_t v = 0; v < n; ++v) remap[v] = g->h_row_ptr[v + 1] > g->h_row_ptr[v] ? nsk++ : -1;
+    const bool copy = nsk < n;
+    if (copy) {
+        rp.reserve((size_t)nsk + 1);
+        for (int32_t v = 0; v < n; ++v)
+            if (remap[v] >= 0) rp.push_back(g->h_row_ptr[v]);
+        rp.push_back(m);
+    }
+    auto sk = std::make_unique<bc_skeleton>();
+    const bool arcs_out = copy && g->d_arc;
+    const size_t bytes = (size_t)n * (4 + 4 + 1 + 1) + (size_t)m * 8 +
+                         (copy ? (size_t)n * 4 + (size_t)(nsk + 1) * 8 + (size_t)m * (4 + 4 + 8) : 0) +
+                         (!copy && !g->d_len ? (size_t)m * 4 : 0) + (arcs_out ? (size_t)m * 16 : 0) + 16 * 256;
+    BC_TRY(sk->store.reserve(bytes));
+    Arena& A = sk->store;
+    const size_t M = (size_t)std::max<int64_t>(m, 1);
+    sk->d_nodes = A.take<int32_t>(std::max(nsk, 1));
+    sk->d_out_idx = A.take<int32_t>(n);
+    sk->d_out_which = A.take<uint8_t>(n);
+    sk->d_nflag = A.take<uint8_t>(std::max(nsk, 1));
+    sk->d_mult = A.take<uint64_t>(M);
+    sk->d_trow = A.take<int64_t>(1);
+    int32_t* d_remap = copy ? A.take<int32_t>(n) : nullptr;
+    if (copy) {
+        sk->d_row_ptr = A.take<int64_t>((size_t)nsk + 1);
+        sk->d_col = A.take<int32_t>(M);
+        sk->d_len = A.take<uint32_t>(M);
+        sk->d_twin = A.take<int64_t>(M);
+        sk->d_arc = arcs_out ? A.take<ArcRec>(M) : nullptr;
+        sk->d_arc_store = sk->d_arc;
+    } else {
+        sk->d_row_ptr = g->d_row_ptr;
+        sk->d_col = g->d_col;
+        sk->d_len = g->d_len ? g->d_len : A.take<uint32_t>(M);
+        sk->d_twin = g->d_twin;
+        sk->d_arc = g->d_arc;
+    }
+    if (!sk->d_trow || !sk->d_len || (copy && (!sk->d_twin || (arcs_out && !sk->d_arc))))
+        return fail(BC_E_NOMEM, "skeleton store too small");
+    hipStream_t s = g->stream;
+    if (copy) {
+        BC_HIP(hipMemcpyAsync(d_remap, remap.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+        BC_HIP(hipMemcpyAsync(sk->d_row_ptr, rp.data(), rp.size() * 8, hipMemcpyHostToDevice, s));
+    }
+    hipLaunchKernelGGL(k_identity_nodes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nsk, d_remap,
+                       sk->d_nodes, sk->d_out_idx, sk->d_out_which, sk->d_nflag);
+    if (m > 0)
+        hipLaunchKernelGGL(k_identity_arcs, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, m, d_remap,
+                           g->d_col, g->d_len, g->d_twin, copy ? sk->d_col : nullptr,
+                           (copy || !g->d_len) ? sk->d_len : nullptr, copy ? sk->d_twin : nullptr,
+                           arcs_out ? sk->d_arc : nullptr, sk->d_mult);
+    zero_bytes(s, sk->d_trow, 8);
+    BC_HIP(hipGetLastError());
+    sk->graph = g;
+    sk->n = n;
+    sk->n_sk = nsk;
+    sk->n_int = 0;
+    sk->m_arcs = m;
+    sk->t_nnz = 0;
+    sk->max_len = std::max<int32_t>(1, m > 0 ? g->maxw : 1);
+    sk->max_dist = (int64_t)std::max(n - 1, 0) * g->maxw;
+    sk->h_row_ptr = copy ? rp : g->h_row_ptr;
+    sk->h_target_sk = remap;
+    sk->h_src.clear();
+    for (int32_t f : remap)
+        if (f >= 0) sk->h_src.push_back(f);
+    bc_sk_stats& st = sk->stats;
+    st.n = n;
+    st.n_sk = nsk;
+    st.k_prime = n;
+    st.largest_part = 1;
+    st.r_arcs = m;
+    st.device_bytes = (int64_t)bytes;
+    BC_HIP(hipStreamSynchronize(s));
+    *out = sk.release();
+    return BC_OK;
+}
+
 int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
                    bc_skeleton** out, bool given_singletons, PartitionKeep* keep) {
+    if (!keep && identity_skeleton_applies(g, S, nS, given_singletons)) return identity_skeleton(g, part, k, out);
     PhaseTrace tr("partition");
     SkBuild local;
     SkBuild& b = keep ? keep->b : local;

@@ -161,6 +161,38 @@ def test_pp_overflow(bcpp, engine_only):
     assert ei.value.code == bcpp.BC_E_OVERFLOW
 
 
+def test_identity_skeleton_equals_the_general_build(bcpp, monkeypatch):
+    """Every node a target, in id order: G_SK is G less its isolated nodes (Sec. 5 with
+    S = V), which the library then takes without building it. The skeleton it exports
+    and the scores equal the general build's bit for bit: unit weights without isolated
+    nodes (a grid in strips, G's own arrays), with one (planted_1k, arcs renumbered), and
+    weighted (sbm_10k)."""
+    grid = inputs.grid(30, 40)
+    grid.part = (np.arange(grid.n) // 40 // 6).astype(np.int32)
+    grid.k = 5
+    grid.S = np.arange(grid.n, dtype=np.int32)
+    planted = inputs.planted_1k()
+    assert np.sum(np.diff(planted.row_ptr) == 0) >= 1
+    for g in (grid, planted, inputs.sbm_10k()):
+        assert np.array_equal(g.S, np.arange(g.n))
+        got = {}
+        for mode in ("1", "0"):
+            monkeypatch.setenv("BCPP_SK_IDENTITY", mode)
+            G = bcpp.Graph(g)
+            sk = bcpp.partition_sk(G, g.part, g.k, g.S)
+            got[mode] = (sk.export(), sk.stats(), bcpp.brandes_pp(G, sk))
+        (ea, sa, ba), (eb, sb, bb) = got["1"], got["0"]
+        for key in ea:
+            assert np.array_equal(ea[key], eb[key]), key
+        assert {k: v for k, v in sa.items() if k != "device_bytes"} == {
+            k: v for k, v in sb.items() if k != "device_bytes"}
+        assert np.array_equal(ba, bb)
+    for seed in range(8):
+        g = inputs.random_graph(77 + seed, 40, 0.06, wmax=[None, 3][seed % 2], k=4)
+        g.S = np.arange(g.n, dtype=np.int32)
+        skeleton_matches_oracle(bcpp, g, g.part, g.k, g.S)
+
+
 def test_pp_near_overflow_grid_reports_none(bcpp):
     """34 x 35 grid, corner to corner: the largest path count is C(67, 33) < 2^64. With
     5-row strips as parts every interior row holds up to 70 table entries, so a row's
