@@ -191,6 +191,12 @@ def test_identity_skeleton_equals_the_general_build(bcpp, monkeypatch):
         g = inputs.random_graph(77 + seed, 40, 0.06, wmax=[None, 3][seed % 2], k=4)
         g.S = np.arange(g.n, dtype=np.int32)
         skeleton_matches_oracle(bcpp, g, g.part, g.k, g.S)
+    # every node isolated: an empty skeleton and zero scores
+    g = inputs.empty(5)
+    G = bcpp.Graph(g)
+    sk = bcpp.partition_sk(G, np.zeros(5, np.int32), 1, np.arange(5))
+    assert sk.stats()["n_sk"] == 0
+    assert np.array_equal(bcpp.brandes_pp(G, sk), np.zeros(5))
 
 
 def test_pp_near_overflow_grid_reports_none(bcpp):
