@@ -205,8 +205,10 @@ int bc_brandes_pp_dev(const bc_graph* g, const bc_skeleton* sk, uint32_t flags,
  * parts, and Brandes_SK with Centrality runs from the sources P_i, counting as
  * destinations only the nodes of P_j (the indicator of eq. multibrandes is I[v in
  * P_j]); the k^2 results are summed. Equal to bc_brandes_plain with S = V within the
- * stated tolerance, for any partition. It builds k^2 skeletons and runs k * n sources,
- * so it is much slower than bc_brandes_plain; it is the paper's all-pairs route.
+ * stated tolerance, for any partition. Build_SK's Dijkstra_SK runs once for part and
+ * serves every pass; each pass assembles its own skeleton, and the passes' Brandes_SK
+ * groups (k * n sources in all) share resident launches. It is much slower than
+ * bc_brandes_plain; it is the paper's all-pairs route.
  * Flags: BC_ORDERED only. bc_out: [n] doubles (host). */
 int bc_brandes_pp_all(const bc_graph* g, const int32_t* part, int32_t k, uint32_t flags,
                       double* bc_out);

@@ -70,10 +70,14 @@ inline const uint64_t* sk_mult(const bc_skeleton* sk) {
 }
 int graph_create(const bc_csr* csr, hipStream_t stream, bc_graph** out);
 struct PartitionKeep;
+struct DskCache;
 // Build_SK on g's stream. With keep, the build and the Dijkstra_SK launch stay in
-// *keep for a later replay of the device work (see SkBuild).
+// *keep for a later replay of the device work (see SkBuild). With cache (built over the
+// same graph and partition), the parts that hold no target take their Dijkstra_SK
+// results from it instead of running their groups.
 int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
-                   bc_skeleton** out, bool given_singletons, PartitionKeep* keep = nullptr);
+                   bc_skeleton** out, bool given_singletons, PartitionKeep* keep = nullptr,
+                   const DskCache* cache = nullptr);
 int validate_csr(const bc_csr* g, int32_t* maxw_out);
 int validate_targets(int32_t n, const int32_t* S, int32_t nS);
 int64_t max_steps_bound(int64_t range, int32_t lanes, int64_t max_dist);

@@ -85,21 +85,6 @@ struct Block {
     bool live = false;
 };
 
-// Dijkstra_SK results of a registered graph's parts, kept from one build without
-// targets. A part that holds no target of a query has the same nodes, induced
-// subgraph and frontier in the query's P' (a node next to a target of another part
-// was a frontier already), and its nodes keep their order in the renumbering, so its
-// Dijkstra_SK groups would write exactly these lanes: the query's build takes them
-// instead of running the groups (Sec. 5: parts are independent).
-struct DskCache {
-    bool ok = false;
-    std::vector<int32_t> first, count, nf;  // per part: cached groups [first, first+count), |F_p|
-    std::vector<uint32_t*> dist;            // per cached group: its output lanes
-    std::vector<uint64_t*> sig;
-    Arena store;
-    size_t bytes = 0;
-};
-
 // Q_RDSK / Q_RES: Dijkstra_SK, or Brandes_SK + Centrality, running as resident
 // launches on a side stream (Q_DSK / Q_BSK: the same on the shared engine)
 enum { Q_QUEUED = 0, Q_DSK = 1, Q_BSK = 2, Q_DONE = 3, Q_FAILED = 4, Q_RES = 5, Q_RDSK = 6 };
@@ -465,19 +450,7 @@ static int admit_prepared(bc_server* sv, Query* q) {
             const char* e = getenv("BCPP_SERVE_CACHE");
             return !(e && e[0] == '0');
         }();
-        if (use_cache && C && C->ok) {
-            std::vector<uint8_t> has_t(b.k_in, 0);
-            for (int32_t t : q->S) has_t[part[t]] = 1;
-            for (int32_t p = 0; p < b.k_in; ++p) {
-                if (has_t[p] || b.p_ng[p] == 0 || C->count[p] != b.p_ng[p] || C->nf[p] != b.pnf[p]) continue;
-                for (int32_t j = 0; j < b.p_ng[p]; ++j) {
-                    GroupDesc& G = b.groups[b.p_g0[p] + j];
-                    G.dist = C->dist[C->first[p] + j];
-                    G.sigma = C->sig[C->first[p] + j];
-                    preset[b.p_g0[p] + j] = 1;
-                }
-            }
-        }
+        if (use_cache && C && C->ok) dsk_preset_from_cache(b, *C, part, preset);
         // Dijkstra_SK as one resident launch on a side stream; parts larger than LDS
         // keep their one-source state in the query's block. A query without
         // Dijkstra_SK groups launches nothing and goes on to Brandes_SK when polled
@@ -533,50 +506,6 @@ static int admit_prepared(bc_server* sv, Query* q) {
     return BC_OK;
 }
 
-// The Dijkstra_SK results of every part of g under its own partition (no targets),
-// for DskCache. Leaves c->ok false when the groups do not all take the resident kernel.
-static int build_dsk_cache(bc_graph* g, const int32_t* part, int32_t k, DskCache* c) {
-    hipStream_t s = g->stream;
-    SkBuild b;
-    BC_TRY(b.prepare(g, part, k, nullptr, 0, false));
-    for (auto& G : b.groups)
-        if (!resident_takes((int64_t)G.hi - G.lo)) return BC_OK;
-    size_t need = b.temp_bytes() + resident_launch_bytes(b.groups.size()) + 8192;
-    size_t bytes = 0;
-    for (auto& G : b.groups) {
-        const size_t r = (size_t)(G.hi - G.lo);
-        if ((int64_t)r > resident_max_range()) need += r * 12 + 512;
-        bytes += ((r * 64 * 4 + 255) & ~(size_t)255) + ((r * 64 * 8 + 255) & ~(size_t)255);
-    }
-    Arena W;
-    BC_TRY(W.reserve(need));
-    BC_TRY(b.upload(W, s));
-    for (auto& G : b.groups) {
-        if ((int64_t)G.hi - G.lo <= resident_max_range()) continue;
-        G.gdist = W.take<uint32_t>((size_t)(G.hi - G.lo));
-        G.gsig = W.take<uint64_t>((size_t)(G.hi - G.lo));
-        if (!G.gdist || !G.gsig) return fail(BC_E_NOMEM, "server: cache workspace too small");
-    }
-    BC_TRY(run_resident(s, W, b.groups));
-    BC_TRY(c->store.reserve(bytes + 4096));
-    for (auto& G : b.groups) {
-        const size_t lanes = (size_t)(G.hi - G.lo) * 64;
-        uint32_t* d = c->store.take<uint32_t>(lanes);
-        uint64_t* q = c->store.take<uint64_t>(lanes);
-        if (!d || !q) return fail(BC_E_NOMEM, "server: cache store too small");
-        BC_HIP(hipMemcpyAsync(d, G.dist, lanes * 4, hipMemcpyDeviceToDevice, s));
-        BC_HIP(hipMemcpyAsync(q, G.sigma, lanes * 8, hipMemcpyDeviceToDevice, s));
-        c->dist.push_back(d);
-        c->sig.push_back(q);
-    }
-    BC_HIP(hipStreamSynchronize(s));
-    c->first.assign(b.p_g0.begin(), b.p_g0.begin() + k);
-    c->count.assign(b.p_ng.begin(), b.p_ng.begin() + k);
-    c->nf.assign(b.pnf.begin(), b.pnf.begin() + k);
-    c->bytes = c->store.cap;
-    c->ok = true;
-    return BC_OK;
-}
 
 static void server_loop(bc_server* sv) {
     (void)hipSetDevice(sv->device);

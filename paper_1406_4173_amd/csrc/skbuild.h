@@ -129,6 +129,33 @@ struct PartitionKeep {
     ResidentLaunch L;
 };
 
+// Dijkstra_SK results of a graph's parts, kept from one build without targets. A part
+// that holds no target of a later build over the same partition has the same nodes,
+// induced subgraph and frontier in that build's P' (a node next to a target of another
+// part is a frontier already), and its nodes keep their order in the renumbering, so
+// its Dijkstra_SK groups would write exactly these lanes: the later build takes them
+// instead of running the groups (Sec. 5: parts are independent).
+struct DskCache {
+    bool ok = false;
+    std::vector<int32_t> first, count, nf;  // per part: cached groups [first, first+count), |F_p|
+    std::vector<uint32_t*> dist;            // per cached group: its output lanes
+    std::vector<uint64_t*> sig;
+    Arena store;
+    size_t bytes = 0;
+};
+
+// Build_SK's Dijkstra_SK of every part of g under part (no targets) into *c, on g's
+// stream, in g's work arena. Leaves c->ok false when a group would not take the
+// resident kernel.
+int build_dsk_cache(bc_graph* g, const int32_t* part, int32_t k, DskCache* c);
+
+// After b.prepare and before b.upload: point the output lanes of b's Dijkstra_SK groups
+// at c's for every part of the given partition that holds none of b's targets and has
+// the cached group count and frontier size; preset[i] = 1 for each such group i.
+// Returns the number of groups preset.
+int32_t dsk_preset_from_cache(SkBuild& b, const DskCache& c, const int32_t* part,
+                              std::vector<uint8_t>& preset);
+
 // Brandes_SK groups (with the fused Centrality pass) over a skeleton, sources
 // src[0..nsrc) in skeleton ids, restricted to skeleton ids [lo, hi) and table rows
 // [t_lo, t_lo + tn).

@@ -1024,8 +1024,70 @@ static int identity_skeleton(const bc_graph* g, const int32_t* part, int32_t k, 
     return BC_OK;
 }
 
+int build_dsk_cache(bc_graph* g, const int32_t* part, int32_t k, DskCache* c) {
+    hipStream_t s = g->stream;
+    SkBuild b;
+    BC_TRY(b.prepare(g, part, k, nullptr, 0, false));
+    for (auto& G : b.groups)
+        if (!resident_takes((int64_t)G.hi - G.lo)) return BC_OK;
+    size_t need = b.temp_bytes() + resident_launch_bytes(b.groups.size()) + 8192;
+    size_t bytes = 0;
+    for (auto& G : b.groups) {
+        const size_t r = (size_t)(G.hi - G.lo);
+        if ((int64_t)r > resident_max_range()) need += r * 12 + 512;
+        bytes += ((r * 64 * 4 + 255) & ~(size_t)255) + ((r * 64 * 8 + 255) & ~(size_t)255);
+    }
+    Arena W;
+    BC_TRY(W.reserve(need));
+    BC_TRY(b.upload(W, s));
+    for (auto& G : b.groups) {
+        if ((int64_t)G.hi - G.lo <= resident_max_range()) continue;
+        G.gdist = W.take<uint32_t>((size_t)(G.hi - G.lo));
+        G.gsig = W.take<uint64_t>((size_t)(G.hi - G.lo));
+        if (!G.gdist || !G.gsig) return fail(BC_E_NOMEM, "Dijkstra_SK cache: workspace too small");
+    }
+    BC_TRY(run_resident(s, W, b.groups));
+    BC_TRY(c->store.reserve(bytes + 4096));
+    for (auto& G : b.groups) {
+        const size_t lanes = (size_t)(G.hi - G.lo) * 64;
+        uint32_t* d = c->store.take<uint32_t>(lanes);
+        uint64_t* q = c->store.take<uint64_t>(lanes);
+        if (!d || !q) return fail(BC_E_NOMEM, "Dijkstra_SK cache: store too small");
+        BC_HIP(hipMemcpyAsync(d, G.dist, lanes * 4, hipMemcpyDeviceToDevice, s));
+        BC_HIP(hipMemcpyAsync(q, G.sigma, lanes * 8, hipMemcpyDeviceToDevice, s));
+        c->dist.push_back(d);
+        c->sig.push_back(q);
+    }
+    BC_HIP(hipStreamSynchronize(s));
+    c->first.assign(b.p_g0.begin(), b.p_g0.begin() + k);
+    c->count.assign(b.p_ng.begin(), b.p_ng.begin() + k);
+    c->nf.assign(b.pnf.begin(), b.pnf.begin() + k);
+    c->bytes = c->store.cap;
+    c->ok = true;
+    return BC_OK;
+}
+
+int32_t dsk_preset_from_cache(SkBuild& b, const DskCache& c, const int32_t* part, std::vector<uint8_t>& preset) {
+    preset.assign(b.groups.size(), 0);
+    if (!c.ok || (int32_t)c.count.size() != b.k_in) return 0;
+    std::vector<uint8_t> has_t(b.k_in, 0);
+    for (int32_t t : b.S) has_t[part[t]] = 1;
+    int32_t got = 0;
+    for (int32_t p = 0; p < b.k_in; ++p) {
+        if (has_t[p] || b.p_ng[p] == 0 || c.count[p] != b.p_ng[p] || c.nf[p] != b.pnf[p]) continue;
+        for (int32_t j = 0; j < b.p_ng[p]; ++j) {
+            GroupDesc& G = b.groups[b.p_g0[p] + j];
+            G.dist = c.dist[c.first[p] + j];
+            G.sigma = c.sig[c.first[p] + j];
+            preset[b.p_g0[p] + j] = 1;
+            ++got;
+        }
+    }
+    return got;
+}
+
 int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int32_t* S, int32_t nS,
-                   bc_skeleton** out, bool given_singletons, PartitionKeep* keep) {
+                   bc_skeleton** out, bool given_singletons, PartitionKeep* keep, const DskCache* cache) {
     if (!keep && identity_skeleton_applies(g, S, nS, given_singletons)) return identity_skeleton(g, part, k, out);
     PhaseTrace tr("partition");
     SkBuild local;
@@ -1035,22 +1097,45 @@ int partition_impl(const bc_graph* g, const int32_t* part, int32_t k, const int3
     bc_graph* gm = const_cast<bc_graph*>(g);
     Arena& W = gm->work;
     hipStream_t s = g->stream;
+    // parts without a target take their Dijkstra_SK lanes from the cache (only on the
+    // resident kernel, whose lanes the cache holds, and never for a kept build)
+    std::vector<uint8_t> preset(b.groups.size(), 0);
+    int32_t npreset = 0;
+    if (cache && cache->ok && !keep && !given_singletons) {
+        bool all_res = true;
+        for (auto& G : b.groups) all_res = all_res && resident_takes((int64_t)G.hi - G.lo);
+        if (all_res) npreset = dsk_preset_from_cache(b, *cache, part, preset);
+    }
     int64_t positions = 0;
     for (auto& G : b.groups) positions += (int64_t)G.hi - G.lo;
     // Dijkstra_SK groups run on the resident kernel (parts larger than LDS keep their
     // one-source state in device memory), or on the engine when it is switched off
     bool res = !b.groups.empty();
     size_t extra = 0;
-    for (auto& G : b.groups) {
+    for (size_t i = 0; i < b.groups.size(); ++i) {
+        const GroupDesc& G = b.groups[i];
         res = res && resident_takes((int64_t)G.hi - G.lo);
-        if ((int64_t)G.hi - G.lo > resident_max_range()) extra += (size_t)(G.hi - G.lo) * 12 + 512;
+        if (!preset[i] && (int64_t)G.hi - G.lo > resident_max_range()) extra += (size_t)(G.hi - G.lo) * 12 + 512;
     }
     extra += resident_launch_bytes(b.groups.size());
     BC_TRY(W.reserve(b.temp_bytes() + std::max(extra, engine_bytes(std::max<int32_t>((int32_t)b.groups.size(), 1),
                                                                    positions))));
     BC_TRY(b.upload(W, s));
     tr.mark("upload");
-    if (res) {
+    if (res && npreset > 0) {
+        std::vector<GroupDesc> todo;
+        for (size_t i = 0; i < b.groups.size(); ++i) {
+            if (preset[i]) continue;
+            GroupDesc G = b.groups[i];
+            if ((int64_t)G.hi - G.lo > resident_max_range()) {
+                G.gdist = W.take<uint32_t>((size_t)(G.hi - G.lo));
+                G.gsig = W.take<uint64_t>((size_t)(G.hi - G.lo));
+                if (!G.gdist || !G.gsig) return fail(BC_E_NOMEM, "partition: workspace too small");
+            }
+            todo.push_back(G);
+        }
+        if (!todo.empty()) BC_TRY(run_resident(s, W, todo));
+    } else if (res) {
         for (auto& G : b.groups) {
             if ((int64_t)G.hi - G.lo <= resident_max_range()) continue;
             G.gdist = W.take<uint32_t>((size_t)(G.hi - G.lo));

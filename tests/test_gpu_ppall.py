@@ -51,3 +51,27 @@ def test_pp_all_singletons_and_unused_labels(bcpp):
     assert_scores(bcpp.brandes_pp_all(G, part, 6), want)
     with pytest.raises(bcpp.BcError):
         bcpp.brandes_pp_all(G, part, 4)
+
+
+def test_pp_all_shared_build_equals_per_pass_builds(bcpp, monkeypatch):
+    """Build_SK once (Alg. 3): the passes that take the shared Dijkstra_SK results of
+    the parts other than P_i and P_j, and run their Brandes_SK groups together, give the
+    scores of k^2 independent builds and launches bit for bit, also when the passes are
+    split over several launches (a pending-state cap of 0 MB: one launch per pass)."""
+    g2 = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 97, 0), inputs.equal_sizes(3000, 6),
+                    0.01, 900, 4, "sbm3k")
+    g3 = inputs.random_graph(9300, 60, 0.08, wmax=5, k=4)
+    for g in (inputs.planted_1k(), g2, g3):
+        G = bcpp.Graph(g)
+        got = []
+        for reuse, cap in (("0", None), ("1", None), ("1", "0")):
+            monkeypatch.setenv("BCPP_PPALL_REUSE", reuse)
+            if cap is None:
+                monkeypatch.delenv("BCPP_PPALL_PENDING_MB", raising=False)
+            else:
+                monkeypatch.setenv("BCPP_PPALL_PENDING_MB", cap)
+            got.append(bcpp.brandes_pp_all(G, g.part, g.k))
+        assert np.array_equal(got[0], got[1])
+        assert np.array_equal(got[0], got[2])
+        if g.n <= 1000:
+            assert_scores(got[1], oracle.bc(g, np.arange(g.n, dtype=np.int32)))
