@@ -26,6 +26,11 @@ enum : uint32_t {
     GF_CENT = 4u,      // then the interior-node Centrality pass over the tables
     GF_UNIT = 8u,      // every arc has length 1 (plain stores replace atomics)
     GF_EXPORT = 16u,   // resident backward groups: also write d and sigma after the forward
+    // resident GF_CENT groups: the interior rows are swept after the launch by a kernel
+    // of their own, for all of the group's sources at once, from d and sigma (odist,
+    // osig) and the backward's coefficients (ocoef) of every node per source; set by
+    // resident_alloc for the groups that qualify (resident_interior_split)
+    GF_ISPLIT = 32u,
 };
 
 enum : int32_t { PH_DONE = 0, PH_FWD = 1, PH_BWD = 2, PH_CENT = 3 };
@@ -97,6 +102,12 @@ struct GroupDesc {
     // sweep, source-major: row b (the group's b-th source) is odist[b * (hi-lo) ..]
     uint32_t* odist = nullptr;
     uint64_t* osig = nullptr;
+    // GF_ISPLIT: (I[v in S] + delta(s|v)) / sigma(s,v) of every node after each source's
+    // backward sweep (fp64 bits), laid out as odist
+    uint64_t* ocoef = nullptr;
+    // GF_ISPLIT: the same three node-major, [hi-lo][lanes] each (lanes: a power of two
+    // >= nsrc), for the interior sweep; see interior_rows_bytes for the layout
+    unsigned char* xsave = nullptr;
     int32_t src[LANES];      // source node ids of g, -1 = unused lane
 };
 
@@ -226,6 +237,11 @@ int32_t resident_sources_per_group(int64_t nsrc);
 // the part alone, so a part is split the same way in every build that holds it.
 int32_t dsk_sources_per_group(int64_t part_work);
 size_t resident_group_bytes(const GroupDesc& G);
+// Whether a Brandes_SK group with tables sweeps its interior rows in the kernel of its
+// own (GF_ISPLIT): 4 to 64 sources and their saved rows within a fixed size; a function
+// of the group alone. Environment BCPP_ISPLIT=0 keeps every group's rows in the
+// resident kernel.
+bool resident_interior_split(const GroupDesc& G);
 bool resident_alloc(Arena& a, GroupDesc& G);
 // Workspace run_resident takes from the arena for `ngroups` groups.
 size_t resident_launch_bytes(size_t ngroups);
@@ -241,6 +257,7 @@ int run_resident(hipStream_t s, Arena& a, const GroupDesc* const* groups, size_t
 // memory (ranges beyond LDS whose arcs are at most 63 long).
 struct RGroup;
 struct RCtx;
+struct IGroup;
 struct ResidentLaunch {
     RGroup* d_rg[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int32_t count[5] = {0, 0, 0, 0, 0};
@@ -248,6 +265,11 @@ struct ResidentLaunch {
     const RCtx* d_ctx = nullptr;
     const int32_t* d_src = nullptr;
     uint32_t* d_err = nullptr;
+    // GF_ISPLIT groups: their interior-row sweep, launched after the groups' kernels
+    const IGroup* d_ig = nullptr;
+    int32_t n_ig = 0;
+    int64_t ig_blocks = 0;  // k_interior blocks
+    int64_t ig_tblocks = 0;  // blocks of the transpose before it
     // profiler kind of the launches: BC_K_DIJKSTRA_SK when every group is forward-only
     int kind = BC_K_RESIDENT;
 };

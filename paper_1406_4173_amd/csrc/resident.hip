@@ -495,6 +495,33 @@ struct RGroup {
     uint32_t* steps;  // backward groups: distance of each forward step
     uint32_t* odist;  // GF_EXPORT: [nsrc][hi-lo] d(s,v) after each source's forward sweep
     uint64_t* osig;   //            [nsrc][hi-lo] sigma(s,v)
+    uint64_t* ocoef;  // GF_ISPLIT: [nsrc][hi-lo] coef(s,v) after each source's backward
+};
+
+// A saved value of one (node, source) for k_interior: d(s,v) and a 64-bit word,
+// sigma(s,v) or coef(s,v); 16 bytes, so that a row's threads read one line per node.
+struct IRec {
+    uint32_t d, pad;
+    uint64_t x;
+};
+
+// One GF_ISPLIT group for k_interior: its table rows, the rows its resident kernel saved
+// for each source, its interior scores, and its first block in the launch.
+struct IGroup {
+    int32_t lo, n, t_lo, tn;
+    int32_t nsrc, lanes;  // lanes per table row: a power of two >= nsrc, at most 64
+    int64_t blk0;         // first k_interior block
+    int64_t tblk0;        // first block of the transpose
+    const int64_t* trow;
+    const int32_t* tcol;
+    const uint32_t* tlen;
+    const uint64_t* tsig;
+    const uint32_t* odist;  // [nsrc][n], as the resident kernel saved them
+    const uint64_t* osig;
+    const uint64_t* ocoef;
+    IRec* xa;  // [n][lanes], node-major: {d, sigma} for the first sweep
+    IRec* xb;  //                         {d, coef} for the second
+    double* cint;  // [tn]
 };
 
 namespace {
@@ -610,6 +637,9 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
     const GAS uint32_t* __restrict__ tlen = gas(C.tlen);
     const GAS uint64_t* __restrict__ tsig = gas(C.tsig);
     const bool cent = (R.flags & GF_CENT) != 0 && R.tn > 0;
+    // the interior rows are left to k_interior: this kernel saves d, sigma and coef of
+    // every node per source instead
+    const bool isplit = cent && (R.flags & GF_ISPLIT) != 0;
     GAS double* __restrict__ cacc = gas(R.cacc);
     GAS double* __restrict__ cint = gas(R.cint);
     GAS uint32_t* __restrict__ steps = gas(R.steps);
@@ -1126,7 +1156,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             D = nx;
         }
         if (ovf) ovf_flag = 1u;
-        if (bwd && (R.flags & GF_EXPORT)) {
+        if (bwd && ((R.flags & GF_EXPORT) || isplit)) {
             // (the last step ended with a barrier: every count is final; the barrier
             // after the interior rows orders these reads before the backward's writes)
             GAS uint32_t* __restrict__ od = gas(R.odist) + (int64_t)b * n;
@@ -1153,7 +1183,7 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         // (as the sweeps spread a queue's arcs): first the row minimum of d(s,f) + d(f,v)
         // by segmented minima, then the sum of sigma(s,f) * sigma(f,v) over the entries
         // that attain it by segmented sums (eq. localcentrality's tight frontiers).
-        if (cent) {
+        if (cent && !isplit) {
             for (int32_t r0 = (tid >> 6) * 64; r0 < R.tn; r0 += T) {
                 const int32_t i = r0 + lane;
                 const bool valid = i < R.tn;
@@ -1405,7 +1435,11 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         // --------------------------------------------- interior rows: delta ----
         // the same spread: sum of sigma(f,v) * coef(s,f) over the frontiers f for which v
         // lies on a shortest path from s to f, times sigma(s,v) (eq. localcentrality)
-        if (cent) {
+        if (isplit) {
+            // (the backward's last step ended with a barrier: every coefficient is final)
+            GAS uint64_t* __restrict__ oc = gas(R.ocoef) + (int64_t)b * n;
+            for (int32_t v = tid; v < n; v += T) oc[v] = S_(v);
+        } else if (cent) {
             for (int32_t r0 = (tid >> 6) * 64; r0 < R.tn; r0 += T) {
                 const int32_t i = r0 + lane;
                 const bool valid = i < R.tn;
@@ -1469,6 +1503,172 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         bytes = wsum_u64(bytes);
         if (lane == 0 && bytes) atomicAdd(prof, bytes);
     }
+}
+
+constexpr int IT = 256;  // threads of a k_interior block
+constexpr int IU = 4;    // entries a thread has in flight
+
+// The saved rows of GF_ISPLIT groups, source-major as the resident kernel writes them
+// (one source at a time, in full lines), node-major for k_interior: a block takes
+// IT / lanes consecutive nodes of one group, thread j of a node its j-th source; reads
+// run along nodes per source and writes along the block.
+__global__ void __launch_bounds__(IT) k_itranspose(const IGroup* __restrict__ igs, int32_t nig, int64_t nblk) {
+    const int64_t lb = blockIdx.x;
+    int32_t glo = 0, ghi = nig - 1;
+    while (glo < ghi) {
+        const int32_t mid = (glo + ghi + 1) >> 1;
+        if (igs[mid].tblk0 <= lb)
+            glo = mid;
+        else
+            ghi = mid - 1;
+    }
+    const IGroup& G = igs[glo];
+    const int P = G.lanes;
+    const int t = threadIdx.x;
+    const int j = t & (P - 1);
+    const int64_t v = (lb - G.tblk0) * (IT / P) + t / P;
+    if (v >= G.n || j >= G.nsrc) return;
+    const int64_t i = (int64_t)j * G.n + v, o = v * P + j;
+    const uint32_t d = gas(G.odist)[i];
+    GAS IRec* a = gas(G.xa) + o;
+    GAS IRec* c = gas(G.xb) + o;
+    a->d = d;
+    a->pad = 0u;
+    a->x = gas(G.osig)[i];
+    c->d = d;
+    c->pad = 0u;
+    c->x = gas(G.ocoef)[i];
+}
+
+// Interior rows of GF_ISPLIT groups (Sec. 5, Step 3, eq. localcentrality), after the
+// groups' resident kernel. A block takes IT / lanes consecutive table rows of one group;
+// a row takes `lanes` consecutive threads, thread j for the group's j-th source. Each
+// thread sweeps its row's entries (f, d(f,v), sigma(f,v)) twice, in entry order: first
+// for d(s,v), the least d(s,f) + d(f,v), and sigma(s,v), the sum of sigma(s,f) *
+// sigma(f,v) over the f that attain it; then for the sum of sigma(f,v) * coef(s,f) over
+// the f for which v lies on a shortest path from s to f (d(s,f) = d(s,v) + d(f,v)),
+// which times sigma(s,v) is delta(s|v). The row's score is the sum of these over the
+// group's sources, in source order, as the resident kernel would add them. A row's
+// threads share its entry loads and read the saved values node-major (k_itranspose
+// lays them out so), one line per node for all of them; each thread loads IU entries
+// and then their saved values before it uses any, so that its loads overlap.
+__global__ void __launch_bounds__(IT) k_interior(const IGroup* __restrict__ igs, int32_t nig, int64_t nblk,
+                                                  uint32_t* __restrict__ err) {
+    // Blocks go to the 8 XCDs in turn by index; consecutive logical blocks (rows of one
+    // group, reading the same saved rows) are kept on one XCD and so in one L2.
+    const int64_t b = blockIdx.x;
+    const int64_t per = nblk / 8, rem = nblk % 8, x = b % 8;
+    const int64_t lb = (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + b / 8;
+    int32_t glo = 0, ghi = nig - 1;
+    while (glo < ghi) {
+        const int32_t mid = (glo + ghi + 1) >> 1;
+        if (igs[mid].blk0 <= lb)
+            glo = mid;
+        else
+            ghi = mid - 1;
+    }
+    const IGroup& G = igs[glo];
+    const int P = G.lanes;
+    const int t = threadIdx.x;
+    const int j = t & (P - 1);
+    const int32_t row = (int32_t)((lb - G.blk0) * (IT / P) + t / P);
+    const bool act = row < G.tn && j < G.nsrc;
+    const GAS int64_t* __restrict__ trow = gas(G.trow);
+    const GAS int32_t* __restrict__ tcol = gas(G.tcol);
+    const GAS uint32_t* __restrict__ tlen = gas(G.tlen);
+    const GAS uint64_t* __restrict__ tsig = gas(G.tsig);
+    uint32_t dmin = INF32;
+    uint64_t ssum = 0;
+    bool ovf = false;
+    double acc = 0.0;
+    const int base = (t & 63) & ~(P - 1);  // the row's first lane in the wave
+    if (row < G.tn) {
+        const int64_t e0 = trow[G.t_lo + row], e1 = trow[G.t_lo + row + 1];
+        // this source's saved records, indexed by the graph's node id
+        const int64_t oj = j - (int64_t)G.lo * P;
+        const GAS IRec* __restrict__ xa = gas(G.xa) + oj;
+        const GAS IRec* __restrict__ xb = gas(G.xb) + oj;
+        // The row's entries in chunks of P: thread j loads entry j of the chunk, and the
+        // row's threads pass them round with shuffles (every thread of the row runs the
+        // same trip counts); then each thread loads its source's records for up to IU of
+        // them before it uses any.
+        for (int sweep = 0; sweep < 2; ++sweep) {
+            if (sweep == 1 && __ballot(dmin != INF32 && act) == 0ull) break;
+            const GAS IRec* __restrict__ xr = sweep == 0 ? xa : xb;
+            for (int64_t c0 = e0; c0 < e1; c0 += P) {
+                const int64_t q = c0 + j;
+                int32_t fj = 0;
+                uint32_t Lj = 0u;
+                uint64_t mj = 0ull;
+                if (q < e1) {
+                    fj = tcol[q];
+                    Lj = tlen[q];
+                    mj = tsig[q];
+                }
+                const int cnt = (int)min<int64_t>(P, e1 - c0);
+                for (int u0 = 0; u0 < cnt; u0 += IU) {
+                    int32_t f[IU];
+                    uint32_t L[IU];
+                    uint64_t m[IU];
+                    IRec r[IU];
+#pragma unroll
+                    for (int k = 0; k < IU; ++k) {
+                        const int sl = base + min(u0 + k, cnt - 1);
+                        f[k] = __shfl(fj, sl, 64);
+                        L[k] = (uint32_t)__shfl((int)Lj, sl, 64);
+                        m[k] = (uint64_t)__shfl((long long)mj, sl, 64);
+                    }
+#pragma unroll
+                    for (int k = 0; k < IU; ++k)
+                        if (act) {
+                            // one 16-byte load per record
+                            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                            const u32x4 w = *reinterpret_cast<const GAS u32x4*>(xr + (int64_t)f[k] * P);
+                            r[k].d = w.x;
+                            r[k].x = ((uint64_t)w.w << 32) | w.z;
+                        }
+                    if (!act) continue;
+#pragma unroll
+                    for (int k = 0; k < IU; ++k) {
+                        if (u0 + k >= cnt || r[k].d == INF32) continue;
+                        if (sweep == 0) {
+                            const uint32_t val = r[k].d + L[k];
+                            if (val > dmin) continue;
+                            const bool o = __umul64hi(r[k].x, m[k]) != 0ull;
+                            const uint64_t pr = r[k].x * m[k];
+                            if (val < dmin) {
+                                dmin = val;
+                                ssum = pr;
+                                ovf = o;
+                            } else {
+                                ovf = ovf || o || ssum + pr < ssum;
+                                ssum += pr;
+                            }
+                        } else if (dmin != INF32 && r[k].d == dmin + L[k]) {
+                            acc += (double)m[k] * __longlong_as_double((long long)r[k].x);
+                        }
+                    }
+                }
+            }
+        }
+        if (act && dmin != INF32 && ovf) atomicOr(err, ERR_OVERFLOW);
+    }
+    const double c = (act && dmin != INF32) ? (double)ssum * acc : 0.0;
+    // the row's sum over its sources, in source order (every lane of the wave takes part)
+    double sum = 0.0;
+    for (int jj = 0; jj < G.nsrc; ++jj) sum += __shfl(c, base + jj, 64);
+    if (j == 0 && row < G.tn) gas(G.cint)[row] = sum;
+}
+
+// With the profiler on: the algorithmic bytes of the interior sweeps, 32 per (source,
+// table entry), one thread per group (a count per wave of k_interior would make one
+// device-wide atomic per wave).
+__global__ void k_interior_bytes(const IGroup* __restrict__ igs, int32_t nig, unsigned long long* __restrict__ prof) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nig) return;
+    const IGroup& G = igs[g];
+    const int64_t ents = G.trow[G.t_lo + G.tn] - G.trow[G.t_lo];
+    atomicAdd(prof, 32ull * (unsigned long long)G.nsrc * (unsigned long long)ents);
 }
 
 size_t lds_bytes(int64_t range) { return (((size_t)range * 4 + 15) & ~(size_t)15) + (size_t)range * 8; }
@@ -1615,6 +1815,19 @@ static bool device_tight_bitmap(const GroupDesc& G) {
            G.arcs < ((int64_t)1 << 31) - 64;
 }
 
+// Lanes of a table row in k_interior: a power of two >= nsrc.
+static int32_t interior_lanes(int32_t nsrc) {
+    int32_t P = 1;
+    while (P < nsrc) P <<= 1;
+    return P;
+}
+// The node-major saved records of a split group: {d, sigma} [range][P], then {d, coef}
+// [range][P], each array starting on 256 bytes.
+static size_t xsave_bytes(int64_t range, int32_t P) {
+    const size_t c = (size_t)range * (size_t)P;
+    return ((c * sizeof(IRec) + 255) & ~(size_t)255) * 2;
+}
+
 size_t resident_group_bytes(const GroupDesc& G) {
     const int64_t range = (int64_t)G.hi - G.lo;
     size_t b = ((size_t)range * 8 + 255) & ~(size_t)255;
@@ -1626,7 +1839,23 @@ size_t resident_group_bytes(const GroupDesc& G) {
         b += (((size_t)G.tn * 8 + 255) & ~(size_t)255) * 2 + (((size_t)G.tn * 4 + 255) & ~(size_t)255);
     if (G.flags & GF_BACKWARD)
         b += ((record_ints(range) * 4 + 255) & ~(size_t)255) + (((size_t)(range + 1) * 4 + 255) & ~(size_t)255);
+    if (resident_interior_split(G)) {
+        const size_t rows = (size_t)G.nsrc * (size_t)range;
+        b += ((rows * 4 + 255) & ~(size_t)255) + ((rows * 8 + 255) & ~(size_t)255) * 2 +
+             xsave_bytes(range, interior_lanes(G.nsrc));
+    }
     return b + 256;
+}
+
+bool resident_interior_split(const GroupDesc& G) {
+    const char* e = getenv("BCPP_ISPLIT");
+    if (e && e[0] == '0') return false;
+    if (!(G.flags & GF_CENT) || !(G.flags & GF_BACKWARD) || (G.flags & GF_RESTRICT) || G.tn <= 0) return false;
+    if (G.nsrc < 4 || G.nsrc > 64) return false;
+    // saved rows: d (4 bytes), sigma and coef (8 each) per source and node, source-major,
+    // and two 16-byte records per lane and node, node-major: at most 128 MiB
+    return ((size_t)G.nsrc * 20 + (size_t)interior_lanes(G.nsrc) * 32) * (size_t)((int64_t)G.hi - G.lo) <=
+           ((size_t)128 << 20);
 }
 
 bool resident_alloc(Arena& a, GroupDesc& G) {
@@ -1653,12 +1882,28 @@ bool resident_alloc(Arena& a, GroupDesc& G) {
         G.sigma = a.take<uint64_t>((size_t)G.tn);
         if (!G.cint || !G.dist || !G.sigma) return false;
     }
+    // the saved rows of a split group (a GF_EXPORT caller's own d and sigma rows serve)
+    G.flags &= ~(uint32_t)GF_ISPLIT;
+    G.ocoef = nullptr;
+    G.xsave = nullptr;
+    if (!(G.flags & GF_EXPORT)) G.odist = nullptr, G.osig = nullptr;
+    if (resident_interior_split(G)) {
+        const size_t rows = (size_t)G.nsrc * (size_t)range;
+        if (!(G.flags & GF_EXPORT)) {
+            G.odist = a.take<uint32_t>(rows);
+            G.osig = a.take<uint64_t>(rows);
+        }
+        G.ocoef = a.take<uint64_t>(rows);
+        G.xsave = a.take<unsigned char>(xsave_bytes(range, interior_lanes(G.nsrc)));
+        if (!G.odist || !G.osig || !G.ocoef || !G.xsave) return false;
+        G.flags |= GF_ISPLIT;
+    }
     return true;
 }
 
 size_t resident_launch_bytes(size_t ngroups) {
     // records, contexts and sources of up to five uploads, each rounded to 256 B
-    return ngroups * (sizeof(RGroup) + sizeof(RCtx) + LANES * 4) + 8 * 256 + 512;
+    return ngroups * (sizeof(RGroup) + sizeof(RCtx) + LANES * 4 + sizeof(IGroup)) + 9 * 256 + 512;
 }
 
 int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, size_t ng, ResidentLaunch* L) {
@@ -1669,6 +1914,8 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
     std::vector<RGroup> cls[5];
     std::vector<RCtx> ctx;
     std::vector<int32_t> src;
+    std::vector<IGroup> ig;
+    int64_t ig_blocks = 0, ig_tblocks = 0;
     std::map<std::pair<const void*, const void*>, int32_t> ctx_of;
     const SizeClasses sc;
     bool all_forward = ng > 0;
@@ -1737,8 +1984,37 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         r.steps = G.steps;
         r.odist = G.odist;
         r.osig = G.osig;
+        r.ocoef = G.ocoef;
         if ((G.flags & GF_EXPORT) && (!G.odist || !G.osig || !(G.flags & GF_BACKWARD)))
             return fail(BC_E_INVAL, "resident: export needs a backward group and output rows");
+        if (G.flags & GF_ISPLIT) {
+            if (!G.odist || !G.osig || !G.ocoef || !G.xsave || !G.cint || !(G.flags & GF_CENT) || G.tn <= 0 ||
+                G.nsrc < 1 || G.nsrc > 64)
+                return fail(BC_E_INVAL, "resident: split interior rows need saved rows and scores");
+            IGroup q{};
+            q.lo = G.lo;
+            q.n = (int32_t)range;
+            q.t_lo = G.t_lo;
+            q.tn = G.tn;
+            q.nsrc = G.nsrc;
+            q.lanes = interior_lanes(G.nsrc);
+            q.blk0 = ig_blocks;
+            q.tblk0 = ig_tblocks;
+            const size_t c = (size_t)range * (size_t)q.lanes;
+            q.xa = reinterpret_cast<IRec*>(G.xsave);
+            q.xb = reinterpret_cast<IRec*>(G.xsave + ((c * sizeof(IRec) + 255) & ~(size_t)255));
+            q.trow = G.trow;
+            q.tcol = G.tcol;
+            q.tlen = G.tlen;
+            q.tsig = G.tsig;
+            q.odist = G.odist;
+            q.osig = G.osig;
+            q.ocoef = G.ocoef;
+            q.cint = G.cint;
+            ig_blocks += ((int64_t)G.tn + IT / q.lanes - 1) / (IT / q.lanes);
+            ig_tblocks += (range + IT / q.lanes - 1) / (IT / q.lanes);
+            ig.push_back(q);
+        }
         if ((G.flags & GF_BACKWARD) && (!G.rlist || !G.steps))
             return fail(BC_E_INVAL, "resident: no record buffers for a backward group");
         cls[c].push_back(r);
@@ -1765,6 +2041,17 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         if (!L->d_rg[c]) return fail(BC_E_NOMEM, "resident: workspace too small");
         BC_HIP(hipMemcpyAsync(L->d_rg[c], cls[c].data(), cls[c].size() * sizeof(RGroup), hipMemcpyHostToDevice,
                               s));
+    }
+    if (!ig.empty()) {
+        if (ig_blocks >= ((int64_t)1 << 31) || ig_tblocks >= ((int64_t)1 << 31))
+            return fail(BC_E_INVAL, "resident: too many interior rows");
+        IGroup* d_ig = a.take<IGroup>(ig.size());
+        if (!d_ig) return fail(BC_E_NOMEM, "resident: workspace too small");
+        BC_HIP(hipMemcpyAsync(d_ig, ig.data(), ig.size() * sizeof(IGroup), hipMemcpyHostToDevice, s));
+        L->d_ig = d_ig;
+        L->n_ig = (int32_t)ig.size();
+        L->ig_blocks = ig_blocks;
+        L->ig_tblocks = ig_tblocks;
     }
     return BC_OK;
 }
@@ -1822,7 +2109,28 @@ static int side_set(hipStream_t s, SideSet** out) {
     return BC_OK;
 }
 
+// The interior rows of the launch's GF_ISPLIT groups, after their resident kernels.
+static int launch_interior(hipStream_t s, const ResidentLaunch& L) {
+    if (L.n_ig == 0) return BC_OK;
+    unsigned long long* prof =
+        profiler().on && profiler().d_bytes ? profiler().d_bytes + BC_K_CENTRALITY : nullptr;
+    KTimer kt(BC_K_CENTRALITY, s);
+    hipLaunchKernelGGL(k_itranspose, dim3((unsigned)L.ig_tblocks), dim3(IT), 0, s, L.d_ig, L.n_ig, L.ig_tblocks);
+    hipLaunchKernelGGL(k_interior, dim3((unsigned)L.ig_blocks), dim3(IT), 0, s, L.d_ig, L.n_ig, L.ig_blocks,
+                       L.d_err);
+    if (prof) hipLaunchKernelGGL(k_interior_bytes, dim3((unsigned)((L.n_ig + 255) / 256)), dim3(256), 0, s, L.d_ig, L.n_ig, prof);
+    BC_HIP(hipGetLastError());
+    return BC_OK;
+}
+
+static int launch_classes(hipStream_t s, const ResidentLaunch& L);
+
 int resident_launch(hipStream_t s, const ResidentLaunch& L) {
+    BC_TRY(launch_classes(s, L));
+    return launch_interior(s, L);
+}
+
+static int launch_classes(hipStream_t s, const ResidentLaunch& L) {
     unsigned long long* prof = profiler().on && profiler().d_bytes ? profiler().d_bytes + L.kind : nullptr;
     int ncls = 0;
     for (int c = 0; c < 5; ++c) ncls += L.count[c] > 0;

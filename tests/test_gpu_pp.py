@@ -341,3 +341,33 @@ def test_pp_lds_skeleton_with_wide_cliques(bcpp):
     st = sk.stats()
     assert st["n_sk"] == 1531 and st["r_arcs"] + st["clique_arcs"] >= 6 * st["n_sk"]
     assert_scores(bcpp.brandes_pp(G, sk), oracle.bc(g, g.S))
+
+
+def test_pp_split_interior_rows(bcpp, monkeypatch):
+    """Groups of 4 to 64 sources sweep their interior rows (Sec. 5, eq. localcentrality)
+    in a kernel of their own after the resident launch. Its scores equal the oracle's
+    within 1e-9, and the in-kernel sweep's (BCPP_ISPLIT=0), with rows staged in LDS
+    (parts of 250 nodes) and rows read from device memory (parts of 4,000 nodes, whose
+    frontier does not fit), unit and integer weights, and 6 sources per group in 8
+    lanes; a second run gives the same bits."""
+    cases = []
+    for seed, wmax in ((0, None), (1, 4)):
+        g = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 99, seed), inputs.equal_sizes(3000, 12), 0.012, 600,
+                       wmax, "split3k")
+        cases.append((g, inputs.random_targets(70 + seed, g.n, 1500)))  # 6 sources per group
+    g = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 99, 2), inputs.equal_sizes(12000, 3), 0.002, 3000, 3,
+                   "split12k")
+    cases.append((g, inputs.random_targets(72, g.n, 1024)))  # 4 sources per group
+    for g, S in cases:
+        G = bcpp.Graph(g)
+        sk = bcpp.partition_sk(G, g.part, g.k, S)
+        assert sk.stats()["table_nnz"] > 0
+        want = oracle.bc(g, S)
+        monkeypatch.setenv("BCPP_ISPLIT", "1")
+        a = bcpp.brandes_pp(G, sk)
+        assert np.array_equal(a, bcpp.brandes_pp(G, sk))
+        monkeypatch.setenv("BCPP_ISPLIT", "0")
+        b = bcpp.brandes_pp(G, sk)
+        assert_scores(a, want)
+        assert_scores(b, want)
+        assert_scores(a, b)
