@@ -238,9 +238,9 @@ int32_t resident_sources_per_group(int64_t nsrc);
 int32_t dsk_sources_per_group(int64_t part_work);
 size_t resident_group_bytes(const GroupDesc& G);
 // Whether a Brandes_SK group with tables sweeps its interior rows in the kernel of its
-// own (GF_ISPLIT): 4 to 64 sources and their saved rows within a fixed size; a function
-// of the group alone. Environment BCPP_ISPLIT=0 keeps every group's rows in the
-// resident kernel.
+// own (GF_ISPLIT): at most 64 sources, at least 4 or at least 8192 table rows, and its
+// saved rows within a fixed size; a function of the group alone. Environment
+// BCPP_ISPLIT=0 keeps every group's rows in the resident kernel.
 bool resident_interior_split(const GroupDesc& G);
 bool resident_alloc(Arena& a, GroupDesc& G);
 // Workspace run_resident takes from the arena for `ngroups` groups.

@@ -1161,10 +1161,21 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
             // after the interior rows orders these reads before the backward's writes)
             GAS uint32_t* __restrict__ od = gas(R.odist) + (int64_t)b * n;
             GAS uint64_t* __restrict__ os = gas(R.osig) + (int64_t)b * n;
-            for (int32_t v = tid; v < n; v += T) {
-                const uint32_t dv = D_(v);
-                od[v] = dv;
-                os[v] = dv == INF32 ? 0ull : S_(v);
+            // four nodes per thread at a time, their loads issued before any is used
+            constexpr int XU = 4;
+            for (int32_t v0 = tid; v0 < n; v0 += XU * T) {
+                uint32_t dv[XU];
+                uint64_t sv[XU];
+#pragma unroll
+                for (int u = 0; u < XU; ++u) dv[u] = v0 + u * T < n ? D_(v0 + u * T) : INF32;
+#pragma unroll
+                for (int u = 0; u < XU; ++u) sv[u] = dv[u] != INF32 ? S_(v0 + u * T) : 0ull;
+#pragma unroll
+                for (int u = 0; u < XU; ++u)
+                    if (v0 + u * T < n) {
+                        od[v0 + u * T] = dv[u];
+                        os[v0 + u * T] = sv[u];
+                    }
             }
         }
         if (!bwd) {
@@ -1438,7 +1449,15 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
         if (isplit) {
             // (the backward's last step ended with a barrier: every coefficient is final)
             GAS uint64_t* __restrict__ oc = gas(R.ocoef) + (int64_t)b * n;
-            for (int32_t v = tid; v < n; v += T) oc[v] = S_(v);
+            constexpr int XU = 8;
+            for (int32_t v0 = tid; v0 < n; v0 += XU * T) {
+                uint64_t cv[XU];
+#pragma unroll
+                for (int u = 0; u < XU; ++u) cv[u] = v0 + u * T < n ? S_(v0 + u * T) : 0ull;
+#pragma unroll
+                for (int u = 0; u < XU; ++u)
+                    if (v0 + u * T < n) oc[v0 + u * T] = cv[u];
+            }
         } else if (cent) {
             for (int32_t r0 = (tid >> 6) * 64; r0 < R.tn; r0 += T) {
                 const int32_t i = r0 + lane;
@@ -1851,7 +1870,13 @@ bool resident_interior_split(const GroupDesc& G) {
     const char* e = getenv("BCPP_ISPLIT");
     if (e && e[0] == '0') return false;
     if (!(G.flags & GF_CENT) || !(G.flags & GF_BACKWARD) || (G.flags & GF_RESTRICT) || G.tn <= 0) return false;
-    if (G.nsrc < 4 || G.nsrc > 64) return false;
+    // 4 sources or more, or many rows: a sweep per source then fills a whole launch
+    // (BCPP_ISPLIT_MIN and BCPP_ISPLIT_ROWS set the two bounds, for the tuning sweeps)
+    int32_t lo = 4;
+    int64_t rows = 8192;
+    if (const char* m = getenv("BCPP_ISPLIT_MIN")) lo = std::max(1, atoi(m));
+    if (const char* r = getenv("BCPP_ISPLIT_ROWS")) rows = std::max<int64_t>(1, atoll(r));
+    if (G.nsrc > 64 || (G.nsrc < lo && G.tn < rows)) return false;
     // saved rows: d (4 bytes), sigma and coef (8 each) per source and node, source-major,
     // and two 16-byte records per lane and node, node-major: at most 128 MiB
     return ((size_t)G.nsrc * 20 + (size_t)interior_lanes(G.nsrc) * 32) * (size_t)((int64_t)G.hi - G.lo) <=

@@ -344,12 +344,12 @@ def test_pp_lds_skeleton_with_wide_cliques(bcpp):
 
 
 def test_pp_split_interior_rows(bcpp, monkeypatch):
-    """Groups of 4 to 64 sources sweep their interior rows (Sec. 5, eq. localcentrality)
-    in a kernel of their own after the resident launch. Its scores equal the oracle's
-    within 1e-9, and the in-kernel sweep's (BCPP_ISPLIT=0), with rows staged in LDS
-    (parts of 250 nodes) and rows read from device memory (parts of 4,000 nodes, whose
-    frontier does not fit), unit and integer weights, and 6 sources per group in 8
-    lanes; a second run gives the same bits."""
+    """Groups of 4 to 64 sources, or with at least 8192 table rows, sweep their interior
+    rows (Sec. 5, eq. localcentrality) in a kernel of their own after the resident
+    launch. Its scores equal the oracle's within 1e-9, and the in-kernel sweep's
+    (BCPP_ISPLIT=0): parts of 250 and of 4,000 nodes, unit and integer weights, 6
+    sources per group in 8 lanes, 4 per group, and one source per group over 38,000
+    rows; a second run gives the same bits."""
     cases = []
     for seed, wmax in ((0, None), (1, 4)):
         g = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 99, seed), inputs.equal_sizes(3000, 12), 0.012, 600,
@@ -358,6 +358,9 @@ def test_pp_split_interior_rows(bcpp, monkeypatch):
     g = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 99, 2), inputs.equal_sizes(12000, 3), 0.002, 3000, 3,
                    "split12k")
     cases.append((g, inputs.random_targets(72, g.n, 1024)))  # 4 sources per group
+    g = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 99, 3), inputs.equal_sizes(40000, 2000), 0.3, 1500, 3,
+                   "split40k")
+    cases.append((g, inputs.random_targets(73, g.n, 60)))  # one source per group, many rows
     for g, S in cases:
         G = bcpp.Graph(g)
         sk = bcpp.partition_sk(G, g.part, g.k, S)
