@@ -32,7 +32,8 @@ KERNEL_SOURCES = {
     "settle": "paper_1406_4173_amd/csrc/engine.hip",
     "push": "paper_1406_4173_amd/csrc/engine.hip",
     "backward": "paper_1406_4173_amd/csrc/engine.hip",
-    "centrality": "paper_1406_4173_amd/csrc/engine.hip",
+    # (the resident path's Centrality: the transpose and the interior sweep of split groups)
+    "centrality": "paper_1406_4173_amd/csrc/resident.hip",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
@@ -553,7 +554,7 @@ def main():
     kern = max((k for k in prof if k not in ("other",)), key=lambda k: prof[k]["ms"])
     res["roofline"] = roofline_entry(args.workload, kern, prof[kern])
     res["kernels"] = {k: dict(roofline_entry(args.workload, k, v), ms_per_step=v["ms"] / args.steps)
-                      for k, v in prof.items() if v["launches"] > 0 and k in ("resident", "dijkstra_sk")}
+                      for k, v in prof.items() if v["launches"] > 0 and k in ("resident", "dijkstra_sk", "centrality")}
     res["kernels_ms_per_step"] = {k: v["ms"] / args.steps for k, v in prof.items()}
     # where a Brandes++ step goes: the partition call (P', frontiers, Dijkstra_SK,
     # assembly; host work included) and the Brandes_SK + Centrality call, timed apart
@@ -565,6 +566,7 @@ def main():
         "brandes_sk_centrality": t_bsk * 1e3,
         "dijkstra_sk_kernel": prof["dijkstra_sk"]["ms"] / args.steps,
         "brandes_sk_kernel": prof["resident"]["ms"] / args.steps,
+        "centrality_kernels": prof["centrality"]["ms"] / args.steps,
     }
     if not args.no_plain:
         t_plain = timed(plain_step, args.steps, args.warmup, sync)
