@@ -268,8 +268,10 @@ struct ResidentLaunch {
     // GF_ISPLIT groups: their interior-row sweep, launched after the groups' kernels
     const IGroup* d_ig = nullptr;
     int32_t n_ig = 0;
-    int64_t ig_blocks = 0;  // k_interior blocks
-    int64_t ig_tblocks = 0;  // blocks of the transpose before it
+    int32_t n_ig_wide = 0;   // the first n_ig_wide share entry loads across a row's threads
+    int64_t ig_blocks = 0;   // k_interior blocks of those
+    int64_t ig_nblocks = 0;  // and of the rest
+    int64_t ig_tblocks = 0;  // blocks of the transpose before them
     // profiler kind of the launches: BC_K_DIJKSTRA_SK when every group is forward-only
     int kind = BC_K_RESIDENT;
 };

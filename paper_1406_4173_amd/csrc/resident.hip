@@ -1571,6 +1571,7 @@ __global__ void __launch_bounds__(IT) k_itranspose(const IGroup* __restrict__ ig
 // threads share its entry loads and read the saved values node-major (k_itranspose
 // lays them out so), one line per node for all of them; each thread loads IU entries
 // and then their saved values before it uses any, so that its loads overlap.
+template <bool SHARE>
 __global__ void __launch_bounds__(IT) k_interior(const IGroup* __restrict__ igs, int32_t nig, int64_t nblk,
                                                   uint32_t* __restrict__ err) {
     // Blocks go to the 8 XCDs in turn by index; consecutive logical blocks (rows of one
@@ -1614,17 +1615,20 @@ __global__ void __launch_bounds__(IT) k_interior(const IGroup* __restrict__ igs,
         for (int sweep = 0; sweep < 2; ++sweep) {
             if (sweep == 1 && __ballot(dmin != INF32 && act) == 0ull) break;
             const GAS IRec* __restrict__ xr = sweep == 0 ? xa : xb;
-            for (int64_t c0 = e0; c0 < e1; c0 += P) {
+            // (SHARE: rows of at least IU threads; narrower rows' threads load IU entries
+            // each themselves)
+            const int CH = SHARE ? P : IU;
+            for (int64_t c0 = e0; c0 < e1; c0 += CH) {
                 const int64_t q = c0 + j;
                 int32_t fj = 0;
                 uint32_t Lj = 0u;
                 uint64_t mj = 0ull;
-                if (q < e1) {
+                if (SHARE && q < e1) {
                     fj = tcol[q];
                     Lj = tlen[q];
                     mj = tsig[q];
                 }
-                const int cnt = (int)min<int64_t>(P, e1 - c0);
+                const int cnt = (int)min<int64_t>(CH, e1 - c0);
                 for (int u0 = 0; u0 < cnt; u0 += IU) {
                     int32_t f[IU];
                     uint32_t L[IU];
@@ -1632,10 +1636,17 @@ __global__ void __launch_bounds__(IT) k_interior(const IGroup* __restrict__ igs,
                     IRec r[IU];
 #pragma unroll
                     for (int k = 0; k < IU; ++k) {
-                        const int sl = base + min(u0 + k, cnt - 1);
-                        f[k] = __shfl(fj, sl, 64);
-                        L[k] = (uint32_t)__shfl((int)Lj, sl, 64);
-                        m[k] = (uint64_t)__shfl((long long)mj, sl, 64);
+                        if constexpr (SHARE) {
+                            const int sl = base + min(u0 + k, cnt - 1);
+                            f[k] = __shfl(fj, sl, 64);
+                            L[k] = (uint32_t)__shfl((int)Lj, sl, 64);
+                            m[k] = (uint64_t)__shfl((long long)mj, sl, 64);
+                        } else {
+                            const int64_t qk = c0 + min(u0 + k, cnt - 1);
+                            f[k] = tcol[qk];
+                            L[k] = tlen[qk];
+                            m[k] = tsig[qk];
+                        }
                     }
 #pragma unroll
                     for (int k = 0; k < IU; ++k)
@@ -1939,8 +1950,8 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
     std::vector<RGroup> cls[5];
     std::vector<RCtx> ctx;
     std::vector<int32_t> src;
-    std::vector<IGroup> ig;
-    int64_t ig_blocks = 0, ig_tblocks = 0;
+    std::vector<IGroup> ig, ig_narrow;  // rows of >= IU threads, and narrower
+    int64_t ig_blocks = 0, ig_nblocks = 0, ig_tblocks = 0;
     std::map<std::pair<const void*, const void*>, int32_t> ctx_of;
     const SizeClasses sc;
     bool all_forward = ng > 0;
@@ -2023,8 +2034,8 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
             q.tn = G.tn;
             q.nsrc = G.nsrc;
             q.lanes = interior_lanes(G.nsrc);
-            q.blk0 = ig_blocks;
-            q.tblk0 = ig_tblocks;
+            int64_t& nb = q.lanes >= IU ? ig_blocks : ig_nblocks;
+            q.blk0 = nb;
             const size_t c = (size_t)range * (size_t)q.lanes;
             q.xa = reinterpret_cast<IRec*>(G.xsave);
             q.xb = reinterpret_cast<IRec*>(G.xsave + ((c * sizeof(IRec) + 255) & ~(size_t)255));
@@ -2036,9 +2047,8 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
             q.osig = G.osig;
             q.ocoef = G.ocoef;
             q.cint = G.cint;
-            ig_blocks += ((int64_t)G.tn + IT / q.lanes - 1) / (IT / q.lanes);
-            ig_tblocks += (range + IT / q.lanes - 1) / (IT / q.lanes);
-            ig.push_back(q);
+            nb += ((int64_t)G.tn + IT / q.lanes - 1) / (IT / q.lanes);
+            (q.lanes >= IU ? ig : ig_narrow).push_back(q);
         }
         if ((G.flags & GF_BACKWARD) && (!G.rlist || !G.steps))
             return fail(BC_E_INVAL, "resident: no record buffers for a backward group");
@@ -2067,15 +2077,24 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         BC_HIP(hipMemcpyAsync(L->d_rg[c], cls[c].data(), cls[c].size() * sizeof(RGroup), hipMemcpyHostToDevice,
                               s));
     }
-    if (!ig.empty()) {
-        if (ig_blocks >= ((int64_t)1 << 31) || ig_tblocks >= ((int64_t)1 << 31))
+    if (!ig.empty() || !ig_narrow.empty()) {
+        // one array, the narrow rows' groups last; the transpose's blocks over all of them
+        const int32_t nwide = (int32_t)ig.size();
+        ig.insert(ig.end(), ig_narrow.begin(), ig_narrow.end());
+        for (IGroup& q : ig) {
+            q.tblk0 = ig_tblocks;
+            ig_tblocks += ((int64_t)q.n + IT / q.lanes - 1) / (IT / q.lanes);
+        }
+        if (ig_blocks >= ((int64_t)1 << 31) || ig_nblocks >= ((int64_t)1 << 31) || ig_tblocks >= ((int64_t)1 << 31))
             return fail(BC_E_INVAL, "resident: too many interior rows");
         IGroup* d_ig = a.take<IGroup>(ig.size());
         if (!d_ig) return fail(BC_E_NOMEM, "resident: workspace too small");
         BC_HIP(hipMemcpyAsync(d_ig, ig.data(), ig.size() * sizeof(IGroup), hipMemcpyHostToDevice, s));
         L->d_ig = d_ig;
         L->n_ig = (int32_t)ig.size();
+        L->n_ig_wide = nwide;
         L->ig_blocks = ig_blocks;
+        L->ig_nblocks = ig_nblocks;
         L->ig_tblocks = ig_tblocks;
     }
     return BC_OK;
@@ -2141,8 +2160,12 @@ static int launch_interior(hipStream_t s, const ResidentLaunch& L) {
         profiler().on && profiler().d_bytes ? profiler().d_bytes + BC_K_CENTRALITY : nullptr;
     KTimer kt(BC_K_CENTRALITY, s);
     hipLaunchKernelGGL(k_itranspose, dim3((unsigned)L.ig_tblocks), dim3(IT), 0, s, L.d_ig, L.n_ig, L.ig_tblocks);
-    hipLaunchKernelGGL(k_interior, dim3((unsigned)L.ig_blocks), dim3(IT), 0, s, L.d_ig, L.n_ig, L.ig_blocks,
-                       L.d_err);
+    if (L.n_ig_wide > 0)
+        hipLaunchKernelGGL(k_interior<true>, dim3((unsigned)L.ig_blocks), dim3(IT), 0, s, L.d_ig, L.n_ig_wide,
+                           L.ig_blocks, L.d_err);
+    if (L.n_ig > L.n_ig_wide)
+        hipLaunchKernelGGL(k_interior<false>, dim3((unsigned)L.ig_nblocks), dim3(IT), 0, s, L.d_ig + L.n_ig_wide,
+                           L.n_ig - L.n_ig_wide, L.ig_nblocks, L.d_err);
     if (prof) hipLaunchKernelGGL(k_interior_bytes, dim3((unsigned)((L.n_ig + 255) / 256)), dim3(256), 0, s, L.d_ig, L.n_ig, prof);
     BC_HIP(hipGetLastError());
     return BC_OK;
