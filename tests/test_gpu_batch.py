@@ -139,3 +139,27 @@ def test_batch_ordered_is_twice_unordered(bcpp, graph):
         for x, y, g in zip(a, b, gs):
             assert np.array_equal(y, 2.0 * x)
             assert_scores(y, oracle.bc(g, g.S, True))
+
+
+def test_batch_pp_split_interior_replays(bcpp):
+    """Graphs whose Brandes_SK groups sweep their interior rows in the kernels of their
+    own (groups of 6 sources in 8 lanes; one source over 37,000 rows) inside a batch:
+    the captured pass replays bit for bit equal to its eager run, each graph equals its
+    run alone, and the scores equal the oracle's within 1e-9."""
+    wide = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 99, 0), inputs.equal_sizes(3000, 12), 0.012, 600,
+                      None, "split3k")
+    wide.S = inputs.random_targets(70, wide.n, 1500)
+    narrow = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 99, 3), inputs.equal_sizes(40000, 2000), 0.3, 1500, 3,
+                        "split40k")
+    narrow.S = inputs.random_targets(73, narrow.n, 60)
+    gs = [wide] + inputs.batch_256(6) + [narrow]
+    B = bcpp.Batch(gs)
+    eager = B.run(pp=True, graph=False)
+    for g, got in zip(gs, eager):
+        assert_scores(got, oracle.bc(g, g.S))
+        G = bcpp.Graph(g)
+        assert np.array_equal(got, bcpp.brandes_pp(G, bcpp.partition_sk(G, g.part, g.k, g.S)))
+    for rep in range(3):
+        res = B.run(pp=True)
+        for a, b in zip(res, eager):
+            assert np.array_equal(a, b), f"replay {rep} differs from the eager run"
