@@ -1604,10 +1604,13 @@ __global__ void __launch_bounds__(IT) k_interior(const IGroup* __restrict__ igs,
     const int base = (t & 63) & ~(P - 1);  // the row's first lane in the wave
     if (row < G.tn) {
         const int64_t e0 = trow[G.t_lo + row], e1 = trow[G.t_lo + row + 1];
-        // this source's saved records, indexed by the graph's node id
-        const int64_t oj = j - (int64_t)G.lo * P;
-        const GAS IRec* __restrict__ xa = gas(G.xa) + oj;
-        const GAS IRec* __restrict__ xb = gas(G.xb) + oj;
+        // this source's saved records, indexed by the graph's node id f: the record of
+        // node f of the range sits at (f - lo) * P + j, so the bases are shifted by
+        // lo * P records (in integer arithmetic: they may point before the arrays, and
+        // only base + f * P is dereferenced), which saves a subtraction per record
+        const uintptr_t sh = (uintptr_t)((int64_t)j - (int64_t)G.lo * P) * sizeof(IRec);
+        const GAS IRec* __restrict__ xa = (const GAS IRec*)((uintptr_t)G.xa + sh);
+        const GAS IRec* __restrict__ xb = (const GAS IRec*)((uintptr_t)G.xb + sh);
         // The row's entries in chunks of P: thread j loads entry j of the chunk, and the
         // row's threads pass them round with shuffles (every thread of the row runs the
         // same trip counts); then each thread loads its source's records for up to IU of
@@ -1653,7 +1656,8 @@ __global__ void __launch_bounds__(IT) k_interior(const IGroup* __restrict__ igs,
                         if (act) {
                             // one 16-byte load per record
                             typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-                            const u32x4 w = *reinterpret_cast<const GAS u32x4*>(xr + (int64_t)f[k] * P);
+                            const u32x4 w =
+                                *reinterpret_cast<const GAS u32x4*>(xr + (int64_t)f[k] * P);
                             r[k].d = w.x;
                             r[k].x = ((uint64_t)w.w << 32) | w.z;
                         }
