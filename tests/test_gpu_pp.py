@@ -374,3 +374,25 @@ def test_pp_split_interior_rows(bcpp, monkeypatch):
         assert_scores(a, want)
         assert_scores(b, want)
         assert_scores(a, b)
+
+
+def test_pp_split_interior_64_sources_per_group(bcpp, monkeypatch):
+    """64 sources per group (|S| = 16,384: rows of 64 threads, one per wave's lane): the
+    split interior sweep against plain Brandes on the same targets (itself pinned to the
+    oracle elsewhere; the oracle takes most of a minute here) and against the in-kernel
+    sweep, within 1e-9."""
+    # sparse blocks (mean degree about 2.5), so that many non-targets keep no target
+    # neighbour and stay interior
+    g = inputs.sbm(inputs.rng_for(inputs.SEED_BASE + 99, 4), inputs.equal_sizes(40000, 800), 0.05, 2000, None,
+                   "split40k_sparse")
+    S = inputs.random_targets(74, g.n, 16384)
+    G = bcpp.Graph(g)
+    sk = bcpp.partition_sk(G, g.part, g.k, S)
+    assert sk.stats()["table_nnz"] > 0
+    monkeypatch.setenv("BCPP_ISPLIT", "1")
+    a = bcpp.brandes_pp(G, sk)
+    monkeypatch.setenv("BCPP_ISPLIT", "0")
+    b = bcpp.brandes_pp(G, sk)
+    plain = bcpp.brandes_plain(G, S)
+    assert_scores(a, plain)
+    assert_scores(b, plain)
