@@ -272,6 +272,8 @@ struct ResidentLaunch {
     int64_t ig_blocks = 0;   // k_interior blocks of those
     int64_t ig_nblocks = 0;  // and of the rest
     int64_t ig_tblocks = 0;  // blocks of the transpose before them
+    // each grid's blocks per group when every group owns the same number, else 0
+    int64_t ig_wstride = 0, ig_nstride = 0, ig_tstride = 0;
     // profiler kind of the launches: BC_K_DIJKSTRA_SK when every group is forward-only
     int kind = BC_K_RESIDENT;
 };

@@ -1527,25 +1527,44 @@ __global__ void __launch_bounds__(T) k_resident(const RGroup* __restrict__ rgs,
 constexpr int IT = 256;  // threads of a k_interior block
 constexpr int IU = 4;    // entries a thread has in flight
 
-// The saved rows of GF_ISPLIT groups, source-major as the resident kernel writes them
-// (one source at a time, in full lines), node-major for k_interior: a block takes
-// IT / lanes consecutive nodes of one group, thread j of a node its j-th source; reads
-// run along nodes per source and writes along the block.
-__global__ void __launch_bounds__(IT) k_itranspose(const IGroup* __restrict__ igs, int32_t nig, int64_t nblk) {
-    const int64_t lb = blockIdx.x;
+// The group of logical block lb of an interior launch, and the block's index within it:
+// with a stride, every group owns `stride` consecutive blocks (those past its rows or
+// nodes find nothing to do); without, groups own their blocks from blk0 (or tblk0 for
+// the transpose) on, found by a binary search.
+__device__ __forceinline__ void block_group(const IGroup* __restrict__ igs, int32_t nig, int64_t lb,
+                                            int64_t stride, bool transpose, int32_t* g, int64_t* local) {
+    if (stride > 0) {
+        *g = (int32_t)(lb / stride);
+        *local = lb - (int64_t)*g * stride;
+        return;
+    }
     int32_t glo = 0, ghi = nig - 1;
     while (glo < ghi) {
         const int32_t mid = (glo + ghi + 1) >> 1;
-        if (igs[mid].tblk0 <= lb)
+        if ((transpose ? igs[mid].tblk0 : igs[mid].blk0) <= lb)
             glo = mid;
         else
             ghi = mid - 1;
     }
+    *g = glo;
+    *local = lb - (transpose ? igs[glo].tblk0 : igs[glo].blk0);
+}
+
+// The saved rows of GF_ISPLIT groups, source-major as the resident kernel writes them
+// (one source at a time, in full lines), node-major for k_interior: a block takes
+// IT / lanes consecutive nodes of one group, thread j of a node its j-th source; reads
+// run along nodes per source and writes along the block.
+__global__ void __launch_bounds__(IT) k_itranspose(const IGroup* __restrict__ igs, int32_t nig, int64_t nblk,
+                                                    int64_t stride) {
+    const int64_t lb = blockIdx.x;
+    int32_t glo;
+    int64_t local;
+    block_group(igs, nig, lb, stride, true, &glo, &local);
     const IGroup& G = igs[glo];
     const int P = G.lanes;
     const int t = threadIdx.x;
     const int j = t & (P - 1);
-    const int64_t v = (lb - G.tblk0) * (IT / P) + t / P;
+    const int64_t v = local * (IT / P) + t / P;
     if (v >= G.n || j >= G.nsrc) return;
     const int64_t i = (int64_t)j * G.n + v, o = v * P + j;
     const uint32_t d = gas(G.odist)[i];
@@ -1573,25 +1592,20 @@ __global__ void __launch_bounds__(IT) k_itranspose(const IGroup* __restrict__ ig
 // and then their saved values before it uses any, so that its loads overlap.
 template <bool SHARE>
 __global__ void __launch_bounds__(IT) k_interior(const IGroup* __restrict__ igs, int32_t nig, int64_t nblk,
-                                                  uint32_t* __restrict__ err) {
+                                                  int64_t stride, uint32_t* __restrict__ err) {
     // Blocks go to the 8 XCDs in turn by index; consecutive logical blocks (rows of one
     // group, reading the same saved rows) are kept on one XCD and so in one L2.
     const int64_t b = blockIdx.x;
     const int64_t per = nblk / 8, rem = nblk % 8, x = b % 8;
     const int64_t lb = (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + b / 8;
-    int32_t glo = 0, ghi = nig - 1;
-    while (glo < ghi) {
-        const int32_t mid = (glo + ghi + 1) >> 1;
-        if (igs[mid].blk0 <= lb)
-            glo = mid;
-        else
-            ghi = mid - 1;
-    }
+    int32_t glo;
+    int64_t local;
+    block_group(igs, nig, lb, stride, false, &glo, &local);
     const IGroup& G = igs[glo];
     const int P = G.lanes;
     const int t = threadIdx.x;
     const int j = t & (P - 1);
-    const int32_t row = (int32_t)((lb - G.blk0) * (IT / P) + t / P);
+    const int32_t row = (int32_t)(local * (IT / P) + t / P);
     const bool act = row < G.tn && j < G.nsrc;
     const GAS int64_t* __restrict__ trow = gas(G.trow);
     const GAS int32_t* __restrict__ tcol = gas(G.tcol);
@@ -2091,6 +2105,23 @@ int resident_upload(hipStream_t s, Arena& a, const GroupDesc* const* groups, siz
         }
         if (ig_blocks >= ((int64_t)1 << 31) || ig_nblocks >= ((int64_t)1 << 31) || ig_tblocks >= ((int64_t)1 << 31))
             return fail(BC_E_INVAL, "resident: too many interior rows");
+        // Each instance's grid: with a stride (every group owns as many blocks as the
+        // largest needs) when that at most doubles the blocks, so that a block finds its
+        // group by a division; else the blocks the groups need, found by a search.
+        auto shape = [&](int32_t g0, int32_t g1, bool transpose, int64_t need, int64_t* grid, int64_t* stride) {
+            int64_t mx = 0;
+            for (int32_t g = g0; g < g1; ++g) {
+                const IGroup& q = ig[g];
+                const int64_t units = transpose ? (int64_t)q.n : (int64_t)q.tn;
+                mx = std::max(mx, (units + IT / q.lanes - 1) / (IT / q.lanes));
+            }
+            const int64_t full = mx * (int64_t)(g1 - g0);
+            *stride = (g1 > g0 && full <= 2 * need && full < ((int64_t)1 << 31)) ? mx : 0;
+            *grid = *stride ? full : need;
+        };
+        shape(0, nwide, false, ig_blocks, &ig_blocks, &L->ig_wstride);
+        shape(nwide, (int32_t)ig.size(), false, ig_nblocks, &ig_nblocks, &L->ig_nstride);
+        shape(0, (int32_t)ig.size(), true, ig_tblocks, &ig_tblocks, &L->ig_tstride);
         IGroup* d_ig = a.take<IGroup>(ig.size());
         if (!d_ig) return fail(BC_E_NOMEM, "resident: workspace too small");
         BC_HIP(hipMemcpyAsync(d_ig, ig.data(), ig.size() * sizeof(IGroup), hipMemcpyHostToDevice, s));
@@ -2163,13 +2194,14 @@ static int launch_interior(hipStream_t s, const ResidentLaunch& L) {
     unsigned long long* prof =
         profiler().on && profiler().d_bytes ? profiler().d_bytes + BC_K_CENTRALITY : nullptr;
     KTimer kt(BC_K_CENTRALITY, s);
-    hipLaunchKernelGGL(k_itranspose, dim3((unsigned)L.ig_tblocks), dim3(IT), 0, s, L.d_ig, L.n_ig, L.ig_tblocks);
+    hipLaunchKernelGGL(k_itranspose, dim3((unsigned)L.ig_tblocks), dim3(IT), 0, s, L.d_ig, L.n_ig, L.ig_tblocks,
+                       L.ig_tstride);
     if (L.n_ig_wide > 0)
         hipLaunchKernelGGL(k_interior<true>, dim3((unsigned)L.ig_blocks), dim3(IT), 0, s, L.d_ig, L.n_ig_wide,
-                           L.ig_blocks, L.d_err);
+                           L.ig_blocks, L.ig_wstride, L.d_err);
     if (L.n_ig > L.n_ig_wide)
         hipLaunchKernelGGL(k_interior<false>, dim3((unsigned)L.ig_nblocks), dim3(IT), 0, s, L.d_ig + L.n_ig_wide,
-                           L.n_ig - L.n_ig_wide, L.ig_nblocks, L.d_err);
+                           L.n_ig - L.n_ig_wide, L.ig_nblocks, L.ig_nstride, L.d_err);
     if (prof) hipLaunchKernelGGL(k_interior_bytes, dim3((unsigned)((L.n_ig + 255) / 256)), dim3(256), 0, s, L.d_ig, L.n_ig, prof);
     BC_HIP(hipGetLastError());
     return BC_OK;
