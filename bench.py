@@ -1,8 +1,9 @@
 """Benchmark: exact-BC TEPS (|S| * m / s) of Brandes++ and plain Brandes on one MI355X.
 
 A step is one full Brandes++ pass over the workload: bc_partition_sk (P', frontiers,
-Dijkstra_SK, skeleton assembly) then bc_brandes_pp_dev (Brandes_SK with the fused
-Centrality pass, scores written to a device tensor). The graph is resident on the
+Dijkstra_SK, skeleton assembly) then bc_brandes_pp_dev (Brandes_SK, then Centrality:
+in the resident kernel, or for groups of 4 to 64 sources or many table rows in two
+kernels of its own after it; scores written to a device tensor). The graph is resident on the
 device before timing starts. Plain GPU Brandes on the same graph and targets is timed
 the same way and reported beside it, with the CPU oracle on a bounded sample.
 
