@@ -193,7 +193,11 @@ int bc_skeleton_sssp_counts(const bc_skeleton* sk, const int32_t* src, int32_t n
 
 /* Brandes++ (Sec. 5, Alg. 1): Brandes_SK on the skeleton (eqs. multiparents,
  * multibrandes) for the skeleton's targets, then Centrality (eq. localcentrality) for
- * every interior node, fused per batch of sources. Scores of all n nodes of g. */
+ * every interior node: per group of sources inside the traversal kernel, or, for
+ * groups of 4 to 64 sources or with at least 8192 table rows, in kernels of their own
+ * after it, from d, sigma and the coefficients the traversal saved per source (device
+ * workspace up to 128 MiB per such group). Scores of all n nodes of g; BC_E_NOMEM when
+ * the workspace cannot be allocated. */
 int bc_brandes_pp(const bc_graph* g, const bc_skeleton* sk, uint32_t flags,
                   double* bc_out);
 int bc_brandes_pp_dev(const bc_graph* g, const bc_skeleton* sk, uint32_t flags,
